@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Throughput of the DUWP particle pipeline on one MI355X.
+
+Workload: Mach-8 argon shock, 4000 cells over 200 upstream mean free paths,
+5e7 simulated particles (synthetic, seeded).  The timed path stores particles
+in FP32 (position relative to its cell) with FP64 cell moments, NS wave update
+and absorption fractions; the plain FP64 path is timed on the same workload
+beside it.  A step is one full DUWP time step of every stage, replayed as a
+captured HIP graph.  Metric: particle-steps per second (particles alive at the
+start of each step, summed over the timed steps, over the wall time).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/sec on Mach-8 argon shock (FP32+FP64 vs FP64) + % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per particle of each particle-streaming kernel, per
+# element size s of the particle arrays (4 in FP32 mode, 8 in FP64 mode):
+# absorb_resample reads and writes x,u,v,w once (with nothing absorbed); scatter
+# reads the staged x,u,v,w and writes them to their sorted place; stream_hist
+# reads x,u; moments reads u,v,w.
+BYTES_PER_PARTICLE = {
+    "absorb_resample": lambda s: 8 * s,
+    "scatter": lambda s: 8 * s,
+    "stream_hist": lambda s: 2 * s,
+    "moments": lambda s: 3 * s,
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_path(case, precision, steps, warmup, graph, seed=1):
+    from paper_2305_12071_amd import duwp
+    import torch
+
+    sim = duwp.Sim(case, seed=seed, precision=precision, use_graph=graph)
+    t = time.perf_counter()
+    sim.step(warmup)
+    log(f"  warmup {warmup} steps in {time.perf_counter() - t:.2f}s, N={sim.total_particles()}")
+    sim.particle_steps(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)          # returns after the device finished (error word read back)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ps = sim.particle_steps(reset=True)
+    return sim, ps, t1 - t0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cells", type=int, default=4000)
+    ap.add_argument("--particles", type=float, default=5e7)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--profile-steps", type=int, default=5)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the pipeline would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2305_12071_amd import duwp
+    from paper_2305_12071_amd import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    duwp.lib()
+    case = I.mach8_shock(args.cells, args.particles)
+    graph = not args.no_graph
+
+    log(f"mixed FP32+FP64 path: {case.name}")
+    sim, ps, dt = run_path(case, duwp.MIXED, args.steps, args.warmup, graph)
+    value = ps / dt
+    n_now = sim.total_particles()
+    log(f"  {args.steps} steps in {dt:.3f}s -> {value:.4e} particle-steps/s")
+
+    # per-kernel device time (HIP events on the library's stream, eager launches)
+    kms = sim.profile(args.profile_steps)
+    prof_ps = sim.particle_steps(reset=True) / args.profile_steps
+    dom = max((k for k in kms if k in BYTES_PER_PARTICLE), key=lambda k: kms[k])
+    alg_bytes = BYTES_PER_PARTICLE[dom](4) * prof_ps
+    achieved = alg_bytes / (kms[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_particle": BYTES_PER_PARTICLE[dom](4), "particles_per_launch": int(prof_ps),
+                "kernel_ms": round(kms[dom], 4)}
+    log("  kernels (ms):", json.dumps({k: round(v, 4) for k, v in kms.items()}))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        log(f"CPU oracle: {args.cpu_steps} steps from the GPU state after warm-up")
+        st = sim.get_state()
+        sim.close()
+        del sim
+        orc = O.Oracle(case, seed=1, case_id=0)
+        orc.set_state(st)
+        n0 = len(st["x"])
+        del st
+        t = time.perf_counter()
+        pst = 0
+        for _ in range(args.cpu_steps):
+            pst += orc.n
+            orc.step(1)
+        cdt = time.perf_counter() - t
+        cpu = {"value": pst / cdt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"{case.name}: {args.cpu_steps} FP64 oracle steps from the warmed-up state "
+                         f"({n0} particles), single thread, {cdt:.1f}s"}
+        log(f"  oracle {cpu['value']:.3e} particle-steps/s")
+        del orc
+    else:
+        sim.close()
+        del sim
+
+    fp64 = None
+    if not args.no_fp64:
+        log("plain FP64 path")
+        s64, ps64, dt64 = run_path(case, duwp.FP64, args.steps, args.warmup, graph)
+        fp64 = ps64 / dt64
+        log(f"  {args.steps} steps in {dt64:.3f}s -> {fp64:.4e} particle-steps/s")
+        s64.close()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": case.name, "cells": case.ncells, "particles": n_now,
+                   "particles_target": args.particles, "precision": "fp32 particles + fp64 cells",
+                   "graph": graph, "gas": "argon VHS omega=0.81", "mach": 8},
+        "fp64_value": fp64,
+        "mixed_over_fp64": (value / fp64) if fp64 else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

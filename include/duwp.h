@@ -1,0 +1,164 @@
+/*
+ * duwp.h -- C ABI of the MI355X (gfx950) DUWP particle pipeline.
+ *
+ * One call to duwp_step advances every case of a context by one time step of
+ * the direct unified wave-particle method (Cao, Liu, Yang, Zhong, arXiv
+ * 2305.12071, Sec. 3.4 "Algorithm of DUWP", Steps 1-4): particle moments
+ * (Eq. gkt_moment0), classification of particles for absorption into the
+ * wave part by the fraction P of Eq. p, resampling of 1-P of the wave part
+ * as Maxwellian particles (Eq. maxsample), DSMC no-time-counter collisions
+ * with the VHS model (Appendix A), free transport and boundaries (Step 3),
+ * a stable counting sort of particles into cells, and the finite-volume
+ * update of the wave part with a Navier-Stokes flux (Eq. r1, Sec. 3.3).
+ *
+ * Conventions
+ *  - Every call returns a duwp_status (0 = OK).  No exception crosses the ABI.
+ *  - The context owns all device memory; it allocates with hipMalloc at
+ *    duwp_init and frees in duwp_destroy.  Host buffers passed to accessors
+ *    are owned by the caller and must hold the documented number of elements.
+ *  - Work is queued on the stream given in duwp_opts (NULL: the null stream).
+ *    duwp_step returns after the queued steps finish and the device error
+ *    word has been read; the error is then reported as a status.
+ *  - Cells of all cases are numbered case by case; particle arrays are
+ *    structure-of-arrays sorted by cell, with cell offsets.
+ *  - Not thread-safe: one host thread per context.
+ */
+#ifndef DUWP_H
+#define DUWP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DUWP_OK = 0,
+    DUWP_EINVAL = -1,     /* bad argument or case description */
+    DUWP_ENOMEM = -2,     /* device allocation failed */
+    DUWP_EDEVICE = -3,    /* a HIP call failed */
+    DUWP_ECAPACITY = -4,  /* particle, staging or injection capacity exceeded during a step */
+    DUWP_ESTATE = -5,     /* non-finite cell state detected */
+    DUWP_ERANGE = -6      /* a particle moved more than DUWP_SORT_WINDOW cells in one step */
+} duwp_status;
+
+/* Largest number of cells a particle may cross in one step (dt too large otherwise). */
+#define DUWP_SORT_WINDOW 16
+
+enum { DUWP_BC_RESERVOIR = 0, DUWP_BC_SPECULAR = 1 };
+enum { DUWP_P_RATIONAL = 0,   /* P = max(0, 1 - tau/dt), Eq. p */
+       DUWP_P_EXP = 1 };      /* P = 1 - exp(-dt/tau), the QMC probability of Sec. 3.2 */
+enum { DUWP_EPS1 = 0, DUWP_EPS12 = 1, DUWP_EPS0 = 2, DUWP_EPS_FULL = 3 }; /* Eq. vp1, eps_12, eps_0, Eq. vp */
+enum { DUWP_FP64 = 0,         /* particles and cells in FP64 */
+       DUWP_MIXED = 1 };      /* particles in FP32 (position relative to its cell), cells in FP64 */
+
+/* One independent 1D case.  Dimensional (SI) or nondimensional units. */
+typedef struct {
+    int32_t kind;                 /* informational: 0 shock, 1 Sod, 2 box */
+    int32_t ncells;               /* > 0 */
+    double x_lo, x_hi, x_split;   /* domain and position of the initial step */
+    double rho_L, u_L, T_L;       /* initial state left of x_split; left reservoir state */
+    double rho_R, u_R, T_R;       /* initial state right of x_split; right reservoir state */
+    double R, omega, T_ref;       /* gas constant, viscosity index (mu ~ T^omega), reference T */
+    double m_mol, d_ref;          /* VHS molecule mass and reference diameter (dimensional gas) */
+    double lambda_ref, rho_ref;   /* or: reference mean free path at density rho_ref (if > 0) */
+    double m_particle;            /* mass per simulated particle per unit area (> 0) */
+    double dt;                    /* time step (> 0) */
+    int32_t bc_lo, bc_hi;         /* DUWP_BC_* */
+    int32_t classify_law;         /* DUWP_P_* */
+    int32_t eps_law;              /* DUWP_EPS_* */
+    int32_t dsmc_full_dt;         /* 0: collide over (1-P) dt (default); 1: over dt */
+    int64_t capacity;             /* particle capacity of this case; 0 = derived from the mass */
+} duwp_case;
+
+typedef struct {
+    uint64_t seed;                /* Philox key: (low 32 bits, high 32 bits + case index) */
+    int32_t precision;            /* DUWP_FP64 or DUWP_MIXED */
+    int32_t use_graph;            /* 1: replay each step as a captured HIP graph */
+    void *stream;                 /* hipStream_t, or NULL */
+    double headroom;              /* capacity = headroom * mass / m_particle when capacity = 0 (<= 0: 1.5) */
+    int32_t block_cells;          /* threads per block of the per-cell kernels (0: 256) */
+    int32_t reserved;
+} duwp_opts;
+
+typedef struct duwp_ctx duwp_ctx;
+
+/* Host copy of one case's state (FP64 whatever the precision; x absolute).
+ * x,u,v,w: [n_particles]; off: [ncells+1]; psi_w: [ncells*5] = (rho, rho U, rho V,
+ * rho W, rho E) of the wave part; cr_max: [ncells]. */
+typedef struct {
+    int64_t n_particles;
+    int32_t ncells;
+    uint32_t step;
+    double *x, *u, *v, *w;
+    int64_t *off;
+    double *psi_w;
+    double *cr_max;
+} duwp_state;
+
+/* What duwp_moments returns, each [ncells*5] doubles */
+enum {
+    DUWP_M_PRIM = 0,      /* (rho, U, V, W, T) of Psi_t = Psi_w + Psi_p, current state */
+    DUWP_M_PSI_T = 1,     /* conserved total */
+    DUWP_M_PSI_W = 2,     /* conserved wave part */
+    DUWP_M_PSI_P = 3,     /* conserved particle part */
+    DUWP_M_AVG_PRIM = 4,  /* (rho, U, V, W, T) of the time-averaged Psi_t */
+    DUWP_M_AVG_SUM = 5    /* running sum of Psi_t (divide by duwp_avg_count) */
+};
+
+/* Create a context holding ncases independent cases; all cases step together.
+ * Fails with DUWP_EINVAL on an invalid case (ncells <= 0, x_hi <= x_lo, m_particle
+ * or dt <= 0, no gas constants), DUWP_ENOMEM when buffers do not fit.  The initial
+ * state puts all mass in the wave part (no particles), the first step samples them. */
+duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, const duwp_opts *opts);
+
+/* Advance all cases by nsteps >= 0 steps (Sec. 3.4, Steps 2-3, then Eq. r1).
+ * Returns the first device error seen (DUWP_ECAPACITY, DUWP_ERANGE, DUWP_ESTATE);
+ * after an error the state is undefined but the context may be destroyed or reset
+ * with duwp_set_state. */
+duwp_status duwp_step(duwp_ctx *ctx, int32_t nsteps);
+
+/* Cell moments of one case into out[len], len >= ncells*5 (see DUWP_M_*).
+ * out is host memory, or device memory when out_on_device = 1. */
+duwp_status duwp_moments(duwp_ctx *ctx, int32_t case_id, int32_t what, double *out, int64_t len,
+                         int32_t out_on_device);
+int64_t duwp_avg_count(duwp_ctx *ctx);
+duwp_status duwp_reset_average(duwp_ctx *ctx);
+
+/* Particle-steps (particles alive at the start of each step, summed over steps and
+ * cases) since duwp_init or the last reset; reset = 1 clears the counter after reading. */
+duwp_status duwp_particle_steps(duwp_ctx *ctx, int64_t *psteps, int32_t reset);
+
+/* Particle count, step index and cell count of one case. */
+duwp_status duwp_counts(duwp_ctx *ctx, int32_t case_id, int64_t *n_particles, int32_t *ncells,
+                        uint32_t *step);
+
+/* Per-cell integers of the last step of one case (each [ncells]): particles absorbed,
+ * particles resampled, NTC candidates, accepted collisions; and per case the
+ * injected entrants per side [2] and particles leaving through reservoirs. */
+duwp_status duwp_diag(duwp_ctx *ctx, int32_t case_id, int32_t *n_abs, int32_t *n_new,
+                      int32_t *n_cand, int32_t *n_coll, int64_t *n_inj, int64_t *n_out);
+
+/* Copy one case's state to host buffers sized from duwp_counts (checkpoint, parity). */
+duwp_status duwp_get_state(duwp_ctx *ctx, int32_t case_id, duwp_state *st);
+
+/* Replace one case's state (and the context's step index) from host buffers.  The
+ * particle moments are recomputed; the case keeps its place among the others.
+ * DUWP_EINVAL if offsets are not monotone, DUWP_ECAPACITY if it does not fit. */
+duwp_status duwp_set_state(duwp_ctx *ctx, int32_t case_id, const duwp_state *st);
+
+/* Average device duration in ms of each kernel of the step over nsteps eager steps
+ * (HIP events on the context stream).  names/ms hold up to cap entries; returns the
+ * number of kernels in *count. */
+duwp_status duwp_profile(duwp_ctx *ctx, int32_t nsteps, const char **names, double *ms,
+                         int32_t cap, int32_t *count);
+
+duwp_status duwp_sync(duwp_ctx *ctx);
+void duwp_destroy(duwp_ctx *ctx);
+const char *duwp_strerror(duwp_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,615 @@
+// C ABI of the DUWP library: context set-up, stepping, state access.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "duwp.h"
+#include "duwp_ctx.hpp"
+
+using duwp::DCase;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+#define HIP_OK(expr)                                  \
+    do {                                              \
+        if ((expr) != hipSuccess) return DUWP_EDEVICE; \
+    } while (0)
+
+bool case_valid(const duwp_case &c)
+{
+    if (c.ncells <= 0 || !(c.x_hi > c.x_lo) || !(c.m_particle > 0.0) || !(c.dt > 0.0)) return false;
+    if (!(c.R > 0.0) || !(c.T_ref > 0.0) || !(c.omega > 0.0)) return false;
+    if (!(c.x_split >= c.x_lo && c.x_split <= c.x_hi)) return false;
+    if (!(c.rho_L > 0.0 && c.rho_R > 0.0 && c.T_L > 0.0 && c.T_R > 0.0)) return false;
+    if (!(c.lambda_ref > 0.0 && c.rho_ref > 0.0) && !(c.m_mol > 0.0 && c.d_ref > 0.0)) return false;
+    if (c.bc_lo < 0 || c.bc_lo > 1 || c.bc_hi < 0 || c.bc_hi > 1) return false;
+    if (c.classify_law < 0 || c.classify_law > 1 || c.eps_law < 0 || c.eps_law > 3) return false;
+    return true;
+}
+
+// Gas constants of a case.  beta: mean-free-path factor (Sec. 4.1, Eq. lambda,
+// alpha = 1).  Lam = lambda_ref rho_ref = m/(sqrt(2) pi d_ref^2) (Appendix A).
+// Matching the viscosity and diameter forms of the mean free path at T_ref gives
+// mu_ref = beta Lam sqrt(2 pi R T_ref).  sigma_ref n = rho/(sqrt(2) Lam).
+// VHS reference relative speed c_ref = sqrt(4 R T_ref)/Gamma(5/2-omega)^(1/(2 ups)).
+DCase derive(const duwp_case &c, int cell_base, uint64_t seed, int case_id)
+{
+    DCase d{};
+    d.ncells = c.ncells;
+    d.cell_base = cell_base;
+    d.bc_lo = c.bc_lo;
+    d.bc_hi = c.bc_hi;
+    d.law = c.classify_law;
+    d.eps_law = c.eps_law;
+    d.full_dt = c.dsmc_full_dt;
+    d.key0 = (uint32_t)seed;
+    d.key1 = (uint32_t)(seed >> 32) + (uint32_t)case_id;
+    d.x_lo = c.x_lo;
+    d.x_hi = c.x_hi;
+    d.dx = (c.x_hi - c.x_lo) / (double)c.ncells;
+    d.dt = c.dt;
+    d.R = c.R;
+    d.omega = c.omega;
+    d.T_ref = c.T_ref;
+    const double beta = 30.0 / (4.0 * (5.0 - 2.0 * c.omega) * (7.0 - 2.0 * c.omega));
+    const double lam = (c.lambda_ref > 0.0) ? c.lambda_ref * c.rho_ref
+                                            : c.m_mol / (std::sqrt(2.0) * kPi * c.d_ref * c.d_ref);
+    d.mu_ref = beta * lam * std::sqrt(2.0 * kPi * c.R * c.T_ref);
+    d.coll_k = 1.0 / (std::sqrt(2.0) * lam);
+    d.ups = c.omega - 0.5;
+    d.c_ref = (d.ups != 0.0) ? std::sqrt(4.0 * c.R * c.T_ref) / std::pow(std::tgamma(2.5 - c.omega), 1.0 / (2.0 * d.ups))
+                             : 1.0;
+    d.m_p = c.m_particle;
+    d.fac = c.m_particle / d.dx;
+    d.rho_L = c.rho_L; d.u_L = c.u_L; d.T_L = c.T_L;
+    d.rho_R = c.rho_R; d.u_R = c.u_R; d.T_R = c.T_R;
+    d.dtdx_f = (float)(c.dt / d.dx);
+    return d;
+}
+
+// Upper bound on the entrants of one step: floor((1-P) rho Lg / m_p + u) <= rho Lg / m_p + 1.
+int64_t inject_bound(const duwp_case &c)
+{
+    int64_t n = 0;
+    for (int side = 0; side < 2; ++side) {
+        if ((side == 0 ? c.bc_lo : c.bc_hi) != DUWP_BC_RESERVOIR) continue;
+        double rho = side == 0 ? c.rho_L : c.rho_R, U = side == 0 ? c.u_L : c.u_R, T = side == 0 ? c.T_L : c.T_R;
+        double Lg = c.dt * (std::fabs(U) + 8.0 * std::sqrt(c.R * T));
+        n += (int64_t)std::ceil(rho * Lg / c.m_particle) + 2;
+    }
+    return n;
+}
+
+template <typename P>
+duwp_status dalloc(duwp_ctx *ctx, P **p, size_t bytes)
+{
+    void *q = nullptr;
+    if (hipMalloc(&q, bytes ? bytes : 64) != hipSuccess) return DUWP_ENOMEM;
+    ctx->allocs.push_back(q);
+    *p = (P *)q;
+    return DUWP_OK;
+}
+
+#define TRY(expr)                                \
+    do {                                         \
+        duwp_status s_ = (expr);                 \
+        if (s_ != DUWP_OK) return s_;            \
+    } while (0)
+
+duwp_status alloc_all(duwp_ctx *ctx)
+{
+    const int G = ctx->G;
+    const size_t es = ctx->precision == DUWP_MIXED ? sizeof(float) : sizeof(double);
+    for (int p = 0; p < 2; ++p)
+        for (int a = 0; a < 4; ++a) TRY(dalloc(ctx, &ctx->A[p][a], es * (size_t)ctx->cap));
+    for (int a = 0; a < 4; ++a) TRY(dalloc(ctx, &ctx->S[a], es * (size_t)ctx->cap));
+    for (int a = 0; a < 4; ++a) TRY(dalloc(ctx, &ctx->J[a], es * (size_t)ctx->inj_total));
+    TRY(dalloc(ctx, &ctx->j_dest, 4 * (size_t)ctx->inj_total));
+    TRY(dalloc(ctx, &ctx->j_rank, 4 * (size_t)ctx->inj_total));
+    TRY(dalloc(ctx, &ctx->j_count, 4 * (size_t)ctx->ncases));
+    for (int p = 0; p < 2; ++p) TRY(dalloc(ctx, &ctx->off[p], 8 * (size_t)(G + 1)));
+    TRY(dalloc(ctx, &ctx->ibase, 8 * (size_t)(G + 1)));
+    duwp::Cells &c = ctx->cl;
+    TRY(dalloc(ctx, &c.psi_w, 8 * 5 * (size_t)G));
+    TRY(dalloc(ctx, &c.psi_p, 8 * 5 * (size_t)G));
+    TRY(dalloc(ctx, &c.wt, 8 * 5 * (size_t)G));
+    TRY(dalloc(ctx, &c.pc, 8 * (size_t)G));
+    TRY(dalloc(ctx, &c.okc, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.cr_max, 8 * (size_t)G));
+    TRY(dalloc(ctx, &c.n_surv, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.n_new, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.n_int, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.d_abs, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.d_new, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.d_cand, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.d_coll, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.hist, 4 * (size_t)G * duwp::NBIN));
+    TRY(dalloc(ctx, &c.cnt_new, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.inj_cnt, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.inj_start, 8 * (size_t)G));
+    TRY(dalloc(ctx, &c.cell_case, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.avg, 8 * 5 * (size_t)G));
+    ctx->ntiles = (G + 2047) / 2048;
+    TRY(dalloc(ctx, &ctx->scan_part, 8 * (size_t)std::max(ctx->ntiles, 1)));
+    TRY(dalloc(ctx, &ctx->d_step, 4));
+    TRY(dalloc(ctx, &ctx->d_err, 4));
+    TRY(dalloc(ctx, &ctx->d_nout, 8 * (size_t)ctx->ncases));
+    TRY(dalloc(ctx, &ctx->d_ninj, 16 * (size_t)ctx->ncases));
+    TRY(dalloc(ctx, &ctx->d_total, 16));
+    TRY(dalloc(ctx, &ctx->d_psteps, 8));
+    TRY(dalloc(ctx, &ctx->d_cases, sizeof(DCase) * (size_t)ctx->ncases));
+    return DUWP_OK;
+}
+
+duwp_status upload_initial(duwp_ctx *ctx)
+{
+    const int G = ctx->G;
+    std::vector<double> psi(5 * (size_t)G), cr(G);
+    std::vector<int32_t> cc(G);
+    for (int k = 0; k < ctx->ncases; ++k) {
+        const duwp_case &c = ctx->cases[k];
+        const DCase &d = ctx->hcases[k];
+        for (int i = 0; i < c.ncells; ++i) {
+            const int g = d.cell_base + i;
+            // all mass starts in the wave part at the cell-centre value of the step profile
+            const double xc = c.x_lo + ((double)i + 0.5) * d.dx;
+            const bool left = xc < c.x_split;
+            const double rho = left ? c.rho_L : c.rho_R, U = left ? c.u_L : c.u_R, T = left ? c.T_L : c.T_R;
+            psi[5 * g + 0] = rho;
+            psi[5 * g + 1] = rho * U;
+            psi[5 * g + 2] = 0.0;
+            psi[5 * g + 3] = 0.0;
+            psi[5 * g + 4] = rho * (0.5 * U * U + 1.5 * c.R * T);
+            cr[g] = 6.0 * std::sqrt(c.R * T);
+            cc[g] = k;
+        }
+    }
+    hipStream_t s = ctx->stream;
+    HIP_OK(hipMemcpyAsync(ctx->cl.psi_w, psi.data(), 8 * psi.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(ctx->cl.cr_max, cr.data(), 8 * cr.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(ctx->cl.cell_case, cc.data(), 4 * cc.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(ctx->d_cases, ctx->hcases.data(), sizeof(DCase) * ctx->hcases.size(),
+                          hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemsetAsync(ctx->cl.psi_p, 0, 8 * 5 * (size_t)G, s));
+    HIP_OK(hipMemsetAsync(ctx->cl.avg, 0, 8 * 5 * (size_t)G, s));
+    for (int p = 0; p < 2; ++p) HIP_OK(hipMemsetAsync(ctx->off[p], 0, 8 * (size_t)(G + 1), s));
+    HIP_OK(hipMemsetAsync(ctx->d_step, 0, 4, s));
+    HIP_OK(hipMemsetAsync(ctx->d_err, 0, 4, s));
+    HIP_OK(hipMemsetAsync(ctx->d_psteps, 0, 8, s));
+    HIP_OK(hipMemsetAsync(ctx->d_nout, 0, 8 * (size_t)ctx->ncases, s));
+    HIP_OK(hipMemsetAsync(ctx->d_ninj, 0, 16 * (size_t)ctx->ncases, s));
+    HIP_OK(hipMemsetAsync(ctx->j_count, 0, 4 * (size_t)ctx->ncases, s));
+    const duwp::Cells &c = ctx->cl;
+    for (int32_t *p : {c.d_abs, c.d_new, c.d_cand, c.d_coll}) HIP_OK(hipMemsetAsync(p, 0, 4 * (size_t)G, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return DUWP_OK;
+}
+
+duwp_status read_error(duwp_ctx *ctx)
+{
+    int32_t e = 0;
+    HIP_OK(hipMemcpyAsync(&e, ctx->d_err, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    if (e & duwp::ERR_CAPACITY) return DUWP_ECAPACITY;
+    if (e & duwp::ERR_RANGE) return DUWP_ERANGE;
+    if (e & duwp::ERR_STATE) return DUWP_ESTATE;
+    return DUWP_OK;
+}
+
+duwp_status build_graphs(duwp_ctx *ctx)
+{
+    for (int p = 0; p < 2; ++p) {
+        if (ctx->graph[p]) continue;
+        const uint32_t saved = ctx->step;
+        ctx->step = (uint32_t)p;   // only the parity matters for the captured pointers
+        hipGraph_t g = nullptr;
+        (void)hipGetLastError();
+        if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            ctx->step = saved;
+            return DUWP_EDEVICE;
+        }
+        duwp::enqueue_step(ctx);
+        hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+        ctx->step = saved;
+        if (e != hipSuccess) return DUWP_EDEVICE;
+        e = hipGraphInstantiate(&ctx->graph[p], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return DUWP_EDEVICE;
+    }
+    ctx->graph_ready = true;
+    return DUWP_OK;
+}
+
+// host copy of the canonical offsets of the current parity
+duwp_status host_offsets(duwp_ctx *ctx, std::vector<int64_t> &off)
+{
+    off.resize((size_t)ctx->G + 1);
+    HIP_OK(hipMemcpyAsync(off.data(), ctx->off[ctx->step & 1], 8 * off.size(), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return DUWP_OK;
+}
+
+template <typename T>
+duwp_status download_particles(duwp_ctx *ctx, int64_t b, int64_t n, std::vector<T> (&out)[4])
+{
+    const int p = ctx->step & 1;
+    for (int a = 0; a < 4; ++a) {
+        out[a].resize((size_t)n);
+        if (n) HIP_OK(hipMemcpyAsync(out[a].data(), (T *)ctx->A[p][a] + b, sizeof(T) * n, hipMemcpyDeviceToHost,
+                                     ctx->stream));
+    }
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return DUWP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *duwp_strerror(duwp_status s)
+{
+    switch (s) {
+    case DUWP_OK: return "ok";
+    case DUWP_EINVAL: return "invalid argument or case description";
+    case DUWP_ENOMEM: return "device allocation failed";
+    case DUWP_EDEVICE: return "HIP call failed";
+    case DUWP_ECAPACITY: return "particle, staging or injection capacity exceeded";
+    case DUWP_ESTATE: return "non-finite cell state";
+    case DUWP_ERANGE: return "a particle crossed more cells in one step than the sort window allows";
+    }
+    return "unknown status";
+}
+
+void duwp_destroy(duwp_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto &g : ctx->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    for (hipEvent_t e : ctx->timer.ev) (void)hipEventDestroy(e);
+    for (void *p : ctx->allocs) (void)hipFree(p);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, const duwp_opts *opts)
+{
+    if (!out || !cases || ncases <= 0 || !opts) return DUWP_EINVAL;
+    *out = nullptr;
+    if (opts->precision != DUWP_FP64 && opts->precision != DUWP_MIXED) return DUWP_EINVAL;
+    duwp_ctx *ctx = new (std::nothrow) duwp_ctx();
+    if (!ctx) return DUWP_ENOMEM;
+    ctx->ncases = ncases;
+    ctx->precision = opts->precision;
+    ctx->use_graph = opts->use_graph;
+    ctx->stream = (hipStream_t)opts->stream;
+    if (!ctx->stream) {
+        // the null stream cannot be captured into a graph: use a private stream
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return DUWP_EDEVICE;
+        }
+        ctx->own_stream = true;
+    }
+    ctx->seed = opts->seed;
+    ctx->block_cells = opts->block_cells > 0 ? opts->block_cells : 256;
+    if (ctx->block_cells % 64 || ctx->block_cells > 1024) { delete ctx; return DUWP_EINVAL; }
+    const double head = opts->headroom > 0.0 ? opts->headroom : 1.5;
+    int64_t G = 0, cap = 0, inj = 0;
+    for (int k = 0; k < ncases; ++k) {
+        const duwp_case &c = cases[k];
+        if (!case_valid(c)) { delete ctx; return DUWP_EINVAL; }
+        ctx->cases.push_back(c);
+        ctx->hcases.push_back(derive(c, (int)G, opts->seed, k));
+        G += c.ncells;
+        int64_t cc = c.capacity;
+        if (cc <= 0) {
+            const double mass = c.rho_L * (c.x_split - c.x_lo) + c.rho_R * (c.x_hi - c.x_split);
+            cc = (int64_t)std::ceil(head * mass / c.m_particle) + 4096;
+        }
+        cap += cc;
+        const int64_t ib = inject_bound(c);
+        ctx->hcases.back().inj_base = inj;
+        ctx->hcases.back().inj_cap = ib;
+        inj += ib;
+    }
+    if (G > (int64_t)1 << 30 || cap > ((int64_t)1 << 40)) { delete ctx; return DUWP_EINVAL; }
+    ctx->G = (int)G;
+    ctx->cap = cap;
+    ctx->inj_total = std::max<int64_t>(inj, 1);
+    duwp_status s = alloc_all(ctx);
+    if (s == DUWP_OK) s = upload_initial(ctx);
+    if (s != DUWP_OK) { duwp_destroy(ctx); return s; }
+    *out = ctx;
+    return DUWP_OK;
+}
+
+duwp_status duwp_step(duwp_ctx *ctx, int32_t nsteps)
+{
+    if (!ctx || nsteps < 0) return DUWP_EINVAL;
+    if (ctx->use_graph && !ctx->graph_ready) {
+        duwp_status s = build_graphs(ctx);
+        if (s != DUWP_OK) return s;
+    }
+    (void)hipGetLastError();   // drop errors left by unrelated earlier calls
+    for (int32_t i = 0; i < nsteps; ++i) {
+        if (ctx->use_graph) {
+            if (hipGraphLaunch(ctx->graph[ctx->step & 1], ctx->stream) != hipSuccess) return DUWP_EDEVICE;
+        } else {
+            duwp::enqueue_step(ctx);
+            if (hipGetLastError() != hipSuccess) return DUWP_EDEVICE;
+        }
+        ctx->step += 1;
+        ctx->avg_count += 1;
+    }
+    return read_error(ctx);
+}
+
+duwp_status duwp_sync(duwp_ctx *ctx)
+{
+    if (!ctx) return DUWP_EINVAL;
+    return read_error(ctx);
+}
+
+duwp_status duwp_counts(duwp_ctx *ctx, int32_t case_id, int64_t *n_particles, int32_t *ncells, uint32_t *step)
+{
+    if (!ctx || case_id < 0 || case_id >= ctx->ncases) return DUWP_EINVAL;
+    const DCase &d = ctx->hcases[case_id];
+    if (n_particles) {
+        int64_t v[2];
+        HIP_OK(hipMemcpyAsync(&v[0], ctx->off[ctx->step & 1] + d.cell_base, 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipMemcpyAsync(&v[1], ctx->off[ctx->step & 1] + d.cell_base + d.ncells, 8, hipMemcpyDeviceToHost,
+                              ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        *n_particles = v[1] - v[0];
+    }
+    if (ncells) *ncells = d.ncells;
+    if (step) *step = ctx->step;
+    return DUWP_OK;
+}
+
+duwp_status duwp_moments(duwp_ctx *ctx, int32_t case_id, int32_t what, double *out, int64_t len,
+                         int32_t out_on_device)
+{
+    if (!ctx || !out || case_id < 0 || case_id >= ctx->ncases || what < 0 || what > 5) return DUWP_EINVAL;
+    const DCase &d = ctx->hcases[case_id];
+    const int C = d.ncells;
+    if (len < 5 * (int64_t)C) return DUWP_EINVAL;
+    std::vector<double> w(5 * (size_t)C), p(5 * (size_t)C), a(5 * (size_t)C);
+    const size_t o = 5 * (size_t)d.cell_base, nb = 8 * 5 * (size_t)C;
+    HIP_OK(hipMemcpyAsync(w.data(), ctx->cl.psi_w + o, nb, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipMemcpyAsync(p.data(), ctx->cl.psi_p + o, nb, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipMemcpyAsync(a.data(), ctx->cl.avg + o, nb, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    std::vector<double> r(5 * (size_t)C);
+    const double inv = ctx->avg_count > 0 ? 1.0 / (double)ctx->avg_count : 0.0;
+    for (int i = 0; i < C; ++i) {
+        double t[5];
+        for (int k = 0; k < 5; ++k) {
+            switch (what) {
+            case DUWP_M_PSI_W: t[k] = w[5 * i + k]; break;
+            case DUWP_M_PSI_P: t[k] = p[5 * i + k]; break;
+            case DUWP_M_AVG_SUM: t[k] = a[5 * i + k]; break;
+            case DUWP_M_AVG_PRIM: t[k] = a[5 * i + k] * inv; break;
+            default: t[k] = w[5 * i + k] + p[5 * i + k]; break;
+            }
+        }
+        if (what == DUWP_M_PRIM || what == DUWP_M_AVG_PRIM) {
+            const double rho = t[0];
+            double U = 0, V = 0, W = 0, T = 0;
+            if (rho > 0.0) {
+                U = t[1] / rho; V = t[2] / rho; W = t[3] / rho;
+                T = (2.0 / (3.0 * d.R)) * (t[4] / rho - 0.5 * (U * U + V * V + W * W));
+            }
+            t[0] = rho; t[1] = U; t[2] = V; t[3] = W; t[4] = T;
+        }
+        for (int k = 0; k < 5; ++k) r[5 * i + k] = t[k];
+    }
+    if (out_on_device) {
+        HIP_OK(hipMemcpyAsync(out, r.data(), 8 * r.size(), hipMemcpyHostToDevice, ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+    } else {
+        std::memcpy(out, r.data(), 8 * r.size());
+    }
+    return DUWP_OK;
+}
+
+int64_t duwp_avg_count(duwp_ctx *ctx) { return ctx ? ctx->avg_count : 0; }
+
+duwp_status duwp_particle_steps(duwp_ctx *ctx, int64_t *psteps, int32_t reset)
+{
+    if (!ctx || !psteps) return DUWP_EINVAL;
+    HIP_OK(hipMemcpyAsync(psteps, ctx->d_psteps, 8, hipMemcpyDeviceToHost, ctx->stream));
+    if (reset) HIP_OK(hipMemsetAsync(ctx->d_psteps, 0, 8, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return DUWP_OK;
+}
+
+duwp_status duwp_reset_average(duwp_ctx *ctx)
+{
+    if (!ctx) return DUWP_EINVAL;
+    HIP_OK(hipMemsetAsync(ctx->cl.avg, 0, 8 * 5 * (size_t)ctx->G, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    ctx->avg_count = 0;
+    return DUWP_OK;
+}
+
+duwp_status duwp_diag(duwp_ctx *ctx, int32_t case_id, int32_t *n_abs, int32_t *n_new, int32_t *n_cand,
+                      int32_t *n_coll, int64_t *n_inj, int64_t *n_out)
+{
+    if (!ctx || case_id < 0 || case_id >= ctx->ncases) return DUWP_EINVAL;
+    const DCase &d = ctx->hcases[case_id];
+    const size_t nb = 4 * (size_t)d.ncells;
+    const duwp::Cells &c = ctx->cl;
+    hipStream_t s = ctx->stream;
+    if (n_abs) HIP_OK(hipMemcpyAsync(n_abs, c.d_abs + d.cell_base, nb, hipMemcpyDeviceToHost, s));
+    if (n_new) HIP_OK(hipMemcpyAsync(n_new, c.d_new + d.cell_base, nb, hipMemcpyDeviceToHost, s));
+    if (n_cand) HIP_OK(hipMemcpyAsync(n_cand, c.d_cand + d.cell_base, nb, hipMemcpyDeviceToHost, s));
+    if (n_coll) HIP_OK(hipMemcpyAsync(n_coll, c.d_coll + d.cell_base, nb, hipMemcpyDeviceToHost, s));
+    if (n_inj) HIP_OK(hipMemcpyAsync(n_inj, ctx->d_ninj + 2 * case_id, 16, hipMemcpyDeviceToHost, s));
+    if (n_out) HIP_OK(hipMemcpyAsync(n_out, ctx->d_nout + case_id, 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return DUWP_OK;
+}
+
+duwp_status duwp_get_state(duwp_ctx *ctx, int32_t case_id, duwp_state *st)
+{
+    if (!ctx || !st || case_id < 0 || case_id >= ctx->ncases) return DUWP_EINVAL;
+    const DCase &d = ctx->hcases[case_id];
+    std::vector<int64_t> off;
+    TRY(host_offsets(ctx, off));
+    const int64_t b = off[d.cell_base], n = off[d.cell_base + d.ncells] - b;
+    if (st->ncells != d.ncells || st->n_particles < n) return DUWP_EINVAL;
+    st->n_particles = n;
+    st->step = ctx->step;
+    if (st->off)
+        for (int i = 0; i <= d.ncells; ++i) st->off[i] = off[d.cell_base + i] - b;
+    if (ctx->precision == DUWP_MIXED) {
+        std::vector<float> h[4];
+        TRY(download_particles<float>(ctx, b, n, h));
+        for (int i = 0; i < d.ncells; ++i)
+            for (int64_t q = off[d.cell_base + i] - b; q < off[d.cell_base + i + 1] - b; ++q) {
+                if (st->x) st->x[q] = d.x_lo + ((double)i + (double)h[0][q]) * d.dx;
+                if (st->u) st->u[q] = h[1][q];
+                if (st->v) st->v[q] = h[2][q];
+                if (st->w) st->w[q] = h[3][q];
+            }
+    } else {
+        std::vector<double> h[4];
+        TRY(download_particles<double>(ctx, b, n, h));
+        double *dst[4] = {st->x, st->u, st->v, st->w};
+        for (int a = 0; a < 4; ++a)
+            if (dst[a]) std::memcpy(dst[a], h[a].data(), 8 * (size_t)n);
+    }
+    hipStream_t s = ctx->stream;
+    if (st->psi_w)
+        HIP_OK(hipMemcpyAsync(st->psi_w, ctx->cl.psi_w + 5 * (size_t)d.cell_base, 8 * 5 * (size_t)d.ncells,
+                              hipMemcpyDeviceToHost, s));
+    if (st->cr_max)
+        HIP_OK(hipMemcpyAsync(st->cr_max, ctx->cl.cr_max + d.cell_base, 8 * (size_t)d.ncells, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return DUWP_OK;
+}
+
+duwp_status duwp_set_state(duwp_ctx *ctx, int32_t case_id, const duwp_state *st)
+{
+    if (!ctx || !st || case_id < 0 || case_id >= ctx->ncases) return DUWP_EINVAL;
+    const DCase &d = ctx->hcases[case_id];
+    if (st->ncells != d.ncells || !st->off || !st->psi_w || !st->cr_max || st->n_particles < 0) return DUWP_EINVAL;
+    if (st->n_particles > 0 && (!st->x || !st->u || !st->v || !st->w)) return DUWP_EINVAL;
+    if (st->off[0] != 0 || st->off[d.ncells] != st->n_particles) return DUWP_EINVAL;
+    for (int i = 0; i < d.ncells; ++i)
+        if (st->off[i + 1] < st->off[i]) return DUWP_EINVAL;
+    std::vector<int64_t> off;
+    TRY(host_offsets(ctx, off));
+    const int G = ctx->G, p = ctx->step & 1;
+    const int64_t b = off[d.cell_base], nold = off[d.cell_base + d.ncells] - b;
+    const int64_t total = off[G] - nold + st->n_particles;
+    if (total > ctx->cap) return DUWP_ECAPACITY;
+    // rebuild the whole canonical array on the host: earlier cases, this case, later cases
+    const bool mixed = ctx->precision == DUWP_MIXED;
+    const size_t es = mixed ? 4 : 8;
+    std::vector<char> hh[4];
+    for (int a = 0; a < 4; ++a) {
+        hh[a].resize(es * (size_t)total);
+        std::vector<char> old(es * (size_t)off[G]);
+        if (off[G]) HIP_OK(hipMemcpyAsync(old.data(), ctx->A[p][a], old.size(), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        std::memcpy(hh[a].data(), old.data(), es * (size_t)b);
+        std::memcpy(hh[a].data() + es * (size_t)(b + st->n_particles), old.data() + es * (size_t)(b + nold),
+                    es * (size_t)(off[G] - b - nold));
+        const double *srcv[4] = {st->x, st->u, st->v, st->w};
+        for (int i = 0; i < d.ncells; ++i)
+            for (int64_t q = st->off[i]; q < st->off[i + 1]; ++q) {
+                double val = srcv[a][q];
+                if (mixed) {
+                    float f;
+                    if (a == 0) {
+                        double s = (val - d.x_lo) / d.dx - (double)i;
+                        f = (float)s;
+                        if (f < 0.0f) f = 0.0f;
+                        if (f >= 1.0f) f = 0.99999994f;
+                    } else {
+                        f = (float)val;
+                    }
+                    std::memcpy(hh[a].data() + 4 * (size_t)(b + q), &f, 4);
+                } else {
+                    std::memcpy(hh[a].data() + 8 * (size_t)(b + q), &val, 8);
+                }
+            }
+        if (total) HIP_OK(hipMemcpyAsync(ctx->A[p][a], hh[a].data(), hh[a].size(), hipMemcpyHostToDevice, ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+    }
+    std::vector<int64_t> noff((size_t)G + 1);
+    const int64_t delta = st->n_particles - nold;
+    for (int g = 0; g <= G; ++g) {
+        if (g < d.cell_base) noff[g] = off[g];
+        else if (g <= d.cell_base + d.ncells) noff[g] = b + st->off[g - d.cell_base];
+        else noff[g] = off[g] + delta;
+    }
+    hipStream_t s = ctx->stream;
+    HIP_OK(hipMemcpyAsync(ctx->off[p], noff.data(), 8 * noff.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(ctx->cl.psi_w + 5 * (size_t)d.cell_base, st->psi_w, 8 * 5 * (size_t)d.ncells,
+                          hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(ctx->cl.cr_max + d.cell_base, st->cr_max, 8 * (size_t)d.ncells, hipMemcpyHostToDevice, s));
+    // the step index is shared by all cases; the parity of the buffers follows it
+    if ((st->step & 1u) != (ctx->step & 1u)) {
+        for (int a = 0; a < 4; ++a)
+            if (total)
+                HIP_OK(hipMemcpyAsync(ctx->A[p ^ 1][a], ctx->A[p][a], es * (size_t)total, hipMemcpyDeviceToDevice, s));
+        HIP_OK(hipMemcpyAsync(ctx->off[p ^ 1], ctx->off[p], 8 * (size_t)(G + 1), hipMemcpyDeviceToDevice, s));
+    }
+    ctx->step = st->step;
+    uint32_t dstep = st->step;
+    HIP_OK(hipMemcpyAsync(ctx->d_step, &dstep, 4, hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    (void)hipGetLastError();
+    duwp::enqueue_moments(ctx);
+    if (hipGetLastError() != hipSuccess) return DUWP_EDEVICE;
+    HIP_OK(hipStreamSynchronize(s));
+    return DUWP_OK;
+}
+
+duwp_status duwp_profile(duwp_ctx *ctx, int32_t nsteps, const char **names, double *ms, int32_t cap,
+                         int32_t *count)
+{
+    if (!ctx || nsteps <= 0) return DUWP_EINVAL;
+    duwp::KernelTimer &t = ctx->timer;
+    const int nk = 16;
+    if (t.ev.empty()) {
+        t.ev.resize(2 * nk);
+        for (auto &e : t.ev) HIP_OK(hipEventCreate(&e));
+    }
+    std::vector<double> acc(nk, 0.0);
+    int used = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        t.on = true;
+        t.idx = 0;
+        duwp::enqueue_step(ctx);
+        t.on = false;
+        ctx->step += 1;
+        ctx->avg_count += 1;
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        used = t.idx;
+        for (int i = 0; i < used; ++i) {
+            float m = 0.0f;
+            HIP_OK(hipEventElapsedTime(&m, t.ev[2 * i], t.ev[2 * i + 1]));
+            acc[i] += m;
+        }
+    }
+    if (count) *count = used;
+    for (int i = 0; i < used && i < cap; ++i) {
+        if (names) names[i] = t.names[i].c_str();
+        if (ms) ms[i] = acc[i] / nsteps;
+    }
+    return read_error(ctx);
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Host-side context of the DUWP library (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "duwp.h"
+#include "duwp_device.hpp"
+
+namespace duwp {
+
+// One kernel of the step, for per-kernel timing.
+struct KernelTimer {
+    std::vector<std::string> names;
+    std::vector<hipEvent_t> ev;     // ev[2*i], ev[2*i+1] bracket kernel i
+    std::vector<double> ms;
+    bool on = false;
+    int idx = 0;
+};
+
+}  // namespace duwp
+
+struct duwp_ctx {
+    int ncases = 0, G = 0;
+    int precision = DUWP_FP64;
+    int use_graph = 0;
+    int block_cells = 256;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;  // created by the library when the caller passed none
+    uint64_t seed = 0;
+    std::vector<duwp_case> cases;
+    std::vector<duwp::DCase> hcases;
+    int64_t cap = 0;          // particle capacity (canonical and staging arrays)
+    int64_t inj_total = 0;    // injection buffer slots
+    uint32_t step = 0;        // host copy of the step index
+    int64_t avg_count = 0;
+
+    duwp::DCase *d_cases = nullptr;
+    void *A[2][4] = {{nullptr}};   // canonical particle arrays, by step parity
+    void *S[4] = {nullptr};        // staging (intermediate) arrays
+    void *J[4] = {nullptr};        // injected entrants
+    int32_t *j_dest = nullptr, *j_rank = nullptr, *j_count = nullptr;
+    int64_t *off[2] = {nullptr, nullptr};
+    int64_t *ibase = nullptr;
+    duwp::Cells cl{};
+    int64_t *scan_part = nullptr;
+    int ntiles = 0;
+    uint32_t *d_step = nullptr;
+    int32_t *d_err = nullptr;
+    int64_t *d_nout = nullptr;     // [ncases]
+    int64_t *d_ninj = nullptr;     // [ncases*2]
+    int64_t *d_total = nullptr;    // [2]
+    int64_t *d_psteps = nullptr;   // particle-steps since init or the last reset
+
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    bool graph_ready = false;
+    duwp::KernelTimer timer;
+    std::vector<void *> allocs;
+};
+
+namespace duwp {
+// Launch the kernels of one step on ctx->stream (defined with the kernels).
+void enqueue_step(duwp_ctx *ctx);
+// Recompute the particle moments of the current canonical state (no averaging).
+void enqueue_moments(duwp_ctx *ctx);
+}  // namespace duwp

@@ -1,0 +1,164 @@
+// Device-side types and helpers of the DUWP pipeline (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace duwp {
+
+constexpr int KWIN = 16;             // a particle may move at most KWIN cells per step
+constexpr int NBIN = 2 * KWIN + 1;   // destination bins per source cell
+constexpr int WAVE = 64;
+
+// Philox counter tags: one per kind of random draw.
+enum : uint32_t { TAG_CLS = 1, TAG_RCNT = 2, TAG_RVEL = 3, TAG_NCNT = 4, TAG_PAIR = 5,
+                  TAG_ICNT = 6, TAG_IVEL = 7 };
+
+// Device error word bits.
+enum : int32_t { ERR_CAPACITY = 1, ERR_RANGE = 2, ERR_STATE = 4 };
+
+// Per-case constants, derived on the host once.
+struct DCase {
+    int32_t ncells, cell_base;
+    int32_t bc_lo, bc_hi, law, eps_law, full_dt, pad0;
+    uint32_t key0, key1;
+    int64_t inj_base, inj_cap;       // slot range of this case in the injection buffer
+    double x_lo, x_hi, dx, dt;
+    double R, omega, T_ref, mu_ref, coll_k, ups, c_ref;
+    double m_p, fac;                 // fac = m_p / dx
+    double rho_L, u_L, T_L, rho_R, u_R, T_R;
+    float dtdx_f, pad1;              // dt/dx for the cell-relative FP32 positions
+};
+
+// Per-step, per-cell work arrays shared by the stage kernels.
+struct Cells {
+    double *psi_w;      // [G*5] wave part
+    double *psi_p;      // [G*5] particle part of the canonical array
+    double *wt;         // [G*5] (rho, U, V, W, T) of the total at step start
+    double *pc;         // [G] absorbed fraction P
+    int32_t *okc;       // [G] 1 unless vacuum
+    double *cr_max;     // [G]
+    int32_t *n_surv, *n_new, *n_int;   // [G]
+    int32_t *d_abs, *d_new, *d_cand, *d_coll;  // [G] diagnostics
+    int32_t *hist;      // [G*NBIN] destination histogram, then scatter bases
+    int32_t *cnt_new;   // [G]
+    int32_t *inj_cnt;   // [G] injected entrants per destination cell
+    int64_t *inj_start; // [G] first slot of the injected entrants of each destination cell
+    int32_t *cell_case; // [G]
+    double *avg;        // [G*5]
+};
+
+// Injection buffer: entrants of every case, plus their destination and rank.
+template <typename T>
+struct Inj {
+    T *x, *u, *v, *w;
+    int32_t *dest;      // global destination cell, -1 for an unused slot
+    int32_t *rank;      // rank among injected entrants of the same destination
+    int32_t *count;     // [ncases] entrants written this step
+};
+
+template <typename T>
+struct Soa {
+    T *x, *u, *v, *w;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+// ---------------------------------------------------------------------------
+struct U4 { uint32_t a, b, c, d; };
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ U4 draw(const DCase &cs, uint32_t step, uint32_t a, uint32_t b,
+                                   uint32_t tag, uint32_t j)
+{
+    return philox(step, a, b, (tag << 16) | j, cs.key0, cs.key1);
+}
+
+// [0,1) with 2^-32 resolution (exact in FP64)
+__device__ __forceinline__ double u01(uint32_t r) { return (double)r * 2.3283064365386962890625e-10; }
+
+// uniform index in [0,n): floor(r n / 2^64)
+__device__ __forceinline__ uint64_t mulhi64(uint64_t r, uint64_t n) { return __umul64hi(r, n); }
+
+// ---------------------------------------------------------------------------
+// Wave / block primitives
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+// Deterministic block sum of N doubles per thread; the result is valid in every thread.
+// red must hold N * (blockDim/64) doubles.
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double *red)
+{
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
+    __syncthreads();
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) red[k * nw + w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < nw; ++i) s += red[k * nw + i];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+// Exclusive block prefix of a 0/1 flag; returns this thread's prefix, *total the block total.
+// scratch must hold blockDim/64 ints.
+__device__ __forceinline__ int block_flag_prefix(bool f, int *scratch, int *total)
+{
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint64_t m = __ballot(f);
+    int in_wave = __popcll(m & lanemask_lt());
+    __syncthreads();
+    if (lane_id() == 0) scratch[w] = __popcll(m);
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        int c = scratch[i];
+        if (i < w) base += c;
+        tot += c;
+    }
+    *total = tot;
+    return base + in_wave;
+}
+
+}  // namespace duwp

@@ -1,0 +1,203 @@
+"""Parity of the HIP pipeline (through the C ABI) with the CPU oracle.
+
+Integer work (cell offsets, i.e. the sort's cell structure, and per-cell counts
+of absorbed, resampled, candidate and accepted collisions, injected and leaving
+particles) must be identical; floating state within 1e-12 relative per step.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2305_12071_amd import duwp
+from paper_2305_12071_amd import inputs as I
+
+from _parity import RTOL, assert_close, compare_diag, compare_states
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cases():
+    out = {
+        "mach3": I.mach3_small(),                       # P = 0: DSMC, reservoirs, injection
+        "sod_kn1e-4": I.sod_paper(1e-4),                # P ~ 0.8 on the left: absorb/resample/wave
+        "sod_kn1e-5": I.sod_paper(1e-5),                # P ~ 0.98: near-continuum
+        "sod_kn1e-2": I.sod_paper(1e-2),                # pure DSMC with walls
+        "box_p97": I.box(12, 1.0, 1.0, 300, 30.0),     # heavy absorption
+    }
+    c = I.sod_paper(3e-4)
+    c.classify_law = I.CLASSIFY_EXP
+    c.eps_law = I.EPS_FULL
+    out["sod_exp_epsfull"] = c
+    c = I.sod_paper(1e-4)
+    c.eps_law = I.EPS12
+    c.dsmc_full_dt = 1
+    out["sod_eps12_fulldt"] = c
+    c = I.box(7, 0.8, 2.0, 150, 0.5, u=0.3)
+    out["box_ragged"] = c
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    O.build(force=False)
+    duwp.lib()
+
+
+def test_single_hip_runtime_in_process():
+    import torch
+    assert torch.cuda.is_available()
+    g = duwp.Sim(CASES["mach3"], seed=1)
+    g.step(1)
+    assert len(duwp.hip_runtimes_loaded()) == 1, duwp.hip_runtimes_loaded()
+    g.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_first_step_from_initial_state(name):
+    c = CASES[name]
+    _say("case", name, "fp64 first step")
+    g = duwp.Sim(c, seed=1, precision=duwp.FP64)
+    o = O.Oracle(c, seed=1, case_id=0)
+    g.step(1)
+    o.step(1)
+    compare_diag(g.diag(), o.diag(), name)
+    compare_states(g.get_state(), o.get_state(), label=name, psi_t=o.cells()["psi_t"])
+    g.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_step_from_identical_developed_state(name):
+    """Develop a state with the oracle, load it on the GPU, then one step on both."""
+    c = CASES[name]
+    _say("case", name, "fp64 one step from a developed state")
+    o = O.Oracle(c, seed=3, case_id=0)
+    o.step(12)
+    st = o.get_state()
+    g = duwp.Sim(c, seed=3, precision=duwp.FP64)
+    g.set_state(st)
+    gs = g.get_state()
+    compare_states(gs, st, rtol=0.0, label=name + ":roundtrip")
+    assert_close(g.moments(0, duwp.M_PSI_P), o.cells()["psi_p"], RTOL, name + ":psi_p")
+    for k in range(2):
+        g.step(1)
+        o.step(1)
+        compare_diag(g.diag(), o.diag(), f"{name}:{k}")
+        compare_states(g.get_state(), o.get_state(), label=f"{name}:{k}", psi_t=o.cells()["psi_t"])
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["mach3", "sod_kn1e-4", "box_p97"])
+def test_twenty_steps_from_initial_state(name):
+    c = CASES[name]
+    _say("case", name, "fp64 20 steps")
+    g = duwp.Sim(c, seed=7, precision=duwp.FP64)
+    o = O.Oracle(c, seed=7, case_id=0)
+    for k in range(20):
+        g.step(1)
+        o.step(1)
+        compare_diag(g.diag(), o.diag(), f"{name}:{k}")
+    compare_states(g.get_state(), o.get_state(), rtol=1e-10, label=name, psi_t=o.cells()["psi_t"])
+    assert_close(g.moments(0, duwp.M_AVG_SUM), o.average()[0], 1e-10, name + ":avg")
+    g.close()
+
+
+def test_batched_uneven_cases_match_per_case_oracles():
+    names = ["mach3", "sod_kn1e-4", "box_ragged", "sod_kn1e-2", "sod_exp_epsfull"]
+    cases = [CASES[n] for n in names]
+    _say("batched", names)
+    g = duwp.Sim(cases, seed=5, precision=duwp.FP64)
+    ors = [O.Oracle(c, seed=5, case_id=k) for k, c in enumerate(cases)]
+    for s in range(6):
+        g.step(1)
+        for k, o in enumerate(ors):
+            o.step(1)
+            compare_diag(g.diag(k), o.diag(), f"{names[k]}:{s}")
+    for k, o in enumerate(ors):
+        compare_states(g.get_state(k), o.get_state(), rtol=1e-11, label=names[k], psi_t=o.cells()["psi_t"])
+    g.close()
+
+
+def test_graph_replay_equals_eager_bitwise():
+    cases = [CASES["mach3"], CASES["sod_kn1e-4"]]
+    _say("graph vs eager")
+    a = duwp.Sim(cases, seed=2, precision=duwp.FP64, use_graph=False)
+    b = duwp.Sim(cases, seed=2, precision=duwp.FP64, use_graph=True)
+    for _ in range(3):
+        a.step(3)
+        b.step(3)
+        for k in range(2):
+            sa, sb = a.get_state(k), b.get_state(k)
+            for key in ("x", "u", "v", "w", "off", "psi_w", "cr_max"):
+                assert np.array_equal(sa[key], sb[key]), key
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("prec", [duwp.FP64, duwp.MIXED])
+def test_run_twice_is_bitwise_identical(prec):
+    c = CASES["sod_kn1e-4"]
+    _say("determinism", prec)
+    a = duwp.Sim(c, seed=9, precision=prec)
+    b = duwp.Sim(c, seed=9, precision=prec)
+    a.step(15)
+    b.step(15)
+    sa, sb = a.get_state(), b.get_state()
+    for key in ("x", "u", "v", "w", "off", "psi_w", "cr_max"):
+        assert np.array_equal(sa[key], sb[key]), key
+    a.close()
+    b.close()
+
+
+def test_resume_from_checkpoint_is_bitwise_identical():
+    c = CASES["mach3"]
+    _say("resume")
+    a = duwp.Sim(c, seed=4)
+    a.step(7)
+    b = duwp.Sim(c, seed=4)
+    b.set_state(a.get_state())
+    a.step(5)
+    b.step(5)
+    sa, sb = a.get_state(), b.get_state()
+    for key in ("x", "u", "v", "w", "off", "psi_w", "cr_max"):
+        assert np.array_equal(sa[key], sb[key]), key
+
+
+def test_capacity_overflow_is_reported():
+    c = I.sod_paper(1e-2)
+    c.capacity = 1000      # far below the ~1.1e5 particles of the first step
+    _say("capacity")
+    g = duwp.Sim(c, seed=1)
+    with pytest.raises(duwp.DuwpError) as e:
+        g.step(2)
+    assert e.value.status == -4
+    g.close()
+
+
+def test_mixed_precision_profiles_match_fp64():
+    """FP32 particles + FP64 cells against FP64: time-averaged profiles of the Mach-3
+    shock agree to the seed-to-seed noise of the FP64 path."""
+    c = CASES["mach3"]
+    _say("mixed vs fp64")
+    res = {}
+    for prec in (duwp.FP64, duwp.MIXED):
+        for seed in (1, 2):
+            g = duwp.Sim(c, seed=seed, precision=prec)
+            g.step(200)
+            g.reset_average()
+            g.step(300)
+            res[(prec, seed)] = g.moments(0, duwp.M_AVG_PRIM)
+            g.close()
+    noise = np.abs(res[(0, 1)] - res[(0, 2)])[:, [0, 4]].mean(0)
+    diff = np.abs(res[(1, 1)] - res[(0, 1)])[:, [0, 4]].mean(0)
+    _say("noise", noise, "mixed-fp64", diff)
+    assert np.all(diff < 3.0 * noise + 1e-12)
