@@ -73,17 +73,14 @@ DCase derive(const duwp_case &c, int cell_base, uint64_t seed, int case_id)
     return d;
 }
 
-// Upper bound on the entrants of one step: floor((1-P) rho Lg / m_p + u) <= rho Lg / m_p + 1.
-int64_t inject_bound(const duwp_case &c)
+// Upper bound on the injection candidates of one side in one step:
+// floor((1-P) rho Lg / m_p + u) <= rho Lg / m_p + 1.
+int64_t inject_bound(const duwp_case &c, int side)
 {
-    int64_t n = 0;
-    for (int side = 0; side < 2; ++side) {
-        if ((side == 0 ? c.bc_lo : c.bc_hi) != DUWP_BC_RESERVOIR) continue;
-        double rho = side == 0 ? c.rho_L : c.rho_R, U = side == 0 ? c.u_L : c.u_R, T = side == 0 ? c.T_L : c.T_R;
-        double Lg = c.dt * (std::fabs(U) + 8.0 * std::sqrt(c.R * T));
-        n += (int64_t)std::ceil(rho * Lg / c.m_particle) + 2;
-    }
-    return n;
+    if ((side == 0 ? c.bc_lo : c.bc_hi) != DUWP_BC_RESERVOIR) return 0;
+    double rho = side == 0 ? c.rho_L : c.rho_R, U = side == 0 ? c.u_L : c.u_R, T = side == 0 ? c.T_L : c.T_R;
+    double Lg = c.dt * (std::fabs(U) + 8.0 * std::sqrt(c.R * T));
+    return (int64_t)std::ceil(rho * Lg / c.m_particle) + 2;
 }
 
 template <typename P>
@@ -113,6 +110,9 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &ctx->j_dest, 4 * (size_t)ctx->inj_total));
     TRY(dalloc(ctx, &ctx->j_rank, 4 * (size_t)ctx->inj_total));
     TRY(dalloc(ctx, &ctx->j_count, 4 * (size_t)ctx->ncases));
+    for (int a = 0; a < 4; ++a) TRY(dalloc(ctx, &ctx->K[a], es * (size_t)ctx->cand_total));
+    TRY(dalloc(ctx, &ctx->k_dest, 4 * (size_t)ctx->cand_total));
+    TRY(dalloc(ctx, &ctx->k_n, 16 * (size_t)ctx->ncases));
     for (int p = 0; p < 2; ++p) TRY(dalloc(ctx, &ctx->off[p], 8 * (size_t)(G + 1)));
     TRY(dalloc(ctx, &ctx->ibase, 8 * (size_t)(G + 1)));
     duwp::Cells &c = ctx->cl;
@@ -125,6 +125,10 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &c.n_surv, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.n_new, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.n_int, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.n_stage, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.seg, 8 * (size_t)G));
+    TRY(dalloc(ctx, &c.seg_stg, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.mpart, 8 * 5 * (size_t)G * duwp::NBIN));
     TRY(dalloc(ctx, &c.d_abs, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.d_new, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.d_cand, 4 * (size_t)G));
@@ -185,6 +189,7 @@ duwp_status upload_initial(duwp_ctx *ctx)
     HIP_OK(hipMemsetAsync(ctx->d_nout, 0, 8 * (size_t)ctx->ncases, s));
     HIP_OK(hipMemsetAsync(ctx->d_ninj, 0, 16 * (size_t)ctx->ncases, s));
     HIP_OK(hipMemsetAsync(ctx->j_count, 0, 4 * (size_t)ctx->ncases, s));
+    HIP_OK(hipMemsetAsync(ctx->k_n, 0, 16 * (size_t)ctx->ncases, s));
     const duwp::Cells &c = ctx->cl;
     for (int32_t *p : {c.d_abs, c.d_new, c.d_cand, c.d_coll}) HIP_OK(hipMemsetAsync(p, 0, 4 * (size_t)G, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -302,7 +307,7 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
     ctx->block_cells = opts->block_cells > 0 ? opts->block_cells : 256;
     if (ctx->block_cells % 64 || ctx->block_cells > 1024) { delete ctx; return DUWP_EINVAL; }
     const double head = opts->headroom > 0.0 ? opts->headroom : 1.5;
-    int64_t G = 0, cap = 0, inj = 0;
+    int64_t G = 0, cap = 0, inj = 0, cand = 0, max_side = 0;
     for (int k = 0; k < ncases; ++k) {
         const duwp_case &c = cases[k];
         if (!case_valid(c)) { delete ctx; return DUWP_EINVAL; }
@@ -315,15 +320,26 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
             cc = (int64_t)std::ceil(head * mass / c.m_particle) + 4096;
         }
         cap += cc;
-        const int64_t ib = inject_bound(c);
-        ctx->hcases.back().inj_base = inj;
-        ctx->hcases.back().inj_cap = ib;
+        DCase &d = ctx->hcases.back();
+        int64_t ib = 0;
+        for (int side = 0; side < 2; ++side) {
+            const int64_t nb = inject_bound(c, side);
+            d.cand_base[side] = cand;
+            d.cand_cap[side] = nb;
+            cand += nb;
+            ib += nb;
+            max_side = std::max(max_side, nb);
+        }
+        d.inj_base = inj;
+        d.inj_cap = ib;
         inj += ib;
     }
     if (G > (int64_t)1 << 30 || cap > ((int64_t)1 << 40)) { delete ctx; return DUWP_EINVAL; }
     ctx->G = (int)G;
     ctx->cap = cap;
     ctx->inj_total = std::max<int64_t>(inj, 1);
+    ctx->cand_total = std::max<int64_t>(cand, 1);
+    ctx->inj_blocks = (int)std::min<int64_t>((max_side + 255) / 256, 64);
     duwp_status s = alloc_all(ctx);
     if (s == DUWP_OK) s = upload_initial(ctx);
     if (s != DUWP_OK) { duwp_destroy(ctx); return s; }

@@ -42,6 +42,11 @@ struct duwp_ctx {
     void *S[4] = {nullptr};        // staging (intermediate) arrays
     void *J[4] = {nullptr};        // injected entrants
     int32_t *j_dest = nullptr, *j_rank = nullptr, *j_count = nullptr;
+    void *K[4] = {nullptr};        // injection candidates
+    int32_t *k_dest = nullptr;
+    int64_t *k_n = nullptr;        // [ncases*2] candidates per side
+    int64_t cand_total = 0;
+    int inj_blocks = 0;            // x-blocks of the candidate kernel
     int64_t *off[2] = {nullptr, nullptr};
     int64_t *ibase = nullptr;
     duwp::Cells cl{};

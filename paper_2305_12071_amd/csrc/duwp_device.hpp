@@ -22,7 +22,8 @@ struct DCase {
     int32_t ncells, cell_base;
     int32_t bc_lo, bc_hi, law, eps_law, full_dt, pad0;
     uint32_t key0, key1;
-    int64_t inj_base, inj_cap;       // slot range of this case in the injection buffer
+    int64_t inj_base, inj_cap;       // slot range of this case's entrants in the injection buffer
+    int64_t cand_base[2], cand_cap[2];  // injection candidate slots per side
     double x_lo, x_hi, dx, dt;
     double R, omega, T_ref, mu_ref, coll_k, ups, c_ref;
     double m_p, fac;                 // fac = m_p / dx
@@ -38,7 +39,10 @@ struct Cells {
     double *pc;         // [G] absorbed fraction P
     int32_t *okc;       // [G] 1 unless vacuum
     double *cr_max;     // [G]
-    int32_t *n_surv, *n_new, *n_int;   // [G]
+    int32_t *n_surv, *n_new, *n_int;   // [G] survivors, resampled, survivors+resampled
+    int32_t *n_stage;   // [G] particles copied to staging (0 for an untouched cell)
+    int64_t *seg;       // [G] start of the cell's intermediate segment
+    int32_t *seg_stg;   // [G] 1: segment in the staging buffer, 0: in place in the canonical buffer
     int32_t *d_abs, *d_new, *d_cand, *d_coll;  // [G] diagnostics
     int32_t *hist;      // [G*NBIN] destination histogram, then scatter bases
     int32_t *cnt_new;   // [G]
@@ -46,15 +50,20 @@ struct Cells {
     int64_t *inj_start; // [G] first slot of the injected entrants of each destination cell
     int32_t *cell_case; // [G]
     double *avg;        // [G*5]
+    double *mpart;      // [G*NBIN*5] particle moment sums per (source cell, destination)
 };
 
-// Injection buffer: entrants of every case, plus their destination and rank.
+// Injection buffers: candidates of every (case, side), then the entrants of
+// every case in (side, slot) order with their destination and rank.
 template <typename T>
 struct Inj {
     T *x, *u, *v, *w;
-    int32_t *dest;      // global destination cell, -1 for an unused slot
+    int32_t *dest;      // global destination cell of an entrant
     int32_t *rank;      // rank among injected entrants of the same destination
     int32_t *count;     // [ncases] entrants written this step
+    T *cx, *cu, *cv, *cw;
+    int32_t *cdest;     // local destination of a candidate, -1 if it does not enter
+    int64_t *ncand;     // [ncases*2] candidates generated per side
 };
 
 template <typename T>

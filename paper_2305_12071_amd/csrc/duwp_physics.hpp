@@ -1,0 +1,294 @@
+// Device-side gas physics of the DUWP step: viscosity and relaxation time,
+// absorption fraction (Eq. p), primitive state, Maxwellian sampling
+// (Eq. maxsample), free flight with boundaries, and the wave flux (Sec. 3.3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <type_traits>
+
+#include "duwp_device.hpp"
+
+namespace duwp {
+
+#define D_TWO_PI 6.283185307179586
+
+// ---------------------------------------------------------------------------
+// Gas physics
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double viscosity(const DCase &c, double T)
+{
+    return c.mu_ref * pow(T / c.T_ref, c.omega);
+}
+
+// Eq. p (law 0) or the QMC probability 1 - exp(-dt/tau) (law 1)
+__device__ __forceinline__ double absorb_fraction(int law, double dt, double tau)
+{
+    if (law == 1) return -expm1(-dt / tau);
+    return (dt > tau) ? 1.0 - tau / dt : 0.0;
+}
+
+// (rho,U,V,W,T) of a conserved vector; 0 for vacuum (rho <= 0, T <= 0 or not finite)
+__device__ __forceinline__ int primitive(const double t[5], double R, double W[5])
+{
+    double rho = t[0];
+    if (!(rho > 0.0)) { W[0] = rho; W[1] = W[2] = W[3] = W[4] = 0.0; return 0; }
+    double U = t[1] / rho, V = t[2] / rho, Wv = t[3] / rho;
+    double e = t[4] / rho;
+    double T = (2.0 / (3.0 * R)) * (e - 0.5 * (U * U + V * V + Wv * Wv));
+    W[0] = rho; W[1] = U; W[2] = V; W[3] = Wv; W[4] = T;
+    return (T > 0.0) && isfinite(T);
+}
+
+__device__ __forceinline__ uint32_t pick(const U4 &r, uint32_t i)
+{
+    return i == 0 ? r.a : (i == 1 ? r.b : (i == 2 ? r.c : r.d));
+}
+
+// Maxwellian velocity, one (cos, log) pair of uniforms per component (Eq. maxsample)
+__device__ __forceinline__ void maxwell(double U, double V, double W, double T, double R,
+                                        const double uu[6], double out[3])
+{
+    double sd = sqrt(2.0 * R * T);
+    double mean[3] = {U, V, W};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        out[d] = mean[d] + sd * cos(D_TWO_PI * uu[2 * d]) * sqrt(-log(1.0 - uu[2 * d + 1]));
+}
+
+// ---------------------------------------------------------------------------
+// Free flight and boundaries.  Returns the local destination cell, -1 if the
+// particle left through a reservoir side.
+// ---------------------------------------------------------------------------
+
+// FP64, absolute position.
+__device__ __forceinline__ int bc_cell_abs(const DCase &c, double &x, double &u)
+{
+    for (int it = 0; it < 1000; ++it) {
+        if (x < c.x_lo) {
+            if (c.bc_lo == 0) return -1;
+            x = 2.0 * c.x_lo - x;
+            u = -u;
+        } else if (x > c.x_hi) {
+            if (c.bc_hi == 0) return -1;
+            x = 2.0 * c.x_hi - x;
+            u = -u;
+        } else {
+            double f = floor((x - c.x_lo) / c.dx);
+            int64_t ci = (int64_t)f;
+            if (f < 0.0) ci = 0;
+            if (ci > c.ncells - 1) ci = c.ncells - 1;
+            return (int)ci;
+        }
+    }
+    return -1;
+}
+
+// FP32, position as (integer cell I, fraction f in [0,1)) relative to x_lo.
+__device__ __forceinline__ int bc_cell_rel(const DCase &c, int I, float f, float &u, float &s)
+{
+    const int C = c.ncells;
+    for (int it = 0; it < 1000; ++it) {
+        if (I < 0) {
+            if (c.bc_lo == 0) return -1;
+            I = -I - 1;
+            f = 1.0f - f;
+            u = -u;
+        } else if (I >= C) {
+            if (c.bc_hi == 0) return -1;
+            I = 2 * C - I - 1;
+            f = 1.0f - f;
+            u = -u;
+        } else {
+            if (f >= 1.0f) { f -= 1.0f; I += 1; continue; }
+            s = f;
+            return I;
+        }
+    }
+    return -1;
+}
+
+template <typename T>
+struct Flight;
+
+template <>
+struct Flight<double> {
+    // stream a particle of local cell lc; x is absolute
+    __device__ static int go(const DCase &c, int /*lc*/, double &x, double &u)
+    {
+        x = x + u * c.dt;
+        return bc_cell_abs(c, x, u);
+    }
+};
+
+template <>
+struct Flight<float> {
+    // stream a particle of local cell lc; x is the position inside the cell, in cells
+    __device__ static int go(const DCase &c, int lc, float &s, float &u)
+    {
+        float X = s + u * c.dtdx_f;
+        if (!(fabsf(X) < 1.0e9f)) return -1;
+        float fl = floorf(X);
+        return bc_cell_rel(c, lc + (int)fl, X - fl, u, s);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Wave part: NS flux (KFVS inviscid + central viscous, eps-scaled viscosity,
+// weighted by the interface absorption fraction).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void kfvs_half(const double W[5], double R, int sign, double H[5])
+{
+    double U = W[1], V = W[2], Wv = W[3], th = R * W[4];
+    double a = U / sqrt(2.0 * th);
+    double A = 0.5 * erfc(-(double)sign * a);
+    double B = sqrt(th / D_TWO_PI) * exp(-a * a);
+    double sg = (double)sign;
+    double M1 = U * A + sg * B;
+    double M2 = (U * U + th) * A + sg * U * B;
+    double M3 = (U * U * U + 3.0 * U * th) * A + sg * (U * U + 2.0 * th) * B;
+    H[0] = M1;
+    H[1] = M2;
+    H[2] = V * M1;
+    H[3] = Wv * M1;
+    H[4] = 0.5 * M3 + 0.5 * (V * V + Wv * Wv + 2.0 * th) * M1;
+}
+
+__device__ __forceinline__ double eps_factor(int law, double x)
+{
+    switch (law) {
+    case 1: return x / (2.0 + x);
+    case 2: return 1.0;
+    case 3: {
+        double em = -expm1(-x);
+        return (-2.0 * em + x * (1.0 + exp(-x))) / (x - em);
+    }
+    default: return 1.0 - x / expm1(x);
+    }
+}
+
+__device__ __forceinline__ bool valid_state(const double W[5]) { return W[0] > 0.0 && W[4] > 0.0 && isfinite(W[4]); }
+
+__device__ inline void face_flux(const DCase &c, const double Wl[5], const double Wr[5], double F[5])
+{
+#pragma unroll
+    for (int k = 0; k < 5; ++k) F[k] = 0.0;
+    if (!valid_state(Wl) || !valid_state(Wr)) return;
+    double Wm[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Wm[k] = 0.5 * (Wl[k] + Wr[k]);
+    const double mu = viscosity(c, Wm[4]);
+    const double tau = mu / (Wm[0] * c.R * Wm[4]);
+    const double xr = c.dt / tau;
+    const double Pm = absorb_fraction(c.law, c.dt, tau);
+    if (!(Pm > 0.0)) return;
+    double Hp[5], Hm[5];
+    kfvs_half(Wl, c.R, +1, Hp);
+    kfvs_half(Wr, c.R, -1, Hm);
+    const double mue = eps_factor(c.eps_law, xr) * mu;
+    const double dU = (Wr[1] - Wl[1]) / c.dx;
+    const double dV = (Wr[2] - Wl[2]) / c.dx;
+    const double dW = (Wr[3] - Wl[3]) / c.dx;
+    const double dT = (Wr[4] - Wl[4]) / c.dx;
+    const double sxx = (4.0 / 3.0) * mue * dU;
+    const double sxy = mue * dV;
+    const double sxz = mue * dW;
+    const double q = -(15.0 / 4.0) * c.R * mue * dT;
+    const double visc[5] = {0.0, sxx, sxy, sxz, Wm[1] * sxx + Wm[2] * sxy + Wm[3] * sxz - q};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) F[k] = Pm * ((Wl[0] * Hp[k] + Wr[0] * Hm[k]) - visc[k]);
+}
+
+// flux through local face f (between local cells f-1 and f) of a case
+__device__ inline void case_face_flux(const DCase &c, const Cells &cl, int f, double F[5])
+{
+    const int C = c.ncells, base = c.cell_base;
+    double Wl[5], Wr[5];
+    int okl, okr;
+    if (f == 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Wr[k] = cl.wt[(int64_t)base * 5 + k];
+        if (c.bc_lo == 0) { Wl[0] = c.rho_L; Wl[1] = c.u_L; Wl[2] = 0.0; Wl[3] = 0.0; Wl[4] = c.T_L; }
+        else {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) Wl[k] = Wr[k];
+            Wl[1] = -Wr[1];
+        }
+        okl = (c.bc_lo == 0) || cl.okc[base];
+        okr = cl.okc[base];
+    } else if (f == C) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Wl[k] = cl.wt[(int64_t)(base + C - 1) * 5 + k];
+        if (c.bc_hi == 0) { Wr[0] = c.rho_R; Wr[1] = c.u_R; Wr[2] = 0.0; Wr[3] = 0.0; Wr[4] = c.T_R; }
+        else {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) Wr[k] = Wl[k];
+            Wr[1] = -Wl[1];
+        }
+        okl = cl.okc[base + C - 1];
+        okr = (c.bc_hi == 0) || cl.okc[base + C - 1];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            Wl[k] = cl.wt[(int64_t)(base + f - 1) * 5 + k];
+            Wr[k] = cl.wt[(int64_t)(base + f) * 5 + k];
+        }
+        okl = cl.okc[base + f - 1];
+        okr = cl.okc[base + f];
+    }
+    if (okl && okr) face_flux(c, Wl, Wr, F);
+    else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) F[k] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Equal-mass VHS collision of particles i and j of a cell segment (Appendix A):
+// acceptance (c_r/c_max)^(1-2 upsilon), isotropic scattering with
+// cos(theta) = 2 u3 - 1, phi = 2 pi u4.  Returns true when accepted.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ bool collide_pair(T *su, T *sv, T *sw, uint32_t i, uint32_t j, double cm,
+                                             double accept_exp, double u2, double u3, double u4,
+                                             double &seen)
+{
+    if constexpr (std::is_same<T, double>::value) {
+        double ui = su[i], vi = sv[i], wi = sw[i];
+        double uj = su[j], vj = sv[j], wj = sw[j];
+        double d0 = ui - uj, d1 = vi - vj, d2 = wi - wj;
+        double cr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        seen = fmax(seen, cr);
+        double pa = pow(cr / cm, accept_exp);
+        if (!(u2 < pa)) return false;
+        double ct = 2.0 * u3 - 1.0;
+        double st = sqrt(1.0 - ct * ct);
+        double ph = D_TWO_PI * u4;
+        double r0 = cr * st * cos(ph), r1 = cr * st * sin(ph), r2 = cr * ct;
+        double m0 = 0.5 * (ui + uj), m1 = 0.5 * (vi + vj), m2 = 0.5 * (wi + wj);
+        su[i] = m0 + 0.5 * r0; sv[i] = m1 + 0.5 * r1; sw[i] = m2 + 0.5 * r2;
+        su[j] = m0 - 0.5 * r0; sv[j] = m1 - 0.5 * r1; sw[j] = m2 - 0.5 * r2;
+        return true;
+    } else {
+        float ui = su[i], vi = sv[i], wi = sw[i];
+        float uj = su[j], vj = sv[j], wj = sw[j];
+        float d0 = ui - uj, d1 = vi - vj, d2 = wi - wj;
+        float cr = sqrtf(__fmaf_rn(d0, d0, __fmaf_rn(d1, d1, d2 * d2)));
+        seen = fmax(seen, (double)cr);
+        float pa = powf(cr / (float)cm, (float)accept_exp);
+        if (!(u2 < (double)pa)) return false;
+        float ct = __fmaf_rn(2.0f, (float)u3, -1.0f);
+        float st = sqrtf(fmaxf(__fmaf_rn(-ct, ct, 1.0f), 0.0f));
+        float sp, cp;
+        sincosf((float)D_TWO_PI * (float)u4, &sp, &cp);
+        float h = 0.5f * cr;
+        float r0 = h * st * cp, r1 = h * st * sp, r2 = h * ct;
+        float m0 = 0.5f * (ui + uj), m1 = 0.5f * (vi + vj), m2 = 0.5f * (wi + wj);
+        su[i] = m0 + r0; sv[i] = m1 + r1; sw[i] = m2 + r2;
+        su[j] = m0 - r0; sv[j] = m1 - r1; sw[j] = m2 - r2;
+        return true;
+    }
+}
+
+}  // namespace duwp

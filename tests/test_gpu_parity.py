@@ -201,3 +201,21 @@ def test_mixed_precision_profiles_match_fp64():
     diff = np.abs(res[(1, 1)] - res[(0, 1)])[:, [0, 4]].mean(0)
     _say("noise", noise, "mixed-fp64", diff)
     assert np.all(diff < 3.0 * noise + 1e-12)
+
+
+@pytest.mark.parametrize("prec", [duwp.FP64, duwp.MIXED])
+def test_fused_moments_equal_recomputed_moments(prec):
+    """The particle moments produced inside the sort (per source/destination group)
+    equal the moments recomputed from the stored state."""
+    cases = [CASES["mach3"], CASES["sod_kn1e-4"], CASES["box_ragged"]]
+    _say("fused moments", prec)
+    g = duwp.Sim(cases, seed=6, precision=prec)
+    g.step(8)
+    for k in range(len(cases)):
+        h = duwp.Sim(cases, seed=6, precision=prec)
+        h.set_state(g.get_state(k), k)
+        a, b = g.moments(k, duwp.M_PSI_P), h.moments(k, duwp.M_PSI_P)
+        scale = np.abs(b).max(axis=0)[None, :]
+        assert np.all(np.abs(a - b) <= 1e-12 * scale), k
+        h.close()
+    g.close()
