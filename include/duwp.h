@@ -78,7 +78,7 @@ typedef struct {
     int32_t use_graph;            /* 1: replay each step as a captured HIP graph */
     void *stream;                 /* hipStream_t, or NULL */
     double headroom;              /* capacity = headroom * mass / m_particle when capacity = 0 (<= 0: 1.5) */
-    int32_t block_cells;          /* threads per block of the per-cell kernels (0: 256) */
+    int32_t block_cells;          /* threads per block of the per-cell kernels, 64..512 (0: 256) */
     int32_t reserved;
 } duwp_opts;
 

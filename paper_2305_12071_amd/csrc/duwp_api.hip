@@ -113,6 +113,7 @@ duwp_status alloc_all(duwp_ctx *ctx)
     for (int a = 0; a < 4; ++a) TRY(dalloc(ctx, &ctx->K[a], es * (size_t)ctx->cand_total));
     TRY(dalloc(ctx, &ctx->k_dest, 4 * (size_t)ctx->cand_total));
     TRY(dalloc(ctx, &ctx->k_n, 16 * (size_t)ctx->ncases));
+    TRY(dalloc(ctx, &ctx->k_chunk, 4 * (size_t)ctx->chunk_total));
     for (int p = 0; p < 2; ++p) TRY(dalloc(ctx, &ctx->off[p], 8 * (size_t)(G + 1)));
     TRY(dalloc(ctx, &ctx->ibase, 8 * (size_t)(G + 1)));
     duwp::Cells &c = ctx->cl;
@@ -133,7 +134,11 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &c.d_new, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.d_cand, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.d_coll, 4 * (size_t)G));
-    TRY(dalloc(ctx, &c.hist, 4 * (size_t)G * duwp::NBIN));
+    for (int p = 0; p < 2; ++p) {
+        TRY(dalloc(ctx, &ctx->hist_buf[p], 4 * (size_t)G * duwp::NBIN));
+        TRY(dalloc(ctx, &ctx->fix_buf[p], 4 * (size_t)G));
+    }
+    c.hist = ctx->hist_buf[0];
     TRY(dalloc(ctx, &c.cnt_new, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.inj_cnt, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.inj_start, 8 * (size_t)G));
@@ -190,6 +195,10 @@ duwp_status upload_initial(duwp_ctx *ctx)
     HIP_OK(hipMemsetAsync(ctx->d_ninj, 0, 16 * (size_t)ctx->ncases, s));
     HIP_OK(hipMemsetAsync(ctx->j_count, 0, 4 * (size_t)ctx->ncases, s));
     HIP_OK(hipMemsetAsync(ctx->k_n, 0, 16 * (size_t)ctx->ncases, s));
+    for (int p = 0; p < 2; ++p) {
+        HIP_OK(hipMemsetAsync(ctx->hist_buf[p], 0, 4 * (size_t)G * duwp::NBIN, s));
+        HIP_OK(hipMemsetAsync(ctx->fix_buf[p], 0, 4 * (size_t)G, s));
+    }
     const duwp::Cells &c = ctx->cl;
     for (int32_t *p : {c.d_abs, c.d_new, c.d_cand, c.d_coll}) HIP_OK(hipMemsetAsync(p, 0, 4 * (size_t)G, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -305,9 +314,9 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
     }
     ctx->seed = opts->seed;
     ctx->block_cells = opts->block_cells > 0 ? opts->block_cells : 256;
-    if (ctx->block_cells % 64 || ctx->block_cells > 1024) { delete ctx; return DUWP_EINVAL; }
+    if (ctx->block_cells % 64 || ctx->block_cells > 512) { delete ctx; return DUWP_EINVAL; }
     const double head = opts->headroom > 0.0 ? opts->headroom : 1.5;
-    int64_t G = 0, cap = 0, inj = 0, cand = 0, max_side = 0;
+    int64_t G = 0, cap = 0, inj = 0, cand = 0, max_side = 0, chunks = 0;
     for (int k = 0; k < ncases; ++k) {
         const duwp_case &c = cases[k];
         if (!case_valid(c)) { delete ctx; return DUWP_EINVAL; }
@@ -326,6 +335,8 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
             const int64_t nb = inject_bound(c, side);
             d.cand_base[side] = cand;
             d.cand_cap[side] = nb;
+            d.chunk_base[side] = chunks;
+            chunks += (nb + 255) / 256;
             cand += nb;
             ib += nb;
             max_side = std::max(max_side, nb);
@@ -339,6 +350,7 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
     ctx->cap = cap;
     ctx->inj_total = std::max<int64_t>(inj, 1);
     ctx->cand_total = std::max<int64_t>(cand, 1);
+    ctx->chunk_total = std::max<int64_t>(chunks, 1);
     ctx->inj_blocks = (int)std::min<int64_t>((max_side + 255) / 256, 64);
     duwp_status s = alloc_all(ctx);
     if (s == DUWP_OK) s = upload_initial(ctx);

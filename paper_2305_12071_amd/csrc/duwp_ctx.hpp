@@ -46,6 +46,10 @@ struct duwp_ctx {
     int32_t *k_dest = nullptr;
     int64_t *k_n = nullptr;        // [ncases*2] candidates per side
     int64_t cand_total = 0;
+    int32_t *k_chunk = nullptr;    // entrants per candidate chunk
+    int64_t chunk_total = 0;
+    int32_t *hist_buf[2] = {nullptr, nullptr};   // destination histograms, by step parity
+    int32_t *fix_buf[2] = {nullptr, nullptr};    // recount flags, by step parity
     int inj_blocks = 0;            // x-blocks of the candidate kernel
     int64_t *off[2] = {nullptr, nullptr};
     int64_t *ibase = nullptr;

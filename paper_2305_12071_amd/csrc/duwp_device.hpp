@@ -24,6 +24,7 @@ struct DCase {
     uint32_t key0, key1;
     int64_t inj_base, inj_cap;       // slot range of this case's entrants in the injection buffer
     int64_t cand_base[2], cand_cap[2];  // injection candidate slots per side
+    int64_t chunk_base[2];              // per-side entrant counts of 256-slot candidate chunks
     double x_lo, x_hi, dx, dt;
     double R, omega, T_ref, mu_ref, coll_k, ups, c_ref;
     double m_p, fac;                 // fac = m_p / dx
@@ -44,7 +45,10 @@ struct Cells {
     int64_t *seg;       // [G] start of the cell's intermediate segment
     int32_t *seg_stg;   // [G] 1: segment in the staging buffer, 0: in place in the canonical buffer
     int32_t *d_abs, *d_new, *d_cand, *d_coll;  // [G] diagnostics
-    int32_t *hist;      // [G*NBIN] destination histogram, then scatter bases
+    int32_t *hist;      // [G*NBIN] destination histogram of this step, then scatter bases
+    int32_t *hist_nx;   // [G*NBIN] histogram predicted for the next step
+    int32_t *fix;       // [G] 1: this step's histogram of the cell must be recounted
+    int32_t *fix_nx;    // [G] same, for the next step
     int32_t *cnt_new;   // [G]
     int32_t *inj_cnt;   // [G] injected entrants per destination cell
     int64_t *inj_start; // [G] first slot of the injected entrants of each destination cell
@@ -64,6 +68,7 @@ struct Inj {
     T *cx, *cu, *cv, *cw;
     int32_t *cdest;     // local destination of a candidate, -1 if it does not enter
     int64_t *ncand;     // [ncases*2] candidates generated per side
+    int32_t *cchunk;    // entrants per 256-slot candidate chunk (entrants compacted to the chunk front)
 };
 
 template <typename T>

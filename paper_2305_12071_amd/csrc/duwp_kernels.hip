@@ -19,7 +19,7 @@
 //   collide          NTC/VHS (Appendix A), one wave per cell, candidates in
 //                    order with conflict-free rounds
 //   inject_gen/rank  reservoir entrants
-//   stream_hist      free flight + boundaries, destination histogram
+//   hist_fix         recount of the destination histograms of flagged cells
 //   count/scan/bases windowed stable counting-sort offsets
 //   scatter          free flight again, stable scatter into the next canonical
 //                    array, particle moment sums per destination
@@ -45,7 +45,7 @@ constexpr int NBI = 2 * (KWIN + 1);    // injection destination window (both end
 // ---------------------------------------------------------------------------
 // 1. Cell state at step start, absorbed and resampled counts
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ cases, Cells cl,
+__global__ void __launch_bounds__(512) k_cellstate(const DCase *__restrict__ cases, Cells cl,
                                                     const int64_t *__restrict__ off,
                                                     const uint32_t *__restrict__ d_step, int G,
                                                     int32_t *err, int64_t *d_nout, int64_t *d_ninj)
@@ -88,7 +88,9 @@ __global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ ca
             if (nf > 2.0e9) { if (threadIdx.x == 0) atomicOr(err, ERR_CAPACITY); nf = 0.0; }
             nnew = (int32_t)nf;
         }
+        for (int t = threadIdx.x; t < NBIN; t += blockDim.x) cl.hist_nx[(int64_t)g * NBIN + t] = 0;
         if (threadIdx.x == 0) {
+            cl.fix_nx[g] = 0;
 #pragma unroll
             for (int i = 0; i < 5; ++i) cl.wt[(int64_t)g * 5 + i] = W[i];
             cl.pc[g] = P;
@@ -122,6 +124,19 @@ static void enqueue_scan(duwp_ctx *ctx, const int32_t *in, int64_t *out, int64_t
                        ctx->scan_part, out, ctx->cap, total, ctx->d_err);
 }
 
+// Destination bin (d + KWIN) of a particle of local cell lc after free flight;
+// -1 when it leaves through a reservoir (or moves farther than the window,
+// then *far is set).
+template <typename T>
+__device__ __forceinline__ int flight_bin(const DCase &c, int lc, T x, T u, bool *far)
+{
+    const int dest = Flight<T>::go(c, lc, x, u);
+    if (dest < 0) return -1;
+    const int d = dest - lc;
+    if (d < -KWIN || d > KWIN) { *far = true; return -1; }
+    return d + KWIN;
+}
+
 // Cell segment of the intermediate array: staging buffer or in place.
 template <typename T>
 __device__ __forceinline__ Soa<T> segment(const Cells &cl, int g, const Soa<T> &src, const Soa<T> &stg,
@@ -136,7 +151,7 @@ __device__ __forceinline__ Soa<T> segment(const Cells &cl, int g, const Soa<T> &
 // that absorb or resample anything; every cell records where its segment is.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(1024) k_absorb_resample(const DCase *__restrict__ cases, Cells cl,
+__global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict__ cases, Cells cl,
                                                           Soa<T> src, const int64_t *__restrict__ off,
                                                           Soa<T> stg, const int64_t *__restrict__ sbase,
                                                           const uint32_t *__restrict__ d_step, int G,
@@ -144,6 +159,7 @@ __global__ void __launch_bounds__(1024) k_absorb_resample(const DCase *__restric
 {
     __shared__ double red[5 * 16];
     __shared__ int scr[16];
+    __shared__ int dh[NBIN];
     const uint32_t step = *d_step;
     for (int g = blockIdx.x; g < G; g += gridDim.x) {
         const int touched = cl.seg_stg[g];
@@ -162,6 +178,10 @@ __global__ void __launch_bounds__(1024) k_absorb_resample(const DCase *__restric
         const int32_t nsurv = cl.n_surv[g];
         double sa[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         int64_t written = 0;
+        // the cell's destination histogram loses the absorbed and gains the resampled particles
+        for (int t = threadIdx.x; t < NBIN; t += blockDim.x) dh[t] = 0;
+        bool far = false;
+        __syncthreads();
         if (P > 0.0) {
             for (int64_t k0 = b; k0 < e; k0 += blockDim.x) {
                 const int64_t kk = k0 + threadIdx.x;
@@ -178,6 +198,9 @@ __global__ void __launch_bounds__(1024) k_absorb_resample(const DCase *__restric
                     double du = u, dv = v, dw = w;
                     sa[0] += 1.0; sa[1] += du; sa[2] += dv; sa[3] += dw;
                     sa[4] += 0.5 * (du * du + dv * dv + dw * dw);
+                    bool f2 = false;
+                    const int hb = flight_bin<T>(c, lc, x, u, &f2);
+                    if (hb >= 0) atomicSub(&dh[hb], 1);
                 }
                 int tot;
                 const bool keep = valid && !absorbed;
@@ -216,6 +239,8 @@ __global__ void __launch_bounds__(1024) k_absorb_resample(const DCase *__restric
                     if (px >= 1.0f) px = 0.99999994f;
                 }
                 T pu = (T)xi[0], pv = (T)xi[1], pw = (T)xi[2];
+                const int hb = flight_bin<T>(c, lc, px, pu, &far);
+                if (hb >= 0) atomicAdd(&dh[hb], 1);
                 int64_t d = ob + nsurv + q;
                 if (d < cap) { stg.x[d] = px; stg.u[d] = pu; stg.v[d] = pv; stg.w[d] = pw; }
                 else atomicOr(err, ERR_CAPACITY);
@@ -226,7 +251,11 @@ __global__ void __launch_bounds__(1024) k_absorb_resample(const DCase *__restric
             }
             block_sum<5>(ss, red);
         }
+        far = __syncthreads_or(far);
+        for (int t = threadIdx.x; t < NBIN; t += blockDim.x)
+            if (dh[t]) cl.hist[(int64_t)g * NBIN + t] += dh[t];
         if (threadIdx.x == 0) {
+            if (far) cl.fix[g] = 1;
             const int32_t nabs = (int32_t)(e - b) - nsurv;
             if (nabs > 0)
 #pragma unroll
@@ -267,6 +296,7 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
         int ncoll = 0;
         double seen = 0.0;
         double cm = 0.0;
+        bool far = false;
         if (cl.okc[g] && N >= 2 && sb + N <= cap) {
             const double P = cl.pc[g];
             const double dtc = c.full_dt ? c.dt : (1.0 - P) * c.dt;
@@ -279,6 +309,8 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
             M = (int64_t)Mf;
             const double aexp = 1.0 - 2.0 * c.ups;
             T *su = sg.u + sb, *sv = sg.v + sb, *sw = sg.w + sb;
+            const T *sx = sg.x + sb;
+            int32_t *hg = cl.hist + (int64_t)g * NBIN;
             for (int64_t q0 = 0; q0 < M; q0 += WAVE) {
                 const int64_t q = q0 + lane;
                 const bool act = q < M;
@@ -307,7 +339,23 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
                 while (done != ~0ull) {
                     const bool ready = act && !((done >> lane) & 1ull) && ((dep & ~done) == 0ull);
                     if (ready) {
-                        if (collide_pair<T>(su, sv, sw, i, j, cm, aexp, u2, u3, u4, seen)) ++ncoll;
+                        const T ui0 = su[i], uj0 = su[j];
+                        if (collide_pair<T>(su, sv, sw, i, j, cm, aexp, u2, u3, u4, seen)) {
+                            ++ncoll;
+                            // move the pair between destination bins of this step's histogram
+                            const T xi = sx[i], xj = sx[j], ui1 = su[i], uj1 = su[j];
+                            bool f0 = false;
+                            const int a0 = flight_bin<T>(c, lc, xi, ui0, &f0), a1 = flight_bin<T>(c, lc, xi, ui1, &far);
+                            const int b0 = flight_bin<T>(c, lc, xj, uj0, &f0), b1 = flight_bin<T>(c, lc, xj, uj1, &far);
+                            if (a0 != a1) {
+                                if (a0 >= 0) atomicSub(&hg[a0], 1);
+                                if (a1 >= 0) atomicAdd(&hg[a1], 1);
+                            }
+                            if (b0 != b1) {
+                                if (b0 >= 0) atomicSub(&hg[b0], 1);
+                                if (b1 >= 0) atomicAdd(&hg[b1], 1);
+                            }
+                        }
                     }
                     // this round's stores are complete before the next round loads
                     __threadfence_block();
@@ -317,7 +365,9 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
         }
         seen = wave_max(seen);
         ncoll = wave_sum_i(ncoll);
+        const bool anyfar = __ballot(far) != 0ull;
         if (lane == 0) {
+            if (anyfar) cl.fix[g] = 1;
             cl.d_cand[g] = (int32_t)M;
             cl.d_coll[g] = ncoll;
             if (seen > cm && M > 0) cl.cr_max[g] = seen;
@@ -356,33 +406,45 @@ __global__ void __launch_bounds__(256) k_inject_gen(const DCase *__restrict__ ca
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) inj.ncand[blockIdx.y] = ng;
     const int64_t cb = c.cand_base[side];
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < ng; q += (int64_t)gridDim.x * blockDim.x) {
-        U4 a = draw(c, step, (uint32_t)side, (uint32_t)q, TAG_IVEL, 0);
-        U4 bb = draw(c, step, (uint32_t)side, (uint32_t)q, TAG_IVEL, 1);
-        double uu[6] = {u01(a.b), u01(a.c), u01(a.d), u01(bb.a), u01(bb.b), u01(bb.c)};
-        double xi[3];
-        maxwell(U, 0.0, 0.0, Ts, c.R, uu, xi);
-        int dest;
-        T px, pu;
-        if constexpr (std::is_same<T, double>::value) {
-            double x = side == 0 ? c.x_lo - u01(a.a) * Lg : c.x_hi + u01(a.a) * Lg;
-            double u = xi[0];
-            x = x + u * c.dt;
-            dest = bc_cell_abs(c, x, u);
-            px = x; pu = u;
-        } else {
-            float u = (float)xi[0];
-            const float lgc = (float)(Lg / c.dx);
-            const float X0 = side == 0 ? -(float)u01(a.a) * lgc : (float)u01(a.a) * lgc;
-            const float X = X0 + u * c.dtdx_f;
-            const float fl = floorf(X);
-            float s = 0.0f;
-            dest = (fabsf(X) < 1.0e9f) ? bc_cell_rel(c, (side == 0 ? 0 : c.ncells) + (int)fl, X - fl, u, s) : -1;
-            px = s; pu = u;
+    __shared__ int scr[16];
+    // 256-slot chunks; the entrants of a chunk are compacted, in slot order, to its front
+    for (int64_t ci = blockIdx.x; ci * 256 < ng; ci += gridDim.x) {
+        const int64_t q = ci * 256 + threadIdx.x;
+        int dest = -1;
+        T px = 0, pu = 0, pv = 0, pw = 0;
+        if (q < ng) {
+            U4 a = draw(c, step, (uint32_t)side, (uint32_t)q, TAG_IVEL, 0);
+            U4 bb = draw(c, step, (uint32_t)side, (uint32_t)q, TAG_IVEL, 1);
+            double uu[6] = {u01(a.b), u01(a.c), u01(a.d), u01(bb.a), u01(bb.b), u01(bb.c)};
+            double xi[3];
+            maxwell(U, 0.0, 0.0, Ts, c.R, uu, xi);
+            if constexpr (std::is_same<T, double>::value) {
+                double x = side == 0 ? c.x_lo - u01(a.a) * Lg : c.x_hi + u01(a.a) * Lg;
+                double u = xi[0];
+                x = x + u * c.dt;
+                dest = bc_cell_abs(c, x, u);
+                px = x; pu = u;
+            } else {
+                float u = (float)xi[0];
+                const float lgc = (float)(Lg / c.dx);
+                const float X0 = side == 0 ? -(float)u01(a.a) * lgc : (float)u01(a.a) * lgc;
+                const float X = X0 + u * c.dtdx_f;
+                const float fl = floorf(X);
+                float s = 0.0f;
+                dest = (fabsf(X) < 1.0e9f) ? bc_cell_rel(c, (side == 0 ? 0 : c.ncells) + (int)fl, X - fl, u, s) : -1;
+                px = s; pu = u;
+            }
+            pv = (T)xi[1]; pw = (T)xi[2];
         }
-        const int64_t sl = cb + q;
-        inj.cx[sl] = px; inj.cu[sl] = pu; inj.cv[sl] = (T)xi[1]; inj.cw[sl] = (T)xi[2];
-        inj.cdest[sl] = dest;
+        const bool ent = dest >= 0;
+        int tot;
+        const int pre = block_flag_prefix(ent, scr, &tot);
+        if (ent) {
+            const int64_t sl = cb + ci * 256 + pre;
+            inj.cx[sl] = px; inj.cu[sl] = pu; inj.cv[sl] = pv; inj.cw[sl] = pw;
+            inj.cdest[sl] = dest;
+        }
+        if (threadIdx.x == 0) inj.cchunk[c.chunk_base[side] + ci] = tot;
     }
 }
 
@@ -436,17 +498,21 @@ __device__ __forceinline__ int block_stable_rank(int key, int *binbase, int (*wc
 }
 
 // 5b. One block per case: entrants in (side, slot) order, with their rank among
-// entrants of the same destination cell.
+// entrants of the same destination cell.  Only the compacted entrants of each
+// candidate chunk are visited: a prefix over the chunk counts maps the e-th
+// entrant of a side to its chunk.
 template <typename T>
 __global__ void __launch_bounds__(256) k_inject_rank(const DCase *__restrict__ cases, Cells cl, Inj<T> inj,
                                                      int64_t *d_ninj, int32_t *err)
 {
+    constexpr int MAXCH = 2048;
     __shared__ int binbase[NBI];
     __shared__ int wcnt[16][NBI];
-    __shared__ int scr[16];
+    __shared__ int pref[MAXCH + 1];
     const int k = blockIdx.x;
     const DCase &c = cases[k];
     const int C = c.ncells;
+    const int lane = lane_id();
     for (int t = threadIdx.x; t < NBI; t += blockDim.x) binbase[t] = 0;
     for (int t = threadIdx.x; t < 16 * NBI; t += blockDim.x) (&wcnt[0][0])[t] = 0;
     __syncthreads();
@@ -454,33 +520,61 @@ __global__ void __launch_bounds__(256) k_inject_rank(const DCase *__restrict__ c
     for (int side = 0; side < 2; ++side) {
         const int64_t n = inj.ncand[2 * k + side];
         const int64_t cb = c.cand_base[side];
+        const int64_t nch = (n + 255) / 256;
         int64_t nside = 0;
-        for (int64_t i0 = 0; i0 < n; i0 += blockDim.x) {
-            const int64_t i = i0 + threadIdx.x;
-            const int d = (i < n) ? inj.cdest[cb + i] : -1;
-            int slot = -1;
-            if (d >= 0) {
-                slot = inj_slot(d, C);
-                if (slot < 0) atomicOr(err, ERR_RANGE);
+        for (int64_t ch0 = 0; ch0 < nch; ch0 += MAXCH) {
+            const int nb = (int)min((int64_t)MAXCH, nch - ch0);
+            // exclusive prefix of the chunk counts (first wave)
+            if (threadIdx.x < WAVE) {
+                int carry = 0;
+                for (int i0 = 0; i0 < nb; i0 += WAVE) {
+                    const int i = i0 + lane;
+                    const int v = i < nb ? inj.cchunk[c.chunk_base[side] + ch0 + i] : 0;
+                    int incl = v;
+#pragma unroll
+                    for (int o = 1; o < WAVE; o <<= 1) {
+                        const int t = __shfl_up(incl, o, WAVE);
+                        if (lane >= o) incl += t;
+                    }
+                    if (i < nb) pref[i] = carry + incl - v;
+                    carry += __shfl(incl, WAVE - 1, WAVE);
+                }
+                if (lane == 0) pref[nb] = carry;
             }
-            const bool ent = slot >= 0;
-            int tot;
-            const int pre = block_flag_prefix(ent, scr, &tot);
-            const int r = block_stable_rank<NBI>(slot, binbase, wcnt);
-            if (ent) {
-                const int64_t pos = count + pre;
-                if (pos < c.inj_cap) {
-                    const int64_t sl = c.inj_base + pos;
-                    inj.x[sl] = inj.cx[cb + i]; inj.u[sl] = inj.cu[cb + i];
-                    inj.v[sl] = inj.cv[cb + i]; inj.w[sl] = inj.cw[cb + i];
-                    inj.dest[sl] = c.cell_base + d;
-                    inj.rank[sl] = r;
-                } else {
-                    atomicOr(err, ERR_CAPACITY);
+            __syncthreads();
+            const int E = pref[nb];
+            for (int e0 = 0; e0 < E; e0 += blockDim.x) {
+                const int e = e0 + threadIdx.x;
+                int slot = -1, d = -1;
+                int64_t slc = 0;
+                if (e < E) {
+                    int lo = 0, hi = nb - 1;          // last chunk with pref <= e
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (pref[mid] <= e) lo = mid; else hi = mid - 1;
+                    }
+                    slc = cb + (ch0 + lo) * 256 + (e - pref[lo]);
+                    d = inj.cdest[slc];
+                    slot = inj_slot(d, C);
+                    if (slot < 0) atomicOr(err, ERR_RANGE);
+                }
+                const int r = block_stable_rank<NBI>(slot, binbase, wcnt);
+                if (slot >= 0) {
+                    const int64_t pos = count + e;
+                    if (pos < c.inj_cap) {
+                        const int64_t sl = c.inj_base + pos;
+                        inj.x[sl] = inj.cx[slc]; inj.u[sl] = inj.cu[slc];
+                        inj.v[sl] = inj.cv[slc]; inj.w[sl] = inj.cw[slc];
+                        inj.dest[sl] = c.cell_base + d;
+                        inj.rank[sl] = r;
+                    } else {
+                        atomicOr(err, ERR_CAPACITY);
+                    }
                 }
             }
-            count += tot;
-            nside += tot;
+            count += E;
+            nside += E;
+            __syncthreads();
         }
         if (threadIdx.x == 0) d_ninj[2 * k + side] = nside;
     }
@@ -495,23 +589,33 @@ __global__ void __launch_bounds__(256) k_inject_rank(const DCase *__restrict__ c
 // 6. Free flight of the intermediate particles: destination histogram per source cell
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(1024) k_stream_hist(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
-                                                      Soa<T> stg, int G, int64_t cap, int32_t *err,
-                                                      int64_t *d_nout)
+__global__ void __launch_bounds__(512) k_hist_build(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
+                                                     Soa<T> stg, const int64_t *__restrict__ off, int G,
+                                                     int64_t cap, int all)
 {
+    // Recount of the destination histogram of a cell from its particles: every
+    // cell of a loaded canonical state (all = 1), or the intermediate segments
+    // of the cells flagged during the step (all = 0).
     constexpr int IT = 4;
     __shared__ int h[NBIN];
-    __shared__ int nout;
     for (int g = blockIdx.x; g < G; g += gridDim.x) {
-        const int k = cl.cell_case[g];
-        const DCase &c = cases[k];
+        if (!all && !cl.fix[g]) continue;
+        const DCase &c = cases[cl.cell_case[g]];
         const int lc = g - c.cell_base;
         for (int t = threadIdx.x; t < NBIN; t += blockDim.x) h[t] = 0;
-        if (threadIdx.x == 0) nout = 0;
         __syncthreads();
         int64_t b;
-        const Soa<T> sg = segment(cl, g, src, stg, b);
-        const int32_t n = (int32_t)min((int64_t)cl.n_int[g], cap - b);
+        Soa<T> sg;
+        int32_t n;
+        if (all) {
+            sg = src;
+            b = off[g];
+            n = (int32_t)(off[g + 1] - b);
+        } else {
+            sg = segment(cl, g, src, stg, b);
+            n = (int32_t)min((int64_t)cl.n_int[g], cap - b);
+        }
+        bool far = false;
         for (int i0 = 0; i0 < n; i0 += IT * blockDim.x) {
             T x[IT], u[IT];
 #pragma unroll
@@ -524,19 +628,13 @@ __global__ void __launch_bounds__(1024) k_stream_hist(const DCase *__restrict__ 
             for (int j = 0; j < IT; ++j) {
                 const int i = i0 + j * blockDim.x + threadIdx.x;
                 if (i >= n) continue;
-                const int dest = Flight<T>::go(c, lc, x[j], u[j]);
-                if (dest < 0) {
-                    atomicAdd(&nout, 1);
-                } else {
-                    const int d = dest - lc;
-                    if (d < -KWIN || d > KWIN) atomicOr(err, ERR_RANGE);
-                    else atomicAdd(&h[d + KWIN], 1);
-                }
+                const int hb = flight_bin<T>(c, lc, x[j], u[j], &far);
+                if (hb >= 0) atomicAdd(&h[hb], 1);
             }
         }
         __syncthreads();
         for (int t = threadIdx.x; t < NBIN; t += blockDim.x) cl.hist[(int64_t)g * NBIN + t] = h[t];
-        if (threadIdx.x == 0 && nout) atomicAdd((unsigned long long *)&d_nout[k], (unsigned long long)nout);
+        if (threadIdx.x == 0) cl.fix[g] = 0;
         __syncthreads();
     }
 }
@@ -585,10 +683,14 @@ __device__ __forceinline__ void add_phi(double (&a)[5], double u, double v, doub
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024) k_scatter(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
+__global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
                                                   Soa<T> stg, Soa<T> dst, const int64_t *__restrict__ off_new,
-                                                  int G, int64_t cap)
+                                                  int G, int64_t cap, int32_t *err, int64_t *d_nout)
 {
+    // Besides placing each particle, the scatter predicts where it goes next
+    // step (free flight from its new place with its current velocity) and
+    // counts the next step's destination histogram of its new cell in hn[]
+    // (new cell relative to this one, next destination), flushed per cell.
     // Each chunk holds IT*blockDim particles; wave w takes the contiguous
     // range of IT*64 particles at w*IT*64, lane l its items l, l+64, ...  Ranks
     // inside a wave come from ballots; the waves' counts are combined once per chunk.
@@ -597,7 +699,11 @@ __global__ void __launch_bounds__(1024) k_scatter(const DCase *__restrict__ case
     __shared__ int bin0[NBIN];
     __shared__ int wcnt[16][NBIN];
     __shared__ double red[NMB * 5 * 16];
+    __shared__ int hn[NBIN * NBIN];
+    __shared__ int nout;
     const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int t = threadIdx.x; t < NBIN * NBIN; t += blockDim.x) hn[t] = 0;
+    if (threadIdx.x == 0) nout = 0;
     for (int g = blockIdx.x; g < G; g += gridDim.x) {
         const int k = cl.cell_case[g];
         const DCase &c = cases[k];
@@ -625,6 +731,7 @@ __global__ void __launch_bounds__(1024) k_scatter(const DCase *__restrict__ case
                 x[j] = 0; u[j] = 0; v[j] = 0; ww[j] = 0;
                 if (i < n) { x[j] = sg.x[b + i]; u[j] = sg.u[b + i]; v[j] = sg.v[b + i]; ww[j] = sg.w[b + i]; }
             }
+            int gone = 0;
 #pragma unroll
             for (int j = 0; j < IT; ++j) {
                 const int i = wbase + j * WAVE + lane;
@@ -634,9 +741,29 @@ __global__ void __launch_bounds__(1024) k_scatter(const DCase *__restrict__ case
                     if (dest >= 0) {
                         const int d = dest - lc;
                         if (d >= -KWIN && d <= KWIN) key[j] = d + KWIN;
+                        else atomicOr(err, ERR_RANGE);
+                    } else {
+                        ++gone;
                     }
                 }
+                // next step's destination of the particle from its new place
+                int key2 = -1;
+                if (key[j] >= 0) {
+                    bool farp = false;
+                    const int hb = flight_bin<T>(c, lc + key[j] - KWIN, x[j], u[j], &farp);
+                    if (hb >= 0) key2 = key[j] * NBIN + hb;
+                    if (farp) cl.fix_nx[g + key[j] - KWIN] = 1;
+                }
+                uint64_t rem2 = __ballot(key2 >= 0);
+                while (rem2) {
+                    const int leader = __ffsll((unsigned long long)rem2) - 1;
+                    const int v0 = __builtin_amdgcn_readlane(key2, leader);
+                    const uint64_t mm = __ballot(key2 == v0);
+                    if (lane == leader) atomicAdd(&hn[v0], __popcll(mm));
+                    rem2 &= ~mm;
+                }
             }
+            if (gone) atomicAdd(&nout, gone);
             // wave-level stable ranks, items in order; wcnt[w][] counts this wave's chunk
 #pragma unroll
             for (int j = 0; j < IT; ++j) {
@@ -684,9 +811,21 @@ __global__ void __launch_bounds__(1024) k_scatter(const DCase *__restrict__ case
         }
         block_sum<NMB * 5>(mb, red);
         const bool any_far = __syncthreads_or(far);
-        double *mp = cl.mpart + (int64_t)g * NBIN * 5;
+        for (int t = threadIdx.x; t < NBIN * NBIN; t += blockDim.x) {
+            const int v0 = hn[t];
+            if (v0) {
+                atomicAdd(&cl.hist_nx[(int64_t)(g + t / NBIN - KWIN) * NBIN + t % NBIN], v0);
+                hn[t] = 0;
+            }
+        }
+        if (threadIdx.x == 0 && nout) {
+            atomicAdd((unsigned long long *)&d_nout[k], (unsigned long long)nout);
+            nout = 0;
+        }
+        // moment sums stored by destination: row d = g + dd, slot KWIN - dd
         for (int t = threadIdx.x; t < NBIN * 5; t += blockDim.x) {
             const int bin = t / 5, comp = t % 5, dd = bin - KWIN;
+            if (g + dd < 0 || g + dd >= G) continue;
             double val = 0.0;
 #pragma unroll
             for (int m = 0; m < NMB; ++m)
@@ -695,7 +834,7 @@ __global__ void __launch_bounds__(1024) k_scatter(const DCase *__restrict__ case
                     for (int q = 0; q < 5; ++q)
                         if (comp == q) val = mb[m * 5 + q];
                 }
-            mp[t] = val;
+            cl.mpart[((int64_t)(g + dd) * NBIN + (KWIN - dd)) * 5 + comp] = val;
         }
         if (any_far) {
             // a second pass per farther destination that received particles
@@ -714,7 +853,7 @@ __global__ void __launch_bounds__(1024) k_scatter(const DCase *__restrict__ case
 #pragma unroll
                     for (int q = 0; q < 5; ++q)
                         if ((int)threadIdx.x == q) val = a[q];
-                    mp[bin * 5 + threadIdx.x] = val;
+                    cl.mpart[((int64_t)(g + dd) * NBIN + (KWIN - dd)) * 5 + threadIdx.x] = val;
                 }
             }
         }
@@ -734,7 +873,12 @@ __global__ void __launch_bounds__(256) k_scatter_inj(const DCase *__restrict__ c
         const int64_t sl = c.inj_base + i;
         const int d = inj.dest[sl];
         const int64_t pos = cl.inj_start[d] + inj.rank[sl];
-        if (pos < cap) { dst.x[pos] = inj.x[sl]; dst.u[pos] = inj.u[sl]; dst.v[pos] = inj.v[sl]; dst.w[pos] = inj.w[sl]; }
+        const T x = inj.x[sl], u = inj.u[sl];
+        if (pos < cap) { dst.x[pos] = x; dst.u[pos] = u; dst.v[pos] = inj.v[sl]; dst.w[pos] = inj.w[sl]; }
+        bool farp = false;
+        const int hb = flight_bin<T>(c, d - c.cell_base, x, u, &farp);
+        if (hb >= 0) atomicAdd(&cl.hist_nx[(int64_t)d * NBIN + hb], 1);
+        if (farp) cl.fix_nx[d] = 1;
     }
 }
 
@@ -765,33 +909,42 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict__ cases, Cells cl, Soa<T> dst,
                                                         const int64_t *__restrict__ off_new, int G, int32_t *err)
 {
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    // one wave per destination cell: lane l holds the sums of source cell d + l - KWIN
+    const int lane = lane_id();
+    const int d = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (d >= G) return;
     const DCase &c = cases[cl.cell_case[d]];
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int src = d - KWIN; src <= d + KWIN; ++src) {
-        if (src < 0 || src >= G) continue;
-        const double *mp = cl.mpart + ((int64_t)src * NBIN + (d - src) + KWIN) * 5;
+    if (lane < NBIN) {
+        const int src = d + lane - KWIN;
+        if (src >= 0 && src < G) {
+            const double *mp = cl.mpart + ((int64_t)d * NBIN + lane) * 5;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) s[q] += mp[q];
+            for (int q = 0; q < 5; ++q) s[q] = mp[q];
+        }
     }
-    for (int64_t kk = cl.inj_start[d]; kk < off_new[d + 1]; ++kk)
-        add_phi(s, (double)dst.u[kk], (double)dst.v[kk], (double)dst.w[kk]);
-    bool bad = false;
+    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t kk = cl.inj_start[d] + lane; kk < off_new[d + 1]; kk += WAVE)
+        add_phi(a, (double)dst.u[kk], (double)dst.v[kk], (double)dst.w[kk]);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        const double p = c.fac * s[q];
-        cl.psi_p[(int64_t)d * 5 + q] = p;
-        const double t = cl.psi_w[(int64_t)d * 5 + q] + p;
-        if (!isfinite(t)) bad = true;
-        cl.avg[(int64_t)d * 5 + q] += t;
+    for (int q = 0; q < 5; ++q) s[q] = wave_sum(s[q]) + wave_sum(a[q]);
+    if (lane == 0) {
+        bool bad = false;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const double p = c.fac * s[q];
+            cl.psi_p[(int64_t)d * 5 + q] = p;
+            const double t = cl.psi_w[(int64_t)d * 5 + q] + p;
+            if (!isfinite(t)) bad = true;
+            cl.avg[(int64_t)d * 5 + q] += t;
+        }
+        if (bad) atomicOr(err, ERR_STATE);
     }
-    if (bad) atomicOr(err, ERR_STATE);
 }
 
 // Particle moments recomputed from a canonical array (after a state is loaded).
 template <typename T>
-__global__ void __launch_bounds__(1024) k_moments(const DCase *__restrict__ cases, Cells cl, Soa<T> a,
+__global__ void __launch_bounds__(512) k_moments(const DCase *__restrict__ cases, Cells cl, Soa<T> a,
                                                   const int64_t *__restrict__ off, int G, int32_t *err)
 {
     __shared__ double red[5 * 16];
@@ -861,11 +1014,16 @@ static void step_impl(duwp_ctx *ctx)
     const Soa<T> src = soa<T>(ctx->A[p]), dst = soa<T>(ctx->A[p ^ 1]), stg = soa<T>(ctx->S);
     const Inj<T> inj{(T *)ctx->J[0], (T *)ctx->J[1], (T *)ctx->J[2], (T *)ctx->J[3], ctx->j_dest, ctx->j_rank,
                      ctx->j_count, (T *)ctx->K[0], (T *)ctx->K[1], (T *)ctx->K[2], (T *)ctx->K[3], ctx->k_dest,
-                     ctx->k_n};
+                     ctx->k_n, ctx->k_chunk};
     const int gthreads = (G + 255) / 256;
+    Cells cl = ctx->cl;
+    cl.hist = ctx->hist_buf[p];
+    cl.hist_nx = ctx->hist_buf[p ^ 1];
+    cl.fix = ctx->fix_buf[p];
+    cl.fix_nx = ctx->fix_buf[p ^ 1];
     {
         Mark m(ctx, "cellstate");
-        hipLaunchKernelGGL(k_cellstate, dim3(G), dim3(bc), 0, st, ctx->d_cases, ctx->cl, ctx->off[p],
+        hipLaunchKernelGGL(k_cellstate, dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, ctx->off[p],
                            ctx->d_step, G, ctx->d_err, ctx->d_nout, ctx->d_ninj);
     }
     {
@@ -874,31 +1032,31 @@ static void step_impl(duwp_ctx *ctx)
     }
     {
         Mark m(ctx, "absorb_resample");
-        hipLaunchKernelGGL(k_absorb_resample<T>, dim3(G), dim3(bc), 0, st, ctx->d_cases, ctx->cl, src,
+        hipLaunchKernelGGL(k_absorb_resample<T>, dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src,
                            ctx->off[p], stg, ctx->ibase, ctx->d_step, G, ctx->cap, ctx->d_err);
     }
     {
         Mark m(ctx, "collide");
         const int wpb = 4;
         hipLaunchKernelGGL(k_collide<T>, dim3((G + wpb - 1) / wpb), dim3(64 * wpb), 0, st, ctx->d_cases,
-                           ctx->cl, src, stg, ctx->d_step, G, ctx->cap, ctx->d_err);
+                           cl, src, stg, ctx->d_step, G, ctx->cap, ctx->d_err);
+    }
+    {
+        Mark m(ctx, "hist_fix");
+        hipLaunchKernelGGL(k_hist_build<T>, dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg, ctx->off[p], G,
+                           ctx->cap, 0);
     }
     {
         Mark m(ctx, "inject");
         if (ctx->inj_blocks > 0)
             hipLaunchKernelGGL(k_inject_gen<T>, dim3(ctx->inj_blocks, 2 * ctx->ncases), dim3(256), 0, st,
                                ctx->d_cases, inj, ctx->d_step, ctx->d_err);
-        hipLaunchKernelGGL(k_inject_rank<T>, dim3(ctx->ncases), dim3(256), 0, st, ctx->d_cases, ctx->cl, inj,
+        hipLaunchKernelGGL(k_inject_rank<T>, dim3(ctx->ncases), dim3(256), 0, st, ctx->d_cases, cl, inj,
                            ctx->d_ninj, ctx->d_err);
     }
     {
-        Mark m(ctx, "stream_hist");
-        hipLaunchKernelGGL(k_stream_hist<T>, dim3(G), dim3(bc), 0, st, ctx->d_cases, ctx->cl, src, stg, G,
-                           ctx->cap, ctx->d_err, ctx->d_nout);
-    }
-    {
         Mark m(ctx, "count_new");
-        hipLaunchKernelGGL(k_count_new, dim3(gthreads), dim3(256), 0, st, ctx->cl, G);
+        hipLaunchKernelGGL(k_count_new, dim3(gthreads), dim3(256), 0, st, cl, G);
     }
     {
         Mark m(ctx, "scan_offsets");
@@ -906,25 +1064,25 @@ static void step_impl(duwp_ctx *ctx)
     }
     {
         Mark m(ctx, "bases");
-        hipLaunchKernelGGL(k_bases, dim3(gthreads), dim3(256), 0, st, ctx->cl, ctx->off[p ^ 1], G);
+        hipLaunchKernelGGL(k_bases, dim3(gthreads), dim3(256), 0, st, cl, ctx->off[p ^ 1], G);
     }
     {
         Mark m(ctx, "scatter");
-        hipLaunchKernelGGL(k_scatter<T>, dim3(G), dim3(bc), 0, st, ctx->d_cases, ctx->cl, src, stg, dst,
-                           ctx->off[p ^ 1], G, ctx->cap);
+        hipLaunchKernelGGL(k_scatter<T>, dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg, dst,
+                           ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout);
     }
     {
         Mark m(ctx, "scatter_inj");
-        hipLaunchKernelGGL(k_scatter_inj<T>, dim3(ctx->ncases), dim3(256), 0, st, ctx->d_cases, ctx->cl, inj,
+        hipLaunchKernelGGL(k_scatter_inj<T>, dim3(ctx->ncases), dim3(256), 0, st, ctx->d_cases, cl, inj,
                            dst, ctx->cap);
     }
     {
         Mark m(ctx, "wave");
-        hipLaunchKernelGGL(k_wave, dim3(gthreads), dim3(256), 0, st, ctx->d_cases, ctx->cl, G);
+        hipLaunchKernelGGL(k_wave, dim3(gthreads), dim3(256), 0, st, ctx->d_cases, cl, G);
     }
     {
         Mark m(ctx, "gather_moments");
-        hipLaunchKernelGGL(k_gather_moments<T>, dim3(gthreads), dim3(256), 0, st, ctx->d_cases, ctx->cl, dst,
+        hipLaunchKernelGGL(k_gather_moments<T>, dim3((G + 3) / 4), dim3(256), 0, st, ctx->d_cases, cl, dst,
                            ctx->off[p ^ 1], G, ctx->d_err);
     }
     {
@@ -939,15 +1097,32 @@ void enqueue_step(duwp_ctx *ctx)
     else step_impl<double>(ctx);
 }
 
+// Zero an int array (kernel, so it can sit in captured work too).
+__global__ void k_zero_i32(int32_t *a, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+
+template <typename T>
+static void reload_impl(duwp_ctx *ctx)
+{
+    const int p = ctx->step & 1, G = ctx->G;
+    Cells cl = ctx->cl;
+    cl.hist = ctx->hist_buf[p];
+    cl.fix = ctx->fix_buf[p];
+    const Soa<T> a = soa<T>(ctx->A[p]);
+    hipLaunchKernelGGL(k_moments<T>, dim3(G), dim3(ctx->block_cells), 0, ctx->stream, ctx->d_cases, cl, a,
+                       ctx->off[p], G, ctx->d_err);
+    hipLaunchKernelGGL(k_hist_build<T>, dim3(G), dim3(ctx->block_cells), 0, ctx->stream, ctx->d_cases, cl, a, a,
+                       ctx->off[p], G, ctx->cap, 1);
+}
+
+// Particle moments and destination histogram of a loaded canonical state.
 void enqueue_moments(duwp_ctx *ctx)
 {
-    const int p = ctx->step & 1;
-    if (ctx->precision == DUWP_MIXED)
-        hipLaunchKernelGGL(k_moments<float>, dim3(ctx->G), dim3(ctx->block_cells), 0, ctx->stream, ctx->d_cases,
-                           ctx->cl, soa<float>(ctx->A[p]), ctx->off[p], ctx->G, ctx->d_err);
-    else
-        hipLaunchKernelGGL(k_moments<double>, dim3(ctx->G), dim3(ctx->block_cells), 0, ctx->stream, ctx->d_cases,
-                           ctx->cl, soa<double>(ctx->A[p]), ctx->off[p], ctx->G, ctx->d_err);
+    if (ctx->precision == DUWP_MIXED) reload_impl<float>(ctx);
+    else reload_impl<double>(ctx);
 }
 
 }  // namespace duwp
