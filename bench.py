@@ -42,11 +42,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_path(case, precision, steps, warmup, graph, seed=1):
+def run_path(case, precision, steps, warmup, graph, seed=1, block_cells=0):
     from paper_2305_12071_amd import duwp
     import torch
 
-    sim = duwp.Sim(case, seed=seed, precision=precision, use_graph=graph)
+    sim = duwp.Sim(case, seed=seed, precision=precision, use_graph=graph, block_cells=block_cells)
     t = time.perf_counter()
     sim.step(warmup)
     log(f"  warmup {warmup} steps in {time.perf_counter() - t:.2f}s, N={sim.total_particles()}")
@@ -68,6 +68,7 @@ def main():
     ap.add_argument("--cells", type=int, default=4000)
     ap.add_argument("--particles", type=float, default=5e7)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--block-cells", type=int, default=0, help="threads per block of the per-cell kernels")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6)
@@ -99,7 +100,7 @@ def main():
     graph = not args.no_graph
 
     log(f"mixed FP32+FP64 path: {case.name}")
-    sim, ps, dt = run_path(case, duwp.MIXED, args.steps, args.warmup, graph)
+    sim, ps, dt = run_path(case, duwp.MIXED, args.steps, args.warmup, graph, block_cells=args.block_cells)
     value = ps / dt
     n_now = sim.total_particles()
     log(f"  {args.steps} steps in {dt:.3f}s -> {value:.4e} particle-steps/s")
@@ -145,7 +146,7 @@ def main():
     fp64 = None
     if not args.no_fp64:
         log("plain FP64 path")
-        s64, ps64, dt64 = run_path(case, duwp.FP64, args.steps, args.warmup, graph)
+        s64, ps64, dt64 = run_path(case, duwp.FP64, args.steps, args.warmup, graph, block_cells=args.block_cells)
         fp64 = ps64 / dt64
         log(f"  {args.steps} steps in {dt64:.3f}s -> {fp64:.4e} particle-steps/s")
         s64.close()

@@ -411,10 +411,12 @@ void orc_reset_average(orc_state *s)
 
 /* Apply the boundaries to a streamed particle.  Reservoir: leaving the
  * domain deletes it.  Specular wall: mirror position and normal velocity
- * until inside.  Returns 0 when deleted (or stuck after 1000 reflections). */
+ * until inside.  Returns 0 when deleted (or stuck after 1000 reflections,
+ * or with a position that is not a finite number). */
 static int apply_bc(const orc_case *c, double *x, double *u)
 {
     for (int it = 0; it < 1000; ++it) {
+        if (!isfinite(*x)) return 0;
         if (*x < c->x_lo) {
             if (c->bc_lo == 0) return 0;
             *x = 2.0 * c->x_lo - *x;

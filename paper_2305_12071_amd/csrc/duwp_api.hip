@@ -290,6 +290,9 @@ void duwp_destroy(duwp_ctx *ctx)
     for (hipEvent_t e : ctx->timer.ev) (void)hipEventDestroy(e);
     for (void *p : ctx->allocs) (void)hipFree(p);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->stream2) (void)hipStreamDestroy(ctx->stream2);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     delete ctx;
 }
 
@@ -315,6 +318,12 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
     ctx->seed = opts->seed;
     ctx->block_cells = opts->block_cells > 0 ? opts->block_cells : 256;
     if (ctx->block_cells % 64 || ctx->block_cells > 512) { delete ctx; return DUWP_EINVAL; }
+    if (hipStreamCreateWithFlags(&ctx->stream2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
+        duwp_destroy(ctx);
+        return DUWP_EDEVICE;
+    }
     const double head = opts->headroom > 0.0 ? opts->headroom : 1.5;
     int64_t G = 0, cap = 0, inj = 0, cand = 0, max_side = 0, chunks = 0;
     for (int k = 0; k < ncases; ++k) {

@@ -29,6 +29,8 @@ struct duwp_ctx {
     int block_cells = 256;
     hipStream_t stream = nullptr;
     bool own_stream = false;  // created by the library when the caller passed none
+    hipStream_t stream2 = nullptr;   // second stream for work independent of the collisions
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     uint64_t seed = 0;
     std::vector<duwp_case> cases;
     std::vector<duwp::DCase> hcases;

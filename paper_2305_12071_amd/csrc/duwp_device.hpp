@@ -132,6 +132,16 @@ __device__ __forceinline__ int wave_sum_i(int v)
     return v;
 }
 
+// Block barrier that orders LDS only: outstanding global loads (e.g. prefetches)
+// stay in flight across it.  Use where no global memory written before the
+// barrier is read by another thread after it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Deterministic block sum of N doubles per thread; the result is valid in every thread.
 // red must hold N * (blockDim/64) doubles.
 template <int N>

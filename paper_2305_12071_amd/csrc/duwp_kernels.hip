@@ -116,6 +116,11 @@ __global__ void __launch_bounds__(512) k_cellstate(const DCase *__restrict__ cas
 static void enqueue_scan(duwp_ctx *ctx, const int32_t *in, int64_t *out, int64_t *total)
 {
     const int G = ctx->G;
+    if (G <= SCAN1_MAX) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, ctx->stream, in, G, out, ctx->cap, total,
+                           ctx->d_err);
+        return;
+    }
     hipLaunchKernelGGL(k_scan_reduce, dim3(ctx->ntiles), dim3(SCAN_BLOCK), 0, ctx->stream, in, G,
                        ctx->scan_part);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, ctx->stream, ctx->scan_part,
@@ -639,35 +644,42 @@ __global__ void __launch_bounds__(512) k_hist_build(const DCase *__restrict__ ca
     }
 }
 
-// 7. particles arriving in each destination cell
-__global__ void k_count_new(Cells cl, int G)
+// 7. particles arriving in each destination cell (one wave per cell, lane = source offset)
+__global__ void __launch_bounds__(256) k_count_new(Cells cl, int G)
 {
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    const int d = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (d >= G) return;
-    int32_t s = cl.inj_cnt[d];
-#pragma unroll
-    for (int dl = -KWIN; dl <= KWIN; ++dl) {
-        const int src = d - dl;
-        if (src >= 0 && src < G) s += cl.hist[(int64_t)src * NBIN + dl + KWIN];
+    int v = 0;
+    if (lane < NBIN) {
+        const int src = d + lane - KWIN;                 // bin of src pointing at d: d - src + KWIN
+        if (src >= 0 && src < G) v = cl.hist[(int64_t)src * NBIN + (2 * KWIN - lane)];
     }
-    cl.cnt_new[d] = s;
+    v = wave_sum_i(v);
+    if (lane == 0) cl.cnt_new[d] = v + cl.inj_cnt[d];
 }
 
 // 9. start of each (source cell, destination) group inside its destination segment,
-// in source-cell order; entrants follow the cell-sourced particles.
-__global__ void k_bases(Cells cl, const int64_t *__restrict__ off_new, int G)
+// in source-cell order; entrants follow the cell-sourced particles.  One wave per
+// destination cell: lane l is source d + l - KWIN, an exclusive prefix gives the bases.
+__global__ void __launch_bounds__(256) k_bases(Cells cl, const int64_t *__restrict__ off_new, int G)
 {
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    const int d = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (d >= G) return;
-    int32_t run = 0;
-    for (int src = d - KWIN; src <= d + KWIN; ++src) {
-        if (src < 0 || src >= G) continue;
-        const int64_t idx = (int64_t)src * NBIN + (d - src) + KWIN;
-        const int32_t h = cl.hist[idx];
-        cl.hist[idx] = run;
-        run += h;
+    const int src = d + lane - KWIN;
+    const bool ok = lane < NBIN && src >= 0 && src < G;
+    const int64_t idx = (int64_t)src * NBIN + (2 * KWIN - lane);
+    const int h = ok ? cl.hist[idx] : 0;
+    int incl = h;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int t = __shfl_up(incl, o, WAVE);
+        if (lane >= o) incl += t;
     }
-    cl.inj_start[d] = off_new[d] + run;
+    if (ok) cl.hist[idx] = incl - h;
+    const int run = __shfl(incl, WAVE - 1, WAVE);
+    if (lane == 0) cl.inj_start[d] = off_new[d] + run;
 }
 
 // ---------------------------------------------------------------------------
@@ -684,19 +696,22 @@ __device__ __forceinline__ void add_phi(double (&a)[5], double u, double v, doub
 
 template <typename T>
 __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
-                                                  Soa<T> stg, Soa<T> dst, const int64_t *__restrict__ off_new,
-                                                  int G, int64_t cap, int32_t *err, int64_t *d_nout)
+                                                 Soa<T> stg, Soa<T> dst, const int64_t *__restrict__ off_new,
+                                                 int G, int64_t cap, int32_t *err, int64_t *d_nout)
 {
     // Besides placing each particle, the scatter predicts where it goes next
     // step (free flight from its new place with its current velocity) and
     // counts the next step's destination histogram of its new cell in hn[]
     // (new cell relative to this one, next destination), flushed per cell.
+    //
     // Each chunk holds IT*blockDim particles; wave w takes the contiguous
     // range of IT*64 particles at w*IT*64, lane l its items l, l+64, ...  Ranks
-    // inside a wave come from ballots; the waves' counts are combined once per chunk.
+    // inside a wave come from ballots; the waves' counts are combined once per
+    // chunk.  The next chunk is loaded while the current one is placed.
     constexpr int IT = 4;
     __shared__ int binbase[NBIN];
     __shared__ int bin0[NBIN];
+    __shared__ int64_t offb[NBIN];
     __shared__ int wcnt[16][NBIN];
     __shared__ double red[NMB * 5 * 16];
     __shared__ int hn[NBIN * NBIN];
@@ -711,6 +726,8 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
         for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
             binbase[t] = cl.hist[(int64_t)g * NBIN + t];
             bin0[t] = binbase[t];
+            const int d = g + t - KWIN;
+            offb[t] = (d >= 0 && d < G) ? off_new[d] : 0;
         }
         for (int t = threadIdx.x; t < 16 * NBIN; t += blockDim.x) (&wcnt[0][0])[t] = 0;
         __syncthreads();
@@ -721,16 +738,25 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
 #pragma unroll
         for (int i = 0; i < NMB * 5; ++i) mb[i] = 0.0;
         bool far = false;
-        for (int i0 = 0; i0 < n; i0 += IT * (int)blockDim.x) {
+        const int CH = IT * (int)blockDim.x;
+        T x[IT], u[IT], v[IT], ww[IT];
+#pragma unroll
+        for (int j = 0; j < IT; ++j) {
+            const int i = w * IT * WAVE + j * WAVE + lane;
+            x[j] = 0; u[j] = 0; v[j] = 0; ww[j] = 0;
+            if (i < n) { x[j] = sg.x[b + i]; u[j] = sg.u[b + i]; v[j] = sg.v[b + i]; ww[j] = sg.w[b + i]; }
+        }
+        for (int i0 = 0; i0 < n; i0 += CH) {
             const int wbase = i0 + w * IT * WAVE;
-            T x[IT], u[IT], v[IT], ww[IT];
-            int key[IT], rk[IT];
+            // prefetch the next chunk
+            T px[IT], pu[IT], pv[IT], pw[IT];
 #pragma unroll
             for (int j = 0; j < IT; ++j) {
-                const int i = wbase + j * WAVE + lane;
-                x[j] = 0; u[j] = 0; v[j] = 0; ww[j] = 0;
-                if (i < n) { x[j] = sg.x[b + i]; u[j] = sg.u[b + i]; v[j] = sg.v[b + i]; ww[j] = sg.w[b + i]; }
+                const int i = wbase + CH + j * WAVE + lane;
+                px[j] = 0; pu[j] = 0; pv[j] = 0; pw[j] = 0;
+                if (i < n) { px[j] = sg.x[b + i]; pu[j] = sg.u[b + i]; pv[j] = sg.v[b + i]; pw[j] = sg.w[b + i]; }
             }
+            int key[IT], rk[IT];
             int gone = 0;
 #pragma unroll
             for (int j = 0; j < IT; ++j) {
@@ -779,13 +805,13 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
                     rem &= ~mm;
                 }
             }
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int j = 0; j < IT; ++j) {
                 if (key[j] < 0) continue;
                 int r = binbase[key[j]] + rk[j];
                 for (int w2 = 0; w2 < w; ++w2) r += wcnt[w2][key[j]];
-                const int64_t pos = off_new[g + key[j] - KWIN] + r;
+                const int64_t pos = offb[key[j]] + r;
                 if (pos < cap) { dst.x[pos] = x[j]; dst.u[pos] = u[j]; dst.v[pos] = v[j]; dst.w[pos] = ww[j]; }
                 const int dd = key[j] - KWIN;
                 if (dd >= -MB && dd <= MB) {
@@ -801,13 +827,15 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
                     far = true;
                 }
             }
-            __syncthreads();
+            lds_barrier();
             for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
                 int s = 0;
                 for (int w2 = 0; w2 < nw; ++w2) { s += wcnt[w2][t]; wcnt[w2][t] = 0; }
                 binbase[t] += s;
             }
-            __syncthreads();
+            lds_barrier();
+#pragma unroll
+            for (int j = 0; j < IT; ++j) { x[j] = px[j]; u[j] = pu[j]; v[j] = pv[j]; ww[j] = pw[j]; }
         }
         block_sum<NMB * 5>(mb, red);
         const bool any_far = __syncthreads_or(far);
@@ -861,24 +889,38 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
     }
 }
 
-// 11. entrants go after the cell-sourced particles of their destination cell
+// 11. entrants go after the cell-sourced particles of their destination cell;
+// their next-step destinations join the predicted histogram
 template <typename T>
 __global__ void __launch_bounds__(256) k_scatter_inj(const DCase *__restrict__ cases, Cells cl, Inj<T> inj,
                                                      Soa<T> dst, int64_t cap)
 {
-    const int k = blockIdx.x;
+    const int k = blockIdx.y;
     const DCase &c = cases[k];
     const int32_t n = inj.count[k];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int64_t sl = c.inj_base + i;
-        const int d = inj.dest[sl];
-        const int64_t pos = cl.inj_start[d] + inj.rank[sl];
-        const T x = inj.x[sl], u = inj.u[sl];
-        if (pos < cap) { dst.x[pos] = x; dst.u[pos] = u; dst.v[pos] = inj.v[sl]; dst.w[pos] = inj.w[sl]; }
-        bool farp = false;
-        const int hb = flight_bin<T>(c, d - c.cell_base, x, u, &farp);
-        if (hb >= 0) atomicAdd(&cl.hist_nx[(int64_t)d * NBIN + hb], 1);
-        if (farp) cl.fix_nx[d] = 1;
+    const int lane = lane_id();
+    for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
+        const int i = i0 + threadIdx.x;
+        int key = -1;
+        if (i < n) {
+            const int64_t sl = c.inj_base + i;
+            const int d = inj.dest[sl];
+            const int64_t pos = cl.inj_start[d] + inj.rank[sl];
+            const T x = inj.x[sl], u = inj.u[sl];
+            if (pos < cap) { dst.x[pos] = x; dst.u[pos] = u; dst.v[pos] = inj.v[sl]; dst.w[pos] = inj.w[sl]; }
+            bool farp = false;
+            const int hb = flight_bin<T>(c, d - c.cell_base, x, u, &farp);
+            if (hb >= 0) key = d * NBIN + hb;
+            if (farp) cl.fix_nx[d] = 1;
+        }
+        uint64_t rem = __ballot(key >= 0);
+        while (rem) {
+            const int leader = __ffsll((unsigned long long)rem) - 1;
+            const int v0 = __builtin_amdgcn_readlane(key, leader);
+            const uint64_t mm = __ballot(key == v0);
+            if (lane == leader) atomicAdd(&cl.hist_nx[v0], __popcll(mm));
+            rem &= ~mm;
+        }
     }
 }
 
@@ -1035,6 +1077,28 @@ static void step_impl(duwp_ctx *ctx)
         hipLaunchKernelGGL(k_absorb_resample<T>, dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src,
                            ctx->off[p], stg, ctx->ibase, ctx->d_step, G, ctx->cap, ctx->d_err);
     }
+    // Injection and the wave-part update do not depend on the collisions: they run
+    // on a second stream (a parallel branch of the captured graph) while the
+    // collide kernel runs.  Kernel timing keeps everything on one stream.
+    const bool fork = !ctx->timer.on && ctx->stream2 != nullptr;
+    hipStream_t s2 = fork ? ctx->stream2 : st;
+    if (fork) {
+        (void)hipEventRecord(ctx->ev_fork, st);
+        (void)hipStreamWaitEvent(s2, ctx->ev_fork, 0);
+    }
+    {
+        Mark m(ctx, "inject");
+        if (ctx->inj_blocks > 0)
+            hipLaunchKernelGGL(k_inject_gen<T>, dim3(ctx->inj_blocks, 2 * ctx->ncases), dim3(256), 0, s2,
+                               ctx->d_cases, inj, ctx->d_step, ctx->d_err);
+        hipLaunchKernelGGL(k_inject_rank<T>, dim3(ctx->ncases), dim3(256), 0, s2, ctx->d_cases, cl, inj,
+                           ctx->d_ninj, ctx->d_err);
+    }
+    {
+        Mark m(ctx, "wave");
+        hipLaunchKernelGGL(k_wave, dim3(gthreads), dim3(256), 0, s2, ctx->d_cases, cl, G);
+    }
+    if (fork) (void)hipEventRecord(ctx->ev_join, s2);
     {
         Mark m(ctx, "collide");
         const int wpb = 4;
@@ -1046,17 +1110,10 @@ static void step_impl(duwp_ctx *ctx)
         hipLaunchKernelGGL(k_hist_build<T>, dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg, ctx->off[p], G,
                            ctx->cap, 0);
     }
-    {
-        Mark m(ctx, "inject");
-        if (ctx->inj_blocks > 0)
-            hipLaunchKernelGGL(k_inject_gen<T>, dim3(ctx->inj_blocks, 2 * ctx->ncases), dim3(256), 0, st,
-                               ctx->d_cases, inj, ctx->d_step, ctx->d_err);
-        hipLaunchKernelGGL(k_inject_rank<T>, dim3(ctx->ncases), dim3(256), 0, st, ctx->d_cases, cl, inj,
-                           ctx->d_ninj, ctx->d_err);
-    }
+    if (fork) (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
     {
         Mark m(ctx, "count_new");
-        hipLaunchKernelGGL(k_count_new, dim3(gthreads), dim3(256), 0, st, cl, G);
+        hipLaunchKernelGGL(k_count_new, dim3((G + 3) / 4), dim3(256), 0, st, cl, G);
     }
     {
         Mark m(ctx, "scan_offsets");
@@ -1064,7 +1121,7 @@ static void step_impl(duwp_ctx *ctx)
     }
     {
         Mark m(ctx, "bases");
-        hipLaunchKernelGGL(k_bases, dim3(gthreads), dim3(256), 0, st, cl, ctx->off[p ^ 1], G);
+        hipLaunchKernelGGL(k_bases, dim3((G + 3) / 4), dim3(256), 0, st, cl, ctx->off[p ^ 1], G);
     }
     {
         Mark m(ctx, "scatter");
@@ -1073,12 +1130,8 @@ static void step_impl(duwp_ctx *ctx)
     }
     {
         Mark m(ctx, "scatter_inj");
-        hipLaunchKernelGGL(k_scatter_inj<T>, dim3(ctx->ncases), dim3(256), 0, st, ctx->d_cases, cl, inj,
+        hipLaunchKernelGGL(k_scatter_inj<T>, dim3(8, ctx->ncases), dim3(256), 0, st, ctx->d_cases, cl, inj,
                            dst, ctx->cap);
-    }
-    {
-        Mark m(ctx, "wave");
-        hipLaunchKernelGGL(k_wave, dim3(gthreads), dim3(256), 0, st, ctx->d_cases, cl, G);
     }
     {
         Mark m(ctx, "gather_moments");

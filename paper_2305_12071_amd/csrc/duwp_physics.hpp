@@ -62,16 +62,21 @@ __device__ __forceinline__ void maxwell(double U, double V, double W, double T, 
 // particle left through a reservoir side.
 // ---------------------------------------------------------------------------
 
-// FP64, absolute position.
-__device__ __forceinline__ int bc_cell_abs(const DCase &c, double &x, double &u)
+// FP64, absolute position.  A particle that ends inside [x_lo, x_hi] takes the
+// short path; leaving the domain (reflection or deletion) takes the loop.
+struct FlightD { double x, u; int dest; };
+struct FlightF { float s, u; int dest; };
+
+__device__ __noinline__ FlightD bc_cell_abs_slow(const DCase &c, double x, double u)
 {
     for (int it = 0; it < 1000; ++it) {
+        if (!isfinite(x)) return FlightD{x, u, -1};
         if (x < c.x_lo) {
-            if (c.bc_lo == 0) return -1;
+            if (c.bc_lo == 0) return FlightD{x, u, -1};
             x = 2.0 * c.x_lo - x;
             u = -u;
         } else if (x > c.x_hi) {
-            if (c.bc_hi == 0) return -1;
+            if (c.bc_hi == 0) return FlightD{x, u, -1};
             x = 2.0 * c.x_hi - x;
             u = -u;
         } else {
@@ -79,34 +84,60 @@ __device__ __forceinline__ int bc_cell_abs(const DCase &c, double &x, double &u)
             int64_t ci = (int64_t)f;
             if (f < 0.0) ci = 0;
             if (ci > c.ncells - 1) ci = c.ncells - 1;
-            return (int)ci;
+            return FlightD{x, u, (int)ci};
         }
     }
-    return -1;
+    return FlightD{x, u, -1};
+}
+
+__device__ __forceinline__ int bc_cell_abs(const DCase &c, double &x, double &u)
+{
+    if (x >= c.x_lo && x <= c.x_hi) {
+        const double f = floor((x - c.x_lo) / c.dx);
+        int ci = (int)f;
+        if (ci > c.ncells - 1) ci = c.ncells - 1;
+        return ci;
+    }
+    const FlightD r = bc_cell_abs_slow(c, x, u);
+    x = r.x;
+    u = r.u;
+    return r.dest;
 }
 
 // FP32, position as (integer cell I, fraction f in [0,1)) relative to x_lo.
-__device__ __forceinline__ int bc_cell_rel(const DCase &c, int I, float f, float &u, float &s)
+__device__ __noinline__ FlightF bc_cell_rel_slow(const DCase &c, int I, float f, float u)
 {
     const int C = c.ncells;
     for (int it = 0; it < 1000; ++it) {
         if (I < 0) {
-            if (c.bc_lo == 0) return -1;
+            if (c.bc_lo == 0) return FlightF{f, u, -1};
             I = -I - 1;
             f = 1.0f - f;
             u = -u;
         } else if (I >= C) {
-            if (c.bc_hi == 0) return -1;
+            if (c.bc_hi == 0) return FlightF{f, u, -1};
             I = 2 * C - I - 1;
             f = 1.0f - f;
             u = -u;
         } else {
             if (f >= 1.0f) { f -= 1.0f; I += 1; continue; }
-            s = f;
-            return I;
+            return FlightF{f, u, I};
         }
     }
-    return -1;
+    return FlightF{f, u, -1};
+}
+
+__device__ __forceinline__ int bc_cell_rel(const DCase &c, int I, float f, float &u, float &s)
+{
+    if (f >= 1.0f) { f -= 1.0f; I += 1; }
+    if (I >= 0 && I < c.ncells) {
+        s = f;
+        return I;
+    }
+    const FlightF r = bc_cell_rel_slow(c, I, f, u);
+    s = r.s;
+    u = r.u;
+    return r.dest;
 }
 
 template <typename T>
@@ -127,9 +158,9 @@ struct Flight<float> {
     // stream a particle of local cell lc; x is the position inside the cell, in cells
     __device__ static int go(const DCase &c, int lc, float &s, float &u)
     {
-        float X = s + u * c.dtdx_f;
+        const float X = s + u * c.dtdx_f;
         if (!(fabsf(X) < 1.0e9f)) return -1;
-        float fl = floorf(X);
+        const float fl = floorf(X);
         return bc_cell_rel(c, lc + (int)fl, X - fl, u, s);
     }
 };

@@ -93,4 +93,35 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(const int32_t *__rest
     }
 }
 
+// Whole scan in one block of 1024 threads when G <= 8 * 1024.
+constexpr int SCAN1_ITEMS = 8;
+constexpr int SCAN1_MAX = SCAN1_ITEMS * 1024;
+
+__global__ void __launch_bounds__(1024) k_scan_single(const int32_t *__restrict__ in, int G,
+                                                      int64_t *__restrict__ out, int64_t cap, int64_t *total,
+                                                      int32_t *err)
+{
+    __shared__ int64_t lds[16];
+    const int t0 = threadIdx.x * SCAN1_ITEMS;
+    int64_t v[SCAN1_ITEMS];
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN1_ITEMS; ++i) {
+        v[i] = (t0 + i < G) ? in[t0 + i] : 0;
+        s += v[i];
+    }
+    int64_t tot;
+    int64_t run = block_exclusive_scan64(s, lds, &tot);
+#pragma unroll
+    for (int i = 0; i < SCAN1_ITEMS; ++i) {
+        if (t0 + i < G) out[t0 + i] = run < cap ? run : cap;
+        run += v[i];
+        if (t0 + i == G - 1) {
+            out[G] = run < cap ? run : cap;
+            *total = run;
+            if (run > cap) atomicOr(err, ERR_CAPACITY);
+        }
+    }
+}
+
 }  // namespace duwp
