@@ -25,21 +25,41 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-steps/sec on Mach-8 argon shock (FP32+FP64 vs FP64) + % HBM peak"
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic HBM bytes per particle of each particle-streaming kernel, per
-# element size s of the particle arrays (4 in FP32 mode, 8 in FP64 mode):
-# absorb_resample reads and writes x,u,v,w once (with nothing absorbed); scatter
-# reads the staged x,u,v,w and writes them to their sorted place; stream_hist
-# reads x,u; moments reads u,v,w.
+# Algorithmic HBM bytes per particle of the particle-streaming kernels, per
+# element size s of the particle arrays (4 in FP32 mode, 8 in FP64 mode): the
+# scatter reads x,u,v,w of each particle and writes them to its sorted place;
+# absorb_resample reads and writes them once for the cells that absorb or
+# resample (counted over all particles of the step, an upper bound).
 BYTES_PER_PARTICLE = {
-    "absorb_resample": lambda s: 8 * s,
     "scatter": lambda s: 8 * s,
-    "stream_hist": lambda s: 2 * s,
-    "moments": lambda s: 3 * s,
+    "absorb_resample": lambda s: 8 * s,
 }
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+KERNEL_SOURCES = ("duwp_kernels.hip", "duwp_physics.hpp", "duwp_device.hpp", "duwp_scan.hpp")
+
+
+def counted_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE runs, each scaled by a plain copy of known size), or
+    None when the kernel sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2305_12071_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
+        with open(path) as fh:
+            d = json.load(fh)
+        if d.get("kernel") == kernel and d.get("workload") == workload \
+                and d.get("kernel_sources_sha256") == h.hexdigest():
+            return d["hbm_bytes_per_launch"], d["particles_per_launch"]
+    return None
 
 
 def run_path(case, precision, steps, warmup, graph, seed=1, block_cells=0):
@@ -111,8 +131,12 @@ def main():
     dom = max((k for k in kms if k in BYTES_PER_PARTICLE), key=lambda k: kms[k])
     alg_bytes = BYTES_PER_PARTICLE[dom](4) * prof_ps
     achieved = alg_bytes / (kms[dom] * 1e-3) / 1e9
+    kname = {"scatter": "k_scatter<float>", "absorb_resample": "k_absorb_resample<float>"}.get(dom)
+    tr = counted_traffic(kname, case.name) if kname else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": tr[0] if tr else None,
+                "traffic_per_particle": round(tr[0] / tr[1], 2) if tr else None,
                 "bytes_per_particle": BYTES_PER_PARTICLE[dom](4), "particles_per_launch": int(prof_ps),
                 "kernel_ms": round(kms[dom], 4)}
     log("  kernels (ms):", json.dumps({k: round(v, 4) for k, v in kms.items()}))
