@@ -734,6 +734,13 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
         int64_t b;
         const Soa<T> sg = segment(cl, g, src, stg, b);
         const int32_t n = (int32_t)min((int64_t)cl.n_int[g], cap - b);
+        // cell-uniform base pointers: per-particle offsets stay 32-bit
+        const T *__restrict__ gx = sg.x + b, *__restrict__ gu = sg.u + b;
+        const T *__restrict__ gv = sg.v + b, *__restrict__ gw = sg.w + b;
+        const int64_t lo = off_new[max(g - KWIN, 0)];     // no destination of this cell starts lower
+        T *__restrict__ ox = dst.x + lo, *__restrict__ ou = dst.u + lo;
+        T *__restrict__ ov = dst.v + lo, *__restrict__ ow = dst.w + lo;
+        // moment sums of the particles moving |d| <= MB cells, per destination
         double mb[NMB * 5];
 #pragma unroll
         for (int i = 0; i < NMB * 5; ++i) mb[i] = 0.0;
@@ -744,7 +751,7 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
         for (int j = 0; j < IT; ++j) {
             const int i = w * IT * WAVE + j * WAVE + lane;
             x[j] = 0; u[j] = 0; v[j] = 0; ww[j] = 0;
-            if (i < n) { x[j] = sg.x[b + i]; u[j] = sg.u[b + i]; v[j] = sg.v[b + i]; ww[j] = sg.w[b + i]; }
+            if (i < n) { x[j] = gx[i]; u[j] = gu[i]; v[j] = gv[i]; ww[j] = gw[i]; }
         }
         for (int i0 = 0; i0 < n; i0 += CH) {
             const int wbase = i0 + w * IT * WAVE;
@@ -754,7 +761,7 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
             for (int j = 0; j < IT; ++j) {
                 const int i = wbase + CH + j * WAVE + lane;
                 px[j] = 0; pu[j] = 0; pv[j] = 0; pw[j] = 0;
-                if (i < n) { px[j] = sg.x[b + i]; pu[j] = sg.u[b + i]; pv[j] = sg.v[b + i]; pw[j] = sg.w[b + i]; }
+                if (i < n) { px[j] = gx[i]; pu[j] = gu[i]; pv[j] = gv[i]; pw[j] = gw[i]; }
             }
             int key[IT], rk[IT];
             int gone = 0;
@@ -790,7 +797,9 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
                 }
             }
             if (gone) atomicAdd(&nout, gone);
-            // wave-level stable ranks, items in order; wcnt[w][] counts this wave's chunk
+            // wave-level stable ranks, items in order; lane b of wc counts bin b in
+            // this wave's chunk, then goes to wcnt[w][b] for the cross-wave combine
+            int wc = 0;
 #pragma unroll
             for (int j = 0; j < IT; ++j) {
                 rk[j] = 0;
@@ -799,12 +808,13 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
                     const int leader = __ffsll((unsigned long long)rem) - 1;
                     const int v0 = __builtin_amdgcn_readlane(key[j], leader);
                     const uint64_t mm = __ballot(key[j] == v0);
-                    const int base = wcnt[w][v0];
+                    const int base = __builtin_amdgcn_readlane(wc, v0);
                     if (key[j] == v0) rk[j] = base + __popcll(mm & lanemask_lt());
-                    if (lane == leader) wcnt[w][v0] = base + __popcll(mm);
+                    if (lane == v0) wc += __popcll(mm);
                     rem &= ~mm;
                 }
             }
+            if (lane < NBIN) wcnt[w][lane] = wc;
             lds_barrier();
 #pragma unroll
             for (int j = 0; j < IT; ++j) {
@@ -812,7 +822,10 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
                 int r = binbase[key[j]] + rk[j];
                 for (int w2 = 0; w2 < w; ++w2) r += wcnt[w2][key[j]];
                 const int64_t pos = offb[key[j]] + r;
-                if (pos < cap) { dst.x[pos] = x[j]; dst.u[pos] = u[j]; dst.v[pos] = v[j]; dst.w[pos] = ww[j]; }
+                if (pos < cap) {
+                    const uint32_t rel = (uint32_t)(pos - lo);
+                    ox[rel] = x[j]; ou[rel] = u[j]; ov[rel] = v[j]; ow[rel] = ww[j];
+                }
                 const int dd = key[j] - KWIN;
                 if (dd >= -MB && dd <= MB) {
                     const double du = u[j], dv = v[j], dw = ww[j];
@@ -830,7 +843,7 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
             lds_barrier();
             for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
                 int s = 0;
-                for (int w2 = 0; w2 < nw; ++w2) { s += wcnt[w2][t]; wcnt[w2][t] = 0; }
+                for (int w2 = 0; w2 < nw; ++w2) s += wcnt[w2][t];
                 binbase[t] += s;
             }
             lds_barrier();
