@@ -9,7 +9,9 @@ beside it.  A step is one full DUWP time step of every stage, replayed as a
 captured HIP graph.  Metric: particle-steps per second (particles alive at the
 start of each step, summed over the timed steps, over the wall time).
 
-Prints one JSON line.
+Also reported: the batched form (256 independent uneven shock and Sod cases in
+one context, one launch per stage), the roofline of the dominant kernel and the
+CPU oracle on the same state.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -62,11 +64,11 @@ def counted_traffic(kernel: str, workload: str):
     return None
 
 
-def run_path(case, precision, steps, warmup, graph, seed=1, block_cells=0):
+def run_path(cases, precision, steps, warmup, graph, seed=1, block_cells=0):
     from paper_2305_12071_amd import duwp
     import torch
 
-    sim = duwp.Sim(case, seed=seed, precision=precision, use_graph=graph, block_cells=block_cells)
+    sim = duwp.Sim(cases, seed=seed, precision=precision, use_graph=graph, block_cells=block_cells)
     t = time.perf_counter()
     sim.step(warmup)
     log(f"  warmup {warmup} steps in {time.perf_counter() - t:.2f}s, N={sim.total_particles()}")
@@ -80,6 +82,17 @@ def run_path(case, precision, steps, warmup, graph, seed=1, block_cells=0):
     return sim, ps, t1 - t0
 
 
+def block_size(cases, precision, args):
+    """Block size of the per-cell kernels: fixed, tuned now, cached, or 256."""
+    from paper_2305_12071_amd import autotune
+    if args.block_cells:
+        return args.block_cells, "fixed"
+    if args.autotune:
+        return autotune.tune(cases, precision, path=args.tune_cache, log=log), "tuned"
+    bc = autotune.lookup(cases, precision)
+    return (bc, "cache") if bc else (256, "default")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,7 +102,14 @@ def main():
     ap.add_argument("--particles", type=float, default=5e7)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--block-cells", type=int, default=0, help="threads per block of the per-cell kernels")
+    ap.add_argument("--autotune", action="store_true", help="time the block-size candidates first")
+    ap.add_argument("--tune-cache", default=None, help="file --autotune writes (default: the package cache)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
+    ap.add_argument("--batched-cases", type=int, default=256)
+    ap.add_argument("--batched-steps", type=int, default=50)
+    ap.add_argument("--batched-vs-single", action="store_true",
+                    help="also time the batched cases one context per case")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--profile-steps", type=int, default=5)
@@ -119,8 +139,9 @@ def main():
     case = I.mach8_shock(args.cells, args.particles)
     graph = not args.no_graph
 
-    log(f"mixed FP32+FP64 path: {case.name}")
-    sim, ps, dt = run_path(case, duwp.MIXED, args.steps, args.warmup, graph, block_cells=args.block_cells)
+    bc, bc_src = block_size([case], duwp.MIXED, args)
+    log(f"mixed FP32+FP64 path: {case.name}, block_cells={bc} ({bc_src})")
+    sim, ps, dt = run_path([case], duwp.MIXED, args.steps, args.warmup, graph, block_cells=bc)
     value = ps / dt
     n_now = sim.total_particles()
     log(f"  {args.steps} steps in {dt:.3f}s -> {value:.4e} particle-steps/s")
@@ -168,12 +189,38 @@ def main():
         del sim
 
     fp64 = None
+    bc64 = None
     if not args.no_fp64:
-        log("plain FP64 path")
-        s64, ps64, dt64 = run_path(case, duwp.FP64, args.steps, args.warmup, graph, block_cells=args.block_cells)
+        bc64, src64 = block_size([case], duwp.FP64, args)
+        log(f"plain FP64 path, block_cells={bc64} ({src64})")
+        s64, ps64, dt64 = run_path([case], duwp.FP64, args.steps, args.warmup, graph, block_cells=bc64)
         fp64 = ps64 / dt64
         log(f"  {args.steps} steps in {dt64:.3f}s -> {fp64:.4e} particle-steps/s")
         s64.close()
+
+    batched = None
+    if not args.no_batched:
+        cases = I.batched_cases(args.batched_cases)
+        bcb, srcb = block_size(cases, duwp.MIXED, args)
+        ncell = sum(c.ncells for c in cases)
+        log(f"batched form: {len(cases)} cases, {ncell} cells, block_cells={bcb} ({srcb})")
+        sb, psb, dtb = run_path(cases, duwp.MIXED, args.batched_steps, 5, graph, block_cells=bcb)
+        batched = {"value": psb / dtb, "unit": "particle-steps/s", "cases": len(cases), "cells": ncell,
+                   "particles": sb.total_particles(), "steps": args.batched_steps,
+                   "ms_per_step": dtb / args.batched_steps * 1e3,
+                   "precision": "fp32 particles + fp64 cells", "block_cells": bcb}
+        batched["kernels_ms"] = {k: round(v, 4) for k, v in sb.profile(args.profile_steps).items()}
+        sb.close()
+        log(f"  {batched['value']:.4e} particle-steps/s, N={batched['particles']}")
+        if args.batched_vs_single:
+            tot_ps, tot_t = 0, 0.0
+            for c in cases:
+                s1, p1, t1 = run_path([c], duwp.MIXED, args.batched_steps, 5, graph, block_cells=bcb)
+                s1.close()
+                tot_ps += p1
+                tot_t += t1
+            batched["one_context_per_case"] = tot_ps / tot_t
+            log(f"  one context per case: {batched['one_context_per_case']:.4e} particle-steps/s")
 
     out = {
         "metric": METRIC,
@@ -190,9 +237,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": case.name, "cells": case.ncells, "particles": n_now,
                    "particles_target": args.particles, "precision": "fp32 particles + fp64 cells",
-                   "graph": graph, "gas": "argon VHS omega=0.81", "mach": 8},
+                   "graph": graph, "gas": "argon VHS omega=0.81", "mach": 8, "block_cells": bc},
         "fp64_value": fp64,
         "mixed_over_fp64": (value / fp64) if fp64 else None,
+        "fp64_block_cells": bc64,
+        "batched": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -1,0 +1,96 @@
+"""Checks at the benchmark's sizes and in its launch configuration (graph replay).
+
+- Batched uneven cases: every case of a 32-case batch from the seeded batch
+  generator matches its own oracle step for step.
+- Mach-8 shock, 4000 cells, 5e7 particles: one FP64 step from the GPU's
+  warmed-up state matches the oracle's step from the same state (integers exact,
+  FP64 within 1e-12); the FP32+FP64 path keeps exact particle bookkeeping and
+  its state stays well formed.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2305_12071_amd import duwp
+from paper_2305_12071_amd import inputs as I
+
+from _parity import compare_diag, compare_states
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    O.build(force=False)
+    duwp.lib()
+
+
+def test_batched_generator_cases_match_oracles():
+    cases = I.batched_cases(32, ppc_scale=0.2)
+    _say("batched 32 cases", sum(c.ncells for c in cases), "cells")
+    g = duwp.Sim(cases, seed=1, precision=duwp.FP64, use_graph=True)
+    ors = [O.Oracle(c, seed=1, case_id=k) for k, c in enumerate(cases)]
+    for s in range(3):
+        g.step(1)
+        for k, o in enumerate(ors):
+            o.step(1)
+            compare_diag(g.diag(k), o.diag(), f"{cases[k].name}:{s}")
+    for k, o in enumerate(ors):
+        compare_states(g.get_state(k), o.get_state(), rtol=1e-11, label=cases[k].name,
+                       psi_t=o.cells()["psi_t"])
+    g.close()
+
+
+def test_mach8_full_size_fp64_step_matches_oracle():
+    c = I.mach8_shock()
+    _say("mach8 full size fp64: warm-up on the GPU")
+    g = duwp.Sim(c, seed=1, precision=duwp.FP64, use_graph=True)
+    g.step(5)
+    st = g.get_state()
+    n = len(st["x"])
+    assert 4.9e7 < n < 5.1e7
+    _say("oracle load", n)
+    o = O.Oracle(c, seed=1, case_id=0)
+    o.set_state(st)
+    del st
+    g.step(1)
+    o.step(1)
+    _say("compare")
+    compare_diag(g.diag(), o.diag(), "mach8")
+    compare_states(g.get_state(), o.get_state(), label="mach8", psi_t=o.cells()["psi_t"])
+    g.close()
+
+
+def test_mach8_full_size_mixed_bookkeeping():
+    c = I.mach8_shock()
+    _say("mach8 full size mixed")
+    g = duwp.Sim(c, seed=1, precision=duwp.MIXED, use_graph=True)
+    g.step(10)
+    n0 = g.n_particles()
+    m0 = g.moments(0, duwp.M_PSI_T)[:, 0].sum()
+    g.step(1)
+    d = g.diag()
+    n1 = g.n_particles()
+    # every particle is accounted for: absorbed, resampled, injected, left
+    assert n1 == n0 - d["n_abs"].sum() + d["n_new"].sum() + d["n_inj"].sum() - d["n_out"]
+    # P = 0 everywhere (dt < tau): pure DSMC, as the paper states for its shock cases
+    assert d["n_abs"].sum() == 0
+    # total mass changes by the entrants minus the leavers (the wave part carries no flux)
+    m1 = g.moments(0, duwp.M_PSI_T)[:, 0].sum()
+    dm = (d["n_inj"].sum() - d["n_out"]) * c.m_particle / c.dx
+    assert abs((m1 - m0) - dm) <= 1e-9 * m0
+    st = g.get_state()
+    off = st["off"]
+    assert off[0] == 0 and off[-1] == len(st["x"]) == n1 and np.all(np.diff(off) >= 0)
+    cell = np.repeat(np.arange(c.ncells), np.diff(off))
+    f = (st["x"] - c.x_lo) / c.dx - cell
+    assert f.min() >= -1e-6 and f.max() <= 1 + 1e-6
+    assert np.isfinite(st["u"]).all() and np.isfinite(st["v"]).all() and np.isfinite(st["w"]).all()
+    g.close()
