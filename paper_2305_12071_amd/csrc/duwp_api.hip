@@ -130,10 +130,17 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &c.seg, 8 * (size_t)G));
     TRY(dalloc(ctx, &c.seg_stg, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.mpart, 8 * 5 * (size_t)G * duwp::NBIN));
+    TRY(dalloc(ctx, &c.mnear, 8 * 15 * (size_t)G));
+    TRY(dalloc(ctx, &c.far_in, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.d_abs, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.d_new, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.d_cand, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.d_coll, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.cbase, 8 * (size_t)(G + 1)));
+    TRY(dalloc(ctx, &c.cr_seen, 8 * (size_t)G));
+    ctx->items_cap = std::max<int64_t>(1 << 20, 2 * (int64_t)G);
+    TRY(dalloc(ctx, &ctx->item_cell, 4 * (size_t)ctx->items_cap));
+    TRY(dalloc(ctx, &ctx->d_items, 16));
     for (int p = 0; p < 2; ++p) {
         TRY(dalloc(ctx, &ctx->hist_buf[p], 4 * (size_t)G * duwp::NBIN));
         TRY(dalloc(ctx, &ctx->fix_buf[p], 4 * (size_t)G));
@@ -150,7 +157,7 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &ctx->d_err, 4));
     TRY(dalloc(ctx, &ctx->d_nout, 8 * (size_t)ctx->ncases));
     TRY(dalloc(ctx, &ctx->d_ninj, 16 * (size_t)ctx->ncases));
-    TRY(dalloc(ctx, &ctx->d_total, 16));
+    TRY(dalloc(ctx, &ctx->d_total, 24));
     TRY(dalloc(ctx, &ctx->d_psteps, 8));
     TRY(dalloc(ctx, &ctx->d_cases, sizeof(DCase) * (size_t)ctx->ncases));
     return DUWP_OK;
@@ -187,6 +194,9 @@ duwp_status upload_initial(duwp_ctx *ctx)
                           hipMemcpyHostToDevice, s));
     HIP_OK(hipMemsetAsync(ctx->cl.psi_p, 0, 8 * 5 * (size_t)G, s));
     HIP_OK(hipMemsetAsync(ctx->cl.avg, 0, 8 * 5 * (size_t)G, s));
+    HIP_OK(hipMemsetAsync(ctx->cl.cr_seen, 0, 8 * (size_t)G, s));
+    HIP_OK(hipMemsetAsync(ctx->cl.mpart, 0, 8 * 5 * (size_t)G * duwp::NBIN, s));
+    HIP_OK(hipMemsetAsync(ctx->cl.far_in, 0, 4 * (size_t)G, s));
     for (int p = 0; p < 2; ++p) HIP_OK(hipMemsetAsync(ctx->off[p], 0, 8 * (size_t)(G + 1), s));
     HIP_OK(hipMemsetAsync(ctx->d_step, 0, 4, s));
     HIP_OK(hipMemsetAsync(ctx->d_err, 0, 4, s));
@@ -361,6 +371,14 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
     ctx->cand_total = std::max<int64_t>(cand, 1);
     ctx->chunk_total = std::max<int64_t>(chunks, 1);
     ctx->inj_blocks = (int)std::min<int64_t>((max_side + 255) / 256, 64);
+    {
+        // collision work items are taken by a fixed grid of waves: 16 per compute unit
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+            ncu = 256;
+        ctx->coll_blocks = 4 * ncu;
+    }
     duwp_status s = alloc_all(ctx);
     if (s == DUWP_OK) s = upload_initial(ctx);
     if (s != DUWP_OK) { duwp_destroy(ctx); return s; }

@@ -62,7 +62,11 @@ struct duwp_ctx {
     int32_t *d_err = nullptr;
     int64_t *d_nout = nullptr;     // [ncases]
     int64_t *d_ninj = nullptr;     // [ncases*2]
-    int64_t *d_total = nullptr;    // [2]
+    int64_t *d_total = nullptr;    // [3] staged particles, next particle count, collision candidates
+    int32_t *item_cell = nullptr;  // first cell of each collision work item
+    int64_t *d_items = nullptr;    // [2] number of collision work items, candidates per item
+    int64_t items_cap = 0;
+    int coll_blocks = 0;
     int64_t *d_psteps = nullptr;   // particle-steps since init or the last reset
 
     hipGraphExec_t graph[2] = {nullptr, nullptr};

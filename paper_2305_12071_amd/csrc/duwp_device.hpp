@@ -44,7 +44,9 @@ struct Cells {
     int32_t *n_stage;   // [G] particles copied to staging (0 for an untouched cell)
     int64_t *seg;       // [G] start of the cell's intermediate segment
     int32_t *seg_stg;   // [G] 1: segment in the staging buffer, 0: in place in the canonical buffer
-    int32_t *d_abs, *d_new, *d_cand, *d_coll;  // [G] diagnostics
+    int32_t *d_abs, *d_new, *d_cand, *d_coll;  // [G] diagnostics; d_cand is also the collide work size
+    int64_t *cbase;     // [G+1] first collision candidate of each cell in the step's candidate list
+    uint64_t *cr_seen;  // [G] largest relative speed seen this step (bits of a non-negative double)
     int32_t *hist;      // [G*NBIN] destination histogram of this step, then scatter bases
     int32_t *hist_nx;   // [G*NBIN] histogram predicted for the next step
     int32_t *fix;       // [G] 1: this step's histogram of the cell must be recounted
@@ -54,7 +56,9 @@ struct Cells {
     int64_t *inj_start; // [G] first slot of the injected entrants of each destination cell
     int32_t *cell_case; // [G]
     double *avg;        // [G*5]
-    double *mpart;      // [G*NBIN*5] particle moment sums per (source cell, destination)
+    double *mnear;      // [G*15] particle moment sums of a source cell per destination g-1, g, g+1
+    double *mpart;      // [G*NBIN*5] sums from farther sources, by destination (zero unless far_in)
+    int32_t *far_in;    // [G] 1: a farther source left sums in the cell's mpart row this step
 };
 
 // Injection buffers: candidates of every (case, side), then the entrants of
@@ -130,6 +134,26 @@ __device__ __forceinline__ int wave_sum_i(int v)
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
     return v;
+}
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)(uint64_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    return __longlong_as_double(readlane64(__double_as_longlong(v), l));
+}
+
+// Orders this wave's LDS accesses (no barrier): LDS operations of one wave
+// complete in issue order, so a later read by any lane sees an earlier write.
+__device__ __forceinline__ void lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Block barrier that orders LDS only: outstanding global loads (e.g. prefetches)

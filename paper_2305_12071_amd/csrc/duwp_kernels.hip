@@ -43,81 +43,116 @@ constexpr int NMB = 2 * MB + 1;
 constexpr int NBI = 2 * (KWIN + 1);    // injection destination window (both ends)
 
 // ---------------------------------------------------------------------------
-// 1. Cell state at step start, absorbed and resampled counts
+// 1. Cell state at step start, absorbed and resampled counts, collision
+// candidate counts.  One lane per cell; the absorbed particles of a cell with
+// P > 0 are counted by the whole wave, one cell at a time.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(512) k_cellstate(const DCase *__restrict__ cases, Cells cl,
+__global__ void __launch_bounds__(256) k_cellstate(const DCase *__restrict__ cases, Cells cl,
                                                     const int64_t *__restrict__ off,
                                                     const uint32_t *__restrict__ d_step, int G,
                                                     int32_t *err, int64_t *d_nout, int64_t *d_ninj)
 {
-    __shared__ double red[16];
     const uint32_t step = *d_step;
-    for (int g = blockIdx.x; g < G; g += gridDim.x) {
-        const int k = cl.cell_case[g];
-        const DCase &c = cases[k];
-        const int lc = g - c.cell_base;
-        double t[5], W[5];
+    const int lane = lane_id();
+    const int g0 = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * WAVE;
+    if (g0 >= G) return;
+    const int nc = min(WAVE, G - g0);
+    for (int t = lane; t < nc * NBIN; t += WAVE) cl.hist_nx[(int64_t)g0 * NBIN + t] = 0;
+    const int g = g0 + lane;
+    const bool in = lane < nc;
+    const int k = in ? cl.cell_case[g] : 0;
+    const DCase &c = cases[k];
+    double W[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    int ok = 0;
+    double P = 0.0;
+    int64_t b = 0, e = 0, pbase = 0;
+    if (in) {
+        double t[5];
 #pragma unroll
         for (int i = 0; i < 5; ++i) t[i] = cl.psi_w[(int64_t)g * 5 + i] + cl.psi_p[(int64_t)g * 5 + i];
-        const int ok = primitive(t, c.R, W);
-        double P = 0.0;
+        ok = primitive(t, c.R, W);
         if (ok) {
-            double tau = viscosity(c, W[4]) / (W[0] * c.R * W[4]);
+            const double tau = viscosity(c, W[4]) / (W[0] * c.R * W[4]);
             P = absorb_fraction(c.law, c.dt, tau);
         }
-        const int64_t b = off[g], e = off[g + 1];
-        const int64_t pbase = off[c.cell_base];
-        double nabs[1] = {0.0};
-        if (P > 0.0) {
-            // one Philox block classifies four consecutive particles
-            for (int64_t kk = b + threadIdx.x; kk < e; kk += blockDim.x) {
-                uint32_t kl = (uint32_t)(kk - pbase);
-                U4 r = draw(c, step, kl >> 2, 0, TAG_CLS, 0);
-                nabs[0] += (u01(pick(r, kl & 3)) < P) ? 1.0 : 0.0;
-            }
-            block_sum<1>(nabs, red);
-        }
-        int32_t nnew = 0;
-        if (ok) {
-            double Mw = c.dx * cl.psi_w[(int64_t)g * 5 + 0];
-            U4 r = draw(c, step, (uint32_t)lc, 0, TAG_RCNT, 0);
-            double nf = floor((1.0 - P) * Mw / c.m_p + u01(r.a));
-            double cap = floor((Mw > 0.0 ? Mw : 0.0) / c.m_p);
-            if (nf > cap) nf = cap;
-            if (nf < 0.0) nf = 0.0;
-            if (nf > 2.0e9) { if (threadIdx.x == 0) atomicOr(err, ERR_CAPACITY); nf = 0.0; }
-            nnew = (int32_t)nf;
-        }
-        for (int t = threadIdx.x; t < NBIN; t += blockDim.x) cl.hist_nx[(int64_t)g * NBIN + t] = 0;
-        if (threadIdx.x == 0) {
-            cl.fix_nx[g] = 0;
+        b = off[g];
+        e = off[g + 1];
+        pbase = off[c.cell_base];
+    }
+    // classification (one Philox block decides four consecutive particles of a case)
+    int32_t nabs = 0;
+    uint64_t todo = __ballot(in && P > 0.0 && e > b);
+    while (todo) {
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const int64_t bl = readlane64(b, l), el = readlane64(e, l), pl = readlane64(pbase, l);
+        const double Pl = readlane_d(P, l);
+        const DCase &cc = cases[__builtin_amdgcn_readlane(k, l)];
+        const int64_t q0 = (bl - pl) >> 2, q1 = (el - 1 - pl) >> 2;
+        int cnt = 0;
+        for (int64_t q = q0 + lane; q <= q1; q += WAVE) {
+            const U4 r = draw(cc, step, (uint32_t)q, 0, TAG_CLS, 0);
+            const int64_t i0 = pl + 4 * q;
+            const uint32_t wd[4] = {r.a, r.b, r.c, r.d};
 #pragma unroll
-            for (int i = 0; i < 5; ++i) cl.wt[(int64_t)g * 5 + i] = W[i];
-            cl.pc[g] = P;
-            cl.okc[g] = ok;
-            const int32_t na = (int32_t)nabs[0];
-            const int32_t ns = (int32_t)(e - b) - na;
-            cl.n_surv[g] = ns;
-            cl.n_new[g] = nnew;
-            cl.n_int[g] = ns + nnew;
-            const bool touched = na > 0 || nnew > 0;
-            cl.n_stage[g] = touched ? ns + nnew : 0;
-            cl.seg_stg[g] = touched ? 1 : 0;
-            cl.inj_cnt[g] = 0;
-            if (lc == 0) {
-                d_nout[k] = 0;
-                d_ninj[2 * k] = 0;
-                d_ninj[2 * k + 1] = 0;
-            }
+            for (int m = 0; m < 4; ++m)
+                if (i0 + m >= bl && i0 + m < el && u01(wd[m]) < Pl) ++cnt;
         }
+        cnt = wave_sum_i(cnt);
+        if (lane == l) nabs = cnt;
+    }
+    if (!in) return;
+    const int lc = g - c.cell_base;
+    int32_t nnew = 0;
+    if (ok) {
+        const double Mw = c.dx * cl.psi_w[(int64_t)g * 5 + 0];
+        const U4 r = draw(c, step, (uint32_t)lc, 0, TAG_RCNT, 0);
+        double nf = floor((1.0 - P) * Mw / c.m_p + u01(r.a));
+        const double capn = floor((Mw > 0.0 ? Mw : 0.0) / c.m_p);
+        if (nf > capn) nf = capn;
+        if (nf < 0.0) nf = 0.0;
+        if (nf > 2.0e9) { atomicOr(err, ERR_CAPACITY); nf = 0.0; }
+        nnew = (int32_t)nf;
+    }
+    const int32_t ns = (int32_t)(e - b) - nabs;
+    const int32_t N = ns + nnew;
+    // NTC candidate count (Appendix A) over the collision share of the step
+    int32_t M = 0;
+    if (ok && N >= 2) {
+        const double dtc = c.full_dt ? c.dt : (1.0 - P) * c.dt;
+        const double cm = cl.cr_max[g];
+        const double Mr = 0.5 * (double)(N - 1) * c.coll_k * W[0] * pow(c.c_ref / cm, 2.0 * c.ups) * cm * dtc;
+        const U4 r = draw(c, step, (uint32_t)lc, 0, TAG_NCNT, 0);
+        double Mf = floor(Mr + u01(r.a));
+        if (Mf > 2.0e9) { atomicOr(err, ERR_CAPACITY); Mf = 0.0; }
+        M = (int32_t)Mf;
+    }
+    cl.fix_nx[g] = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) cl.wt[(int64_t)g * 5 + i] = W[i];
+    cl.pc[g] = P;
+    cl.okc[g] = ok;
+    cl.n_surv[g] = ns;
+    cl.n_new[g] = nnew;
+    cl.n_int[g] = N;
+    const bool touched = nabs > 0 || nnew > 0;
+    cl.n_stage[g] = touched ? N : 0;
+    cl.seg_stg[g] = touched ? 1 : 0;
+    cl.inj_cnt[g] = 0;
+    cl.d_cand[g] = M;
+    cl.d_coll[g] = 0;
+    if (lc == 0) {
+        d_nout[k] = 0;
+        d_ninj[2 * k] = 0;
+        d_ninj[2 * k + 1] = 0;
     }
 }
 
-static void enqueue_scan(duwp_ctx *ctx, const int32_t *in, int64_t *out, int64_t *total)
+static void enqueue_scan(duwp_ctx *ctx, const int32_t *in, int64_t *out, int64_t *total, int64_t cap)
 {
     const int G = ctx->G;
     if (G <= SCAN1_MAX) {
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, ctx->stream, in, G, out, ctx->cap, total,
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, ctx->stream, in, G, out, cap, total,
                            ctx->d_err);
         return;
     }
@@ -126,7 +161,7 @@ static void enqueue_scan(duwp_ctx *ctx, const int32_t *in, int64_t *out, int64_t
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, ctx->stream, ctx->scan_part,
                        ctx->ntiles);
     hipLaunchKernelGGL(k_scan_apply, dim3(ctx->ntiles), dim3(SCAN_BLOCK), 0, ctx->stream, in, G,
-                       ctx->scan_part, out, ctx->cap, total, ctx->d_err);
+                       ctx->scan_part, out, cap, total, ctx->d_err);
 }
 
 // Destination bin (d + KWIN) of a particle of local cell lc after free flight;
@@ -275,107 +310,215 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// 4. NTC / VHS collisions, one wave per cell.
+// 4. NTC / VHS collisions (Appendix A).
 //
-// Candidates q = 0..M-1 are taken in chunks of 64, one per lane.  Pair indices
-// depend only on the random stream, so each lane can see which earlier lanes
-// of its chunk share a particle with it.  Lanes run in rounds: a lane runs
-// once every earlier lane it shares a particle with has run, which gives the
-// same result as running the candidates one after another.
+// The candidates of all cells form one list in (cell, q) order; cbase[g] is
+// the first candidate of cell g.  The list is cut into work items of S
+// candidates: item w takes every cell whose first candidate lies in
+// [w S, (w+1) S), so a cell belongs to exactly one item and one wave runs all
+// of its candidates, 64 at a time (one per lane, several cells per chunk).
+//
+// Within a chunk, lane L must see particle p as the candidates before it left
+// it.  An LDS table of lane masks hashed by (cell, particle) finds, for each of
+// L's two particles, the last earlier lane that touched it; lanes run in rounds
+// once those (at most two) lanes have run, and take the particle's velocity
+// from that lane's LDS slot instead of memory.  Chunks of one item run in
+// order with the earlier chunks' stores visible, so the result is the
+// candidates' sequential result.
 // ---------------------------------------------------------------------------
+constexpr int COLL_HBITS = 8;
+constexpr int COLL_WPB = 4;      // waves per block
+
+// item_cell[w] = first cell of item w; d_items = {number of items, S}
+__global__ void __launch_bounds__(256) k_items(const int64_t *__restrict__ cbase, int G, int32_t *item_cell,
+                                               int64_t *d_items, int64_t items_cap)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g > G) return;
+    const int64_t total = cbase[G];
+    int64_t S = (total + items_cap - 2) / (items_cap - 1);   // at most items_cap - 1 items
+    S = S < WAVE ? WAVE : (S + WAVE - 1) / WAVE * WAVE;
+    const int64_t nitems = (total + S - 1) / S;
+    if (g == 0) {
+        d_items[0] = nitems;
+        d_items[1] = S;
+        if (nitems > 0) item_cell[0] = 0;
+        return;
+    }
+    // items w >= 1 with cbase[g-1] < w S <= cbase[g] start at cell g
+    const int64_t lo = cbase[g - 1], hi = cbase[g];
+    for (int64_t w = lo / S + 1; w * S <= hi && w < nitems; ++w) item_cell[w] = g;
+}
+
+__device__ __forceinline__ uint32_t coll_slot(int g, uint32_t i)
+{
+    return ((uint32_t)g * 0x9E3779B1u ^ i * 0x85EBCA77u) * 0xC2B2AE3Du >> (32 - COLL_HBITS);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
                                                  Soa<T> stg, const uint32_t *__restrict__ d_step, int G,
-                                                 int64_t cap, int32_t *err)
+                                                 int64_t cap, int32_t *err, const int32_t *__restrict__ item_cell,
+                                                 const int64_t *__restrict__ d_items)
 {
+    __shared__ uint64_t hmask[COLL_WPB][1 << COLL_HBITS];
+    __shared__ T fwd[COLL_WPB][6][WAVE];     // (u,v,w) of particle i, then of j, per lane
+    const int wv = threadIdx.x >> 6, lane = lane_id();
     const uint32_t step = *d_step;
-    const int wpb = blockDim.x >> 6, wid = threadIdx.x >> 6, lane = lane_id();
-    for (int g = blockIdx.x * wpb + wid; g < G; g += gridDim.x * wpb) {
-        const int k = cl.cell_case[g];
-        const DCase &c = cases[k];
-        const int lc = g - c.cell_base;
-        const int32_t N = cl.n_int[g];
-        int64_t sb;
-        const Soa<T> sg = segment(cl, g, src, stg, sb);
-        int64_t M = 0;
-        int ncoll = 0;
-        double seen = 0.0;
-        double cm = 0.0;
-        bool far = false;
-        if (cl.okc[g] && N >= 2 && sb + N <= cap) {
-            const double P = cl.pc[g];
-            const double dtc = c.full_dt ? c.dt : (1.0 - P) * c.dt;
-            cm = cl.cr_max[g];
-            double Mr = 0.5 * (double)(N - 1) * c.coll_k * cl.wt[(int64_t)g * 5 + 0] *
-                        pow(c.c_ref / cm, 2.0 * c.ups) * cm * dtc;
-            U4 r = draw(c, step, (uint32_t)lc, 0, TAG_NCNT, 0);
-            double Mf = floor(Mr + u01(r.a));
-            if (Mf > 2.0e9) { if (lane == 0) atomicOr(err, ERR_CAPACITY); Mf = 0.0; }
-            M = (int64_t)Mf;
-            const double aexp = 1.0 - 2.0 * c.ups;
-            T *su = sg.u + sb, *sv = sg.v + sb, *sw = sg.w + sb;
-            const T *sx = sg.x + sb;
-            int32_t *hg = cl.hist + (int64_t)g * NBIN;
-            for (int64_t q0 = 0; q0 < M; q0 += WAVE) {
-                const int64_t q = q0 + lane;
-                const bool act = q < M;
-                uint32_t i = 0xffffffffu, j = 0xfffffffeu;
-                double u2 = 0.0, u3 = 0.0, u4 = 0.0;
-                if (act) {
-                    U4 a = draw(c, step, (uint32_t)lc, (uint32_t)q, TAG_PAIR, 0);
-                    U4 bb = draw(c, step, (uint32_t)lc, (uint32_t)q, TAG_PAIR, 1);
-                    uint64_t r0 = ((uint64_t)a.a << 32) | a.b;
-                    uint64_t r1 = ((uint64_t)a.c << 32) | a.d;
+    const int64_t nitems = d_items[0];
+    for (int t = lane; t < (1 << COLL_HBITS); t += WAVE) hmask[wv][t] = 0ull;
+    lds_fence();
+    const uint64_t lt = lanemask_lt();
+    for (int64_t it = (int64_t)blockIdx.x * COLL_WPB + wv; it < nitems; it += (int64_t)gridDim.x * COLL_WPB) {
+        const int ga = item_cell[it];
+        const int gb = it + 1 < nitems ? item_cell[it + 1] : G;
+        const int64_t qend = cl.cbase[gb];
+        int gcur = ga;
+        for (int64_t Q0 = cl.cbase[ga]; Q0 < qend; Q0 += WAVE) {
+            const int64_t Q = Q0 + lane;
+            bool act = Q < qend;
+            // cell of candidate Q: gcur + number of cell starts <= Q after gcur
+            int g = -1;
+            int64_t gstart = 0;
+            {
+                bool need = act;
+                int gw = gcur;
+                int64_t prev = cl.cbase[gw];
+                while (__ballot(need)) {
+                    const int gl = gw + 1 + lane;
+                    const int64_t cb = gl <= gb ? cl.cbase[gl] : INT64_MAX;
+                    int n = 0;
+#pragma unroll
+                    for (int st2 = 32; st2 >= 1; st2 >>= 1) {
+                        const int64_t v = __shfl(cb, n + st2 - 1, WAVE);
+                        if (v <= Q) n += st2;
+                    }
+                    const int64_t last = readlane64(cb, WAVE - 1);
+                    if (n == WAVE - 1 && last <= Q) n = WAVE;
+                    const int64_t sprev = __shfl(cb, n > 0 ? n - 1 : 0, WAVE);
+                    if (need && n < WAVE) {
+                        g = gw + n;
+                        gstart = n > 0 ? sprev : prev;
+                        need = false;
+                    }
+                    prev = last;
+                    gw += WAVE;
+                }
+            }
+            const int gnext = __builtin_amdgcn_readlane(g, WAVE - 1);
+            // the cell's particles, constants and pair
+            uint32_t i = 0, j = 0;
+            double u2 = 0.0, u3 = 0.0, u4 = 0.0, cm = 1.0, aexp = 0.0;
+            T xi = 0, ui = 0, vi = 0, wi = 0, xj = 0, uj = 0, vj = 0, wj = 0;
+            T *pu = nullptr, *pv = nullptr, *pw = nullptr;
+            int lc = 0, k = 0;
+            if (act) {
+                const int32_t N = cl.n_int[g];
+                const int64_t sb = cl.seg[g];
+                k = cl.cell_case[g];
+                const DCase &c = cases[k];
+                lc = g - c.cell_base;
+                if (sb + N > cap) {
+                    act = false;   // capacity overflow, already reported
+                } else {
+                    const Soa<T> sg = cl.seg_stg[g] ? stg : src;
+                    cm = cl.cr_max[g];
+                    aexp = 1.0 - 2.0 * c.ups;
+                    const uint32_t q = (uint32_t)(Q - gstart);
+                    const U4 ra = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 0);
+                    const U4 rb = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 1);
+                    const uint64_t r0 = ((uint64_t)ra.a << 32) | ra.b;
+                    const uint64_t r1 = ((uint64_t)ra.c << 32) | ra.d;
                     i = (uint32_t)mulhi64(r0, (uint64_t)N);
                     j = (uint32_t)mulhi64(r1, (uint64_t)(N - 1));
                     if (j >= i) j += 1;
-                    u2 = u01(bb.a); u3 = u01(bb.b); u4 = u01(bb.c);
-                }
-                const uint64_t actm = __ballot(act);
-                uint64_t dep = 0;
-                const int nl = (int)min((int64_t)WAVE, M - q0);
-                for (int l = 0; l < nl; ++l) {
-                    uint32_t il = __builtin_amdgcn_readlane(i, l);
-                    uint32_t jl = __builtin_amdgcn_readlane(j, l);
-                    bool cf = (l < lane) && (il == i || il == j || jl == i || jl == j);
-                    dep |= (uint64_t)cf << l;
-                }
-                uint64_t done = ~actm;
-                while (done != ~0ull) {
-                    const bool ready = act && !((done >> lane) & 1ull) && ((dep & ~done) == 0ull);
-                    if (ready) {
-                        const T ui0 = su[i], uj0 = su[j];
-                        if (collide_pair<T>(su, sv, sw, i, j, cm, aexp, u2, u3, u4, seen)) {
-                            ++ncoll;
-                            // move the pair between destination bins of this step's histogram
-                            const T xi = sx[i], xj = sx[j], ui1 = su[i], uj1 = su[j];
-                            bool f0 = false;
-                            const int a0 = flight_bin<T>(c, lc, xi, ui0, &f0), a1 = flight_bin<T>(c, lc, xi, ui1, &far);
-                            const int b0 = flight_bin<T>(c, lc, xj, uj0, &f0), b1 = flight_bin<T>(c, lc, xj, uj1, &far);
-                            if (a0 != a1) {
-                                if (a0 >= 0) atomicSub(&hg[a0], 1);
-                                if (a1 >= 0) atomicAdd(&hg[a1], 1);
-                            }
-                            if (b0 != b1) {
-                                if (b0 >= 0) atomicSub(&hg[b0], 1);
-                                if (b1 >= 0) atomicAdd(&hg[b1], 1);
-                            }
-                        }
-                    }
-                    // this round's stores are complete before the next round loads
-                    __threadfence_block();
-                    done |= __ballot(ready);
+                    u2 = u01(rb.a); u3 = u01(rb.b); u4 = u01(rb.c);
+                    const T *px = sg.x + sb;
+                    pu = sg.u + sb; pv = sg.v + sb; pw = sg.w + sb;
+                    xi = px[i]; ui = pu[i]; vi = pv[i]; wi = pw[i];
+                    xj = px[j]; uj = pu[j]; vj = pv[j]; wj = pw[j];
                 }
             }
-        }
-        seen = wave_max(seen);
-        ncoll = wave_sum_i(ncoll);
-        const bool anyfar = __ballot(far) != 0ull;
-        if (lane == 0) {
-            if (anyfar) cl.fix[g] = 1;
-            cl.d_cand[g] = (int32_t)M;
-            cl.d_coll[g] = ncoll;
-            if (seen > cm && M > 0) cl.cr_max[g] = seen;
+            if (!act) g = -1;
+            // last earlier lane touching each of this lane's particles
+            const uint32_t si = coll_slot(g, i), sj = coll_slot(g, j);
+            if (act) {
+                atomicOr(&hmask[wv][si], 1ull << lane);
+                atomicOr(&hmask[wv][sj], 1ull << lane);
+            }
+            lds_fence();
+            uint64_t ci = act ? (hmask[wv][si] & lt) : 0ull, cj = act ? (hmask[wv][sj] & lt) : 0ull;
+            lds_fence();
+            if (act) { hmask[wv][si] = 0ull; hmask[wv][sj] = 0ull; }
+            int pi = -1, pj = -1, oi = 0, oj = 0;
+            while (__ballot(ci != 0ull || cj != 0ull)) {
+                const int li = ci ? 63 - __clzll((long long)ci) : lane;
+                const int lj = cj ? 63 - __clzll((long long)cj) : lane;
+                const int gli = __shfl(g, li, WAVE), glj = __shfl(g, lj, WAVE);
+                const uint32_t ii = __shfl(i, li, WAVE), ji = __shfl(j, li, WAVE);
+                const uint32_t ij = __shfl(i, lj, WAVE), jj = __shfl(j, lj, WAVE);
+                if (ci) {
+                    if (gli == g && (ii == i || ji == i)) { pi = li; oi = ii == i ? 0 : 3; ci = 0ull; }
+                    else ci &= ~(1ull << li);
+                }
+                if (cj) {
+                    if (glj == g && (ij == j || jj == j)) { pj = lj; oj = ij == j ? 0 : 3; cj = 0ull; }
+                    else cj &= ~(1ull << lj);
+                }
+            }
+            const uint64_t dep = (pi >= 0 ? 1ull << pi : 0ull) | (pj >= 0 ? 1ull << pj : 0ull);
+            double seen = 0.0;
+            int acc = 0;
+            bool far = false;
+            uint64_t done = ~__ballot(act);
+            while (done != ~0ull) {
+                const bool ready = !((done >> lane) & 1ull) && (dep & ~done) == 0ull;
+                if (ready) {
+                    if (pi >= 0) { ui = fwd[wv][oi][pi]; vi = fwd[wv][oi + 1][pi]; wi = fwd[wv][oi + 2][pi]; }
+                    if (pj >= 0) { uj = fwd[wv][oj][pj]; vj = fwd[wv][oj + 1][pj]; wj = fwd[wv][oj + 2][pj]; }
+                    const T ui0 = ui, uj0 = uj;
+                    if (collide_vals<T>(ui, vi, wi, uj, vj, wj, cm, aexp, u2, u3, u4, seen)) {
+                        acc = 1;
+                        pu[i] = ui; pv[i] = vi; pw[i] = wi;
+                        pu[j] = uj; pv[j] = vj; pw[j] = wj;
+                        // move the pair between destination bins of this step's histogram
+                        const DCase &c = cases[k];
+                        int32_t *hg = cl.hist + (int64_t)g * NBIN;
+                        bool f0 = false;
+                        const int a0 = flight_bin<T>(c, lc, xi, ui0, &f0), a1 = flight_bin<T>(c, lc, xi, ui, &far);
+                        const int b0 = flight_bin<T>(c, lc, xj, uj0, &f0), b1 = flight_bin<T>(c, lc, xj, uj, &far);
+                        if (a0 != a1) {
+                            if (a0 >= 0) atomicSub(&hg[a0], 1);
+                            if (a1 >= 0) atomicAdd(&hg[a1], 1);
+                        }
+                        if (b0 != b1) {
+                            if (b0 >= 0) atomicSub(&hg[b0], 1);
+                            if (b1 >= 0) atomicAdd(&hg[b1], 1);
+                        }
+                    }
+                    fwd[wv][0][lane] = ui; fwd[wv][1][lane] = vi; fwd[wv][2][lane] = wi;
+                    fwd[wv][3][lane] = uj; fwd[wv][4][lane] = vj; fwd[wv][5][lane] = wj;
+                }
+                lds_fence();
+                done |= __ballot(ready);
+            }
+            // per-cell results: accepted collisions (segmented sum over the chunk's
+            // lanes of one cell), largest relative speed, out-of-window flag
+            int sacc = acc;
+#pragma unroll
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const int t = __shfl_up(sacc, o, WAVE);
+                const int gu = __shfl_up(g, o, WAVE);
+                if (lane >= o && gu == g) sacc += t;
+            }
+            const int gd = __shfl_down(g, 1, WAVE);
+            if (g >= 0 && (lane == WAVE - 1 || gd != g) && sacc > 0) atomicAdd(&cl.d_coll[g], sacc);
+            if (act && seen > cm)
+                atomicMax((unsigned long long *)&cl.cr_seen[g], (unsigned long long)__double_as_longlong(seen));
+            if (far) cl.fix[g] = 1;
+            gcur = gnext;
+            // the next chunk of this item reads what this one stored
+            if (Q0 + WAVE < qend) __threadfence_block();
         }
     }
 }
@@ -694,6 +837,12 @@ __device__ __forceinline__ void add_phi(double (&a)[5], double u, double v, doub
     a[4] += 0.5 * (u * u + v * v + w * w);
 }
 
+// number of set bits of m below this lane
+__device__ __forceinline__ int lane_rank(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 template <typename T>
 __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
                                                  Soa<T> stg, Soa<T> dst, const int64_t *__restrict__ off_new,
@@ -702,18 +851,20 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
     // Besides placing each particle, the scatter predicts where it goes next
     // step (free flight from its new place with its current velocity) and
     // counts the next step's destination histogram of its new cell in hn[]
-    // (new cell relative to this one, next destination), flushed per cell.
+    // (new cell relative to this one, next destination), flushed per cell for
+    // the new cells that received particles.
     //
     // Each chunk holds IT*blockDim particles; wave w takes the contiguous
     // range of IT*64 particles at w*IT*64, lane l its items l, l+64, ...  Ranks
     // inside a wave come from ballots; the waves' counts are combined once per
     // chunk.  The next chunk is loaded while the current one is placed.
     constexpr int IT = 4;
+    constexpr int MAXW = 8;
     __shared__ int binbase[NBIN];
     __shared__ int bin0[NBIN];
     __shared__ int64_t offb[NBIN];
-    __shared__ int wcnt[16][NBIN];
-    __shared__ double red[NMB * 5 * 16];
+    __shared__ int wcnt[MAXW][NBIN];
+    __shared__ double red[NMB * 5 * MAXW];
     __shared__ int hn[NBIN * NBIN];
     __shared__ int nout;
     const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -729,7 +880,7 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
             const int d = g + t - KWIN;
             offb[t] = (d >= 0 && d < G) ? off_new[d] : 0;
         }
-        for (int t = threadIdx.x; t < 16 * NBIN; t += blockDim.x) (&wcnt[0][0])[t] = 0;
+        for (int t = threadIdx.x; t < nw * NBIN; t += blockDim.x) (&wcnt[0][0])[t] = 0;
         __syncthreads();
         int64_t b;
         const Soa<T> sg = segment(cl, g, src, stg, b);
@@ -809,7 +960,7 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
                     const int v0 = __builtin_amdgcn_readlane(key[j], leader);
                     const uint64_t mm = __ballot(key[j] == v0);
                     const int base = __builtin_amdgcn_readlane(wc, v0);
-                    if (key[j] == v0) rk[j] = base + __popcll(mm & lanemask_lt());
+                    if (key[j] == v0) rk[j] = base + lane_rank(mm);
                     if (lane == v0) wc += __popcll(mm);
                     rem &= ~mm;
                 }
@@ -852,33 +1003,32 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
         }
         block_sum<NMB * 5>(mb, red);
         const bool any_far = __syncthreads_or(far);
-        for (int t = threadIdx.x; t < NBIN * NBIN; t += blockDim.x) {
-            const int v0 = hn[t];
-            if (v0) {
-                atomicAdd(&cl.hist_nx[(int64_t)(g + t / NBIN - KWIN) * NBIN + t % NBIN], v0);
-                hn[t] = 0;
+        // rows of the predicted histogram: only new cells that received particles
+        for (int r = 0; r < NBIN; ++r) {
+            if (binbase[r] == bin0[r]) continue;
+            for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
+                const int v0 = hn[r * NBIN + t];
+                if (v0) {
+                    atomicAdd(&cl.hist_nx[(int64_t)(g + r - KWIN) * NBIN + t], v0);
+                    hn[r * NBIN + t] = 0;
+                }
             }
         }
         if (threadIdx.x == 0 && nout) {
             atomicAdd((unsigned long long *)&d_nout[k], (unsigned long long)nout);
             nout = 0;
         }
-        // moment sums stored by destination: row d = g + dd, slot KWIN - dd
-        for (int t = threadIdx.x; t < NBIN * 5; t += blockDim.x) {
-            const int bin = t / 5, comp = t % 5, dd = bin - KWIN;
-            if (g + dd < 0 || g + dd >= G) continue;
+        // near sums of this source cell: slot m is destination g + m - MB
+        if (threadIdx.x < NMB * 5) {
             double val = 0.0;
 #pragma unroll
-            for (int m = 0; m < NMB; ++m)
-                if (dd + MB == m) {
-#pragma unroll
-                    for (int q = 0; q < 5; ++q)
-                        if (comp == q) val = mb[m * 5 + q];
-                }
-            cl.mpart[((int64_t)(g + dd) * NBIN + (KWIN - dd)) * 5 + comp] = val;
+            for (int q = 0; q < NMB * 5; ++q)
+                if ((int)threadIdx.x == q) val = mb[q];
+            cl.mnear[(int64_t)g * (NMB * 5) + threadIdx.x] = val;
         }
         if (any_far) {
-            // a second pass per farther destination that received particles
+            // a second pass per farther destination that received particles;
+            // the sums go to the destination's row, slot KWIN - dd
             for (int bin = 0; bin < NBIN; ++bin) {
                 const int dd = bin - KWIN;
                 if ((dd >= -MB && dd <= MB) || binbase[bin] == bin0[bin]) continue;
@@ -896,6 +1046,7 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
                         if ((int)threadIdx.x == q) val = a[q];
                     cl.mpart[((int64_t)(g + dd) * NBIN + (KWIN - dd)) * 5 + threadIdx.x] = val;
                 }
+                if (threadIdx.x == 0) cl.far_in[g + dd] = 1;
             }
         }
         __syncthreads();
@@ -957,44 +1108,73 @@ __global__ void __launch_bounds__(256) k_wave(const DCase *__restrict__ cases, C
 
 // ---------------------------------------------------------------------------
 // 13. Particle moments of the new state per cell (Eq. gkt_moment0): the sums of
-// the source groups in source order, then the entrants; running average of
-// Psi_t; finite-state check.
+// the near source cells, of farther sources if any, then the entrants; running
+// average of Psi_t; largest relative speed of the collisions; finite-state check.
+// One lane per destination cell; the entrants of a cell are summed by the whole wave.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict__ cases, Cells cl, Soa<T> dst,
                                                         const int64_t *__restrict__ off_new, int G, int32_t *err)
 {
-    // one wave per destination cell: lane l holds the sums of source cell d + l - KWIN
     const int lane = lane_id();
-    const int d = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (d >= G) return;
-    const DCase &c = cases[cl.cell_case[d]];
+    const int d = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * WAVE + lane;
+    if ((d - lane) >= G) return;
+    const bool in = d < G;
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (lane < NBIN) {
-        const int src = d + lane - KWIN;
-        if (src >= 0 && src < G) {
-            const double *mp = cl.mpart + ((int64_t)d * NBIN + lane) * 5;
-#pragma unroll
-            for (int q = 0; q < 5; ++q) s[q] = mp[q];
-        }
-    }
-    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t kk = cl.inj_start[d] + lane; kk < off_new[d + 1]; kk += WAVE)
-        add_phi(a, (double)dst.u[kk], (double)dst.v[kk], (double)dst.w[kk]);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) s[q] = wave_sum(s[q]) + wave_sum(a[q]);
-    if (lane == 0) {
-        bool bad = false;
+    int64_t ib = 0, ie = 0;
+    if (in) {
+        constexpr int R = NMB * 5;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            const double p = c.fac * s[q];
-            cl.psi_p[(int64_t)d * 5 + q] = p;
-            const double t = cl.psi_w[(int64_t)d * 5 + q] + p;
-            if (!isfinite(t)) bad = true;
-            cl.avg[(int64_t)d * 5 + q] += t;
+            // sources d-1 (moved +1), d (stayed), d+1 (moved -1)
+            const double a = d > 0 ? cl.mnear[(int64_t)(d - 1) * R + 2 * 5 + q] : 0.0;
+            const double bq = cl.mnear[(int64_t)d * R + 1 * 5 + q];
+            const double cq = d + 1 < G ? cl.mnear[(int64_t)(d + 1) * R + 0 * 5 + q] : 0.0;
+            s[q] = (a + bq) + cq;
         }
-        if (bad) atomicOr(err, ERR_STATE);
+        if (cl.far_in[d]) {
+            double *row = cl.mpart + (int64_t)d * NBIN * 5;
+            for (int t = 0; t < NBIN; ++t)
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    s[q] += row[t * 5 + q];
+                    row[t * 5 + q] = 0.0;
+                }
+            cl.far_in[d] = 0;
+        }
+        ib = cl.inj_start[d];
+        ie = off_new[d + 1];
     }
+    uint64_t todo = __ballot(in && ie > ib);
+    while (todo) {
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const int64_t bl = readlane64(ib, l), el = readlane64(ie, l);
+        double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int64_t kk = bl + lane; kk < el; kk += WAVE)
+            add_phi(a, (double)dst.u[kk], (double)dst.v[kk], (double)dst.w[kk]);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            a[q] = wave_sum(a[q]);
+            if (lane == l) s[q] += a[q];
+        }
+    }
+    if (!in) return;
+    const DCase &c = cases[cl.cell_case[d]];
+    // largest relative speed seen by this cell's collision candidates
+    const double seen = __longlong_as_double((long long)cl.cr_seen[d]);
+    if (seen > cl.cr_max[d]) cl.cr_max[d] = seen;
+    cl.cr_seen[d] = 0ull;
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const double p = c.fac * s[q];
+        cl.psi_p[(int64_t)d * 5 + q] = p;
+        const double t = cl.psi_w[(int64_t)d * 5 + q] + p;
+        if (!isfinite(t)) bad = true;
+        cl.avg[(int64_t)d * 5 + q] += t;
+    }
+    if (bad) atomicOr(err, ERR_STATE);
 }
 
 // Particle moments recomputed from a canonical array (after a state is loaded).
@@ -1078,12 +1258,12 @@ static void step_impl(duwp_ctx *ctx)
     cl.fix_nx = ctx->fix_buf[p ^ 1];
     {
         Mark m(ctx, "cellstate");
-        hipLaunchKernelGGL(k_cellstate, dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, ctx->off[p],
+        hipLaunchKernelGGL(k_cellstate, dim3((G + 255) / 256), dim3(256), 0, st, ctx->d_cases, cl, ctx->off[p],
                            ctx->d_step, G, ctx->d_err, ctx->d_nout, ctx->d_ninj);
     }
     {
         Mark m(ctx, "scan_staging");
-        enqueue_scan(ctx, ctx->cl.n_stage, ctx->ibase, ctx->d_total);
+        enqueue_scan(ctx, ctx->cl.n_stage, ctx->ibase, ctx->d_total, ctx->cap);
     }
     {
         Mark m(ctx, "absorb_resample");
@@ -1114,9 +1294,11 @@ static void step_impl(duwp_ctx *ctx)
     if (fork) (void)hipEventRecord(ctx->ev_join, s2);
     {
         Mark m(ctx, "collide");
-        const int wpb = 4;
-        hipLaunchKernelGGL(k_collide<T>, dim3((G + wpb - 1) / wpb), dim3(64 * wpb), 0, st, ctx->d_cases,
-                           cl, src, stg, ctx->d_step, G, ctx->cap, ctx->d_err);
+        enqueue_scan(ctx, ctx->cl.d_cand, ctx->cl.cbase, ctx->d_total + 2, INT64_MAX);
+        hipLaunchKernelGGL(k_items, dim3((G + 1 + 255) / 256), dim3(256), 0, st, ctx->cl.cbase, G, ctx->item_cell,
+                           ctx->d_items, ctx->items_cap);
+        hipLaunchKernelGGL(k_collide<T>, dim3(ctx->coll_blocks), dim3(64 * COLL_WPB), 0, st, ctx->d_cases,
+                           cl, src, stg, ctx->d_step, G, ctx->cap, ctx->d_err, ctx->item_cell, ctx->d_items);
     }
     {
         Mark m(ctx, "hist_fix");
@@ -1130,7 +1312,7 @@ static void step_impl(duwp_ctx *ctx)
     }
     {
         Mark m(ctx, "scan_offsets");
-        enqueue_scan(ctx, ctx->cl.cnt_new, ctx->off[p ^ 1], ctx->d_total + 1);
+        enqueue_scan(ctx, ctx->cl.cnt_new, ctx->off[p ^ 1], ctx->d_total + 1, ctx->cap);
     }
     {
         Mark m(ctx, "bases");
@@ -1148,7 +1330,7 @@ static void step_impl(duwp_ctx *ctx)
     }
     {
         Mark m(ctx, "gather_moments");
-        hipLaunchKernelGGL(k_gather_moments<T>, dim3((G + 3) / 4), dim3(256), 0, st, ctx->d_cases, cl, dst,
+        hipLaunchKernelGGL(k_gather_moments<T>, dim3((G + 255) / 256), dim3(256), 0, st, ctx->d_cases, cl, dst,
                            ctx->off[p ^ 1], G, ctx->d_err);
     }
     {

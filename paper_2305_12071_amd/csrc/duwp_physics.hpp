@@ -276,18 +276,17 @@ __device__ inline void case_face_flux(const DCase &c, const Cells &cl, int f, do
 }
 
 // ---------------------------------------------------------------------------
-// Equal-mass VHS collision of particles i and j of a cell segment (Appendix A):
+// Equal-mass VHS collision of a particle pair held in registers (Appendix A):
 // acceptance (c_r/c_max)^(1-2 upsilon), isotropic scattering with
-// cos(theta) = 2 u3 - 1, phi = 2 pi u4.  Returns true when accepted.
+// cos(theta) = 2 u3 - 1, phi = 2 pi u4.  Returns true when accepted (the
+// velocities are then replaced by the post-collision ones).
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ bool collide_pair(T *su, T *sv, T *sw, uint32_t i, uint32_t j, double cm,
+__device__ __forceinline__ bool collide_vals(T &ui, T &vi, T &wi, T &uj, T &vj, T &wj, double cm,
                                              double accept_exp, double u2, double u3, double u4,
                                              double &seen)
 {
     if constexpr (std::is_same<T, double>::value) {
-        double ui = su[i], vi = sv[i], wi = sw[i];
-        double uj = su[j], vj = sv[j], wj = sw[j];
         double d0 = ui - uj, d1 = vi - vj, d2 = wi - wj;
         double cr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
         seen = fmax(seen, cr);
@@ -298,12 +297,10 @@ __device__ __forceinline__ bool collide_pair(T *su, T *sv, T *sw, uint32_t i, ui
         double ph = D_TWO_PI * u4;
         double r0 = cr * st * cos(ph), r1 = cr * st * sin(ph), r2 = cr * ct;
         double m0 = 0.5 * (ui + uj), m1 = 0.5 * (vi + vj), m2 = 0.5 * (wi + wj);
-        su[i] = m0 + 0.5 * r0; sv[i] = m1 + 0.5 * r1; sw[i] = m2 + 0.5 * r2;
-        su[j] = m0 - 0.5 * r0; sv[j] = m1 - 0.5 * r1; sw[j] = m2 - 0.5 * r2;
+        ui = m0 + 0.5 * r0; vi = m1 + 0.5 * r1; wi = m2 + 0.5 * r2;
+        uj = m0 - 0.5 * r0; vj = m1 - 0.5 * r1; wj = m2 - 0.5 * r2;
         return true;
     } else {
-        float ui = su[i], vi = sv[i], wi = sw[i];
-        float uj = su[j], vj = sv[j], wj = sw[j];
         float d0 = ui - uj, d1 = vi - vj, d2 = wi - wj;
         float cr = sqrtf(__fmaf_rn(d0, d0, __fmaf_rn(d1, d1, d2 * d2)));
         seen = fmax(seen, (double)cr);
@@ -316,8 +313,8 @@ __device__ __forceinline__ bool collide_pair(T *su, T *sv, T *sw, uint32_t i, ui
         float h = 0.5f * cr;
         float r0 = h * st * cp, r1 = h * st * sp, r2 = h * ct;
         float m0 = 0.5f * (ui + uj), m1 = 0.5f * (vi + vj), m2 = 0.5f * (wi + wj);
-        su[i] = m0 + r0; sv[i] = m1 + r1; sw[i] = m2 + r2;
-        su[j] = m0 - r0; sv[j] = m1 - r1; sw[j] = m2 - r2;
+        ui = m0 + r0; vi = m1 + r1; wi = m2 + r2;
+        uj = m0 - r0; vj = m1 - r1; wj = m2 - r2;
         return true;
     }
 }
