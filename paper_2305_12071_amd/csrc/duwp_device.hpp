@@ -55,6 +55,7 @@ struct Cells {
     int32_t *inj_cnt;   // [G] injected entrants per destination cell
     int64_t *inj_start; // [G] first slot of the injected entrants of each destination cell
     int32_t *cell_case; // [G]
+    int32_t *order;     // [G] cells in the visiting order of the block-per-cell kernels
     double *avg;        // [G*5]
     double *mnear;      // [G*15] particle moment sums of a source cell per destination g-1, g, g+1
     double *mpart;      // [G*NBIN*5] sums from farther sources, by destination (zero unless far_in)

@@ -201,7 +201,8 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
     __shared__ int scr[16];
     __shared__ int dh[NBIN];
     const uint32_t step = *d_step;
-    for (int g = blockIdx.x; g < G; g += gridDim.x) {
+    for (int gi = blockIdx.x; gi < G; gi += gridDim.x) {
+        const int g = cl.order[gi];
         const int touched = cl.seg_stg[g];
         if (threadIdx.x == 0) cl.seg[g] = touched ? sbase[g] : off[g];
         if (!touched) {
@@ -746,7 +747,8 @@ __global__ void __launch_bounds__(512) k_hist_build(const DCase *__restrict__ ca
     // of the cells flagged during the step (all = 0).
     constexpr int IT = 4;
     __shared__ int h[NBIN];
-    for (int g = blockIdx.x; g < G; g += gridDim.x) {
+    for (int gi = blockIdx.x; gi < G; gi += gridDim.x) {
+        const int g = cl.order[gi];
         if (!all && !cl.fix[g]) continue;
         const DCase &c = cases[cl.cell_case[g]];
         const int lc = g - c.cell_base;
@@ -848,208 +850,219 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
                                                  Soa<T> stg, Soa<T> dst, const int64_t *__restrict__ off_new,
                                                  int G, int64_t cap, int32_t *err, int64_t *d_nout)
 {
-    // Besides placing each particle, the scatter predicts where it goes next
-    // step (free flight from its new place with its current velocity) and
-    // counts the next step's destination histogram of its new cell in hn[]
-    // (new cell relative to this one, next destination), flushed per cell for
-    // the new cells that received particles.
+    // One block per cell (grid = G, visiting order cl.order).  Besides placing
+    // each particle, the scatter predicts where it goes next step (free flight
+    // from its new place with its current velocity) and counts the next step's
+    // destination histogram of its new cell in hn[] (new cell relative to this
+    // one, next destination), flushed for the new cells that received particles.
     //
     // Each chunk holds IT*blockDim particles; wave w takes the contiguous
     // range of IT*64 particles at w*IT*64, lane l its items l, l+64, ...  Ranks
     // inside a wave come from ballots; the waves' counts are combined once per
-    // chunk.  The next chunk is loaded while the current one is placed.
+    // chunk behind a single barrier.  Two register sets alternate: the next
+    // chunk is loaded into one while the other is placed, with no copy between
+    // them (a copy would wait for the loads just issued).
     constexpr int IT = 4;
     constexpr int MAXW = 8;
-    __shared__ int binbase[NBIN];
+    __shared__ int binbase[2][NBIN];     // by chunk parity
     __shared__ int bin0[NBIN];
     __shared__ int64_t offb[NBIN];
-    __shared__ int wcnt[MAXW][NBIN];
+    __shared__ int wcnt[2][MAXW][NBIN];  // by chunk parity
     __shared__ double red[NMB * 5 * MAXW];
     __shared__ int hn[NBIN * NBIN];
     __shared__ int nout;
+    if ((int)blockIdx.x >= G) return;
     const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int t = threadIdx.x; t < NBIN * NBIN; t += blockDim.x) hn[t] = 0;
     if (threadIdx.x == 0) nout = 0;
-    for (int g = blockIdx.x; g < G; g += gridDim.x) {
-        const int k = cl.cell_case[g];
-        const DCase &c = cases[k];
-        const int lc = g - c.cell_base;
-        for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
-            binbase[t] = cl.hist[(int64_t)g * NBIN + t];
-            bin0[t] = binbase[t];
-            const int d = g + t - KWIN;
-            offb[t] = (d >= 0 && d < G) ? off_new[d] : 0;
-        }
-        for (int t = threadIdx.x; t < nw * NBIN; t += blockDim.x) (&wcnt[0][0])[t] = 0;
-        __syncthreads();
-        int64_t b;
-        const Soa<T> sg = segment(cl, g, src, stg, b);
-        const int32_t n = (int32_t)min((int64_t)cl.n_int[g], cap - b);
-        // cell-uniform base pointers: per-particle offsets stay 32-bit
-        const T *__restrict__ gx = sg.x + b, *__restrict__ gu = sg.u + b;
-        const T *__restrict__ gv = sg.v + b, *__restrict__ gw = sg.w + b;
-        const int64_t lo = off_new[max(g - KWIN, 0)];     // no destination of this cell starts lower
-        T *__restrict__ ox = dst.x + lo, *__restrict__ ou = dst.u + lo;
-        T *__restrict__ ov = dst.v + lo, *__restrict__ ow = dst.w + lo;
-        // moment sums of the particles moving |d| <= MB cells, per destination
-        double mb[NMB * 5];
+    const int g = cl.order[blockIdx.x];
+    const int k = cl.cell_case[g];
+    const DCase &c = cases[k];
+    const int lc = g - c.cell_base;
+    for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
+        binbase[0][t] = cl.hist[(int64_t)g * NBIN + t];
+        bin0[t] = binbase[0][t];
+        const int d = g + t - KWIN;
+        offb[t] = (d >= 0 && d < G) ? off_new[d] : 0;
+    }
+    __syncthreads();
+    int64_t b;
+    const Soa<T> sg = segment(cl, g, src, stg, b);
+    const int32_t n = (int32_t)min((int64_t)cl.n_int[g], cap - b);
+    // cell-uniform base pointers: per-particle offsets are unsigned 32-bit
+    const T *__restrict__ gx = sg.x + b, *__restrict__ gu = sg.u + b;
+    const T *__restrict__ gv = sg.v + b, *__restrict__ gw = sg.w + b;
+    const int64_t lo = off_new[max(g - KWIN, 0)];     // no destination of this cell starts lower
+    T *__restrict__ ox = dst.x + lo, *__restrict__ ou = dst.u + lo;
+    T *__restrict__ ov = dst.v + lo, *__restrict__ ow = dst.w + lo;
+    // moment sums of the particles moving |d| <= MB cells, per destination
+    double mb[NMB * 5];
 #pragma unroll
-        for (int i = 0; i < NMB * 5; ++i) mb[i] = 0.0;
-        bool far = false;
-        const int CH = IT * (int)blockDim.x;
-        T x[IT], u[IT], v[IT], ww[IT];
+    for (int i = 0; i < NMB * 5; ++i) mb[i] = 0.0;
+    bool far = false;
+    const int CH = IT * (int)blockDim.x;
+    const int wofs = w * IT * WAVE + lane;
+    int cb = 0;
+
+    // loads of a chunk: indices past the end are clamped to the last particle
+    // (their values are loaded but not used), so the loads need no branches
+    auto load = [&](T (&X)[IT], T (&U)[IT], T (&V)[IT], T (&W)[IT], int i0) {
 #pragma unroll
         for (int j = 0; j < IT; ++j) {
-            const int i = w * IT * WAVE + j * WAVE + lane;
-            x[j] = 0; u[j] = 0; v[j] = 0; ww[j] = 0;
-            if (i < n) { x[j] = gx[i]; u[j] = gu[i]; v[j] = gv[i]; ww[j] = gw[i]; }
+            // 32-bit byte offset from a wave-uniform base
+            const uint32_t bo = (uint32_t)min(i0 + wofs + j * WAVE, n - 1) * (uint32_t)sizeof(T);
+            X[j] = *(const T *)((const char *)gx + bo);
+            U[j] = *(const T *)((const char *)gu + bo);
+            V[j] = *(const T *)((const char *)gv + bo);
+            W[j] = *(const T *)((const char *)gw + bo);
         }
-        for (int i0 = 0; i0 < n; i0 += CH) {
-            const int wbase = i0 + w * IT * WAVE;
-            // prefetch the next chunk
-            T px[IT], pu[IT], pv[IT], pw[IT];
+    };
+    auto place = [&](T (&X)[IT], T (&U)[IT], T (&V)[IT], T (&W)[IT], int i0) {
+        int key[IT], rk[IT];
+        int gone = 0;
 #pragma unroll
-            for (int j = 0; j < IT; ++j) {
-                const int i = wbase + CH + j * WAVE + lane;
-                px[j] = 0; pu[j] = 0; pv[j] = 0; pw[j] = 0;
-                if (i < n) { px[j] = gx[i]; pu[j] = gu[i]; pv[j] = gv[i]; pw[j] = gw[i]; }
-            }
-            int key[IT], rk[IT];
-            int gone = 0;
-#pragma unroll
-            for (int j = 0; j < IT; ++j) {
-                const int i = wbase + j * WAVE + lane;
-                key[j] = -1;
-                if (i < n) {
-                    const int dest = Flight<T>::go(c, lc, x[j], u[j]);
-                    if (dest >= 0) {
-                        const int d = dest - lc;
-                        if (d >= -KWIN && d <= KWIN) key[j] = d + KWIN;
-                        else atomicOr(err, ERR_RANGE);
-                    } else {
-                        ++gone;
-                    }
-                }
-                // next step's destination of the particle from its new place
-                int key2 = -1;
-                if (key[j] >= 0) {
-                    bool farp = false;
-                    const int hb = flight_bin<T>(c, lc + key[j] - KWIN, x[j], u[j], &farp);
-                    if (hb >= 0) key2 = key[j] * NBIN + hb;
-                    if (farp) cl.fix_nx[g + key[j] - KWIN] = 1;
-                }
-                uint64_t rem2 = __ballot(key2 >= 0);
-                while (rem2) {
-                    const int leader = __ffsll((unsigned long long)rem2) - 1;
-                    const int v0 = __builtin_amdgcn_readlane(key2, leader);
-                    const uint64_t mm = __ballot(key2 == v0);
-                    if (lane == leader) atomicAdd(&hn[v0], __popcll(mm));
-                    rem2 &= ~mm;
-                }
-            }
-            if (gone) atomicAdd(&nout, gone);
-            // wave-level stable ranks, items in order; lane b of wc counts bin b in
-            // this wave's chunk, then goes to wcnt[w][b] for the cross-wave combine
-            int wc = 0;
-#pragma unroll
-            for (int j = 0; j < IT; ++j) {
-                rk[j] = 0;
-                uint64_t rem = __ballot(key[j] >= 0);
-                while (rem) {
-                    const int leader = __ffsll((unsigned long long)rem) - 1;
-                    const int v0 = __builtin_amdgcn_readlane(key[j], leader);
-                    const uint64_t mm = __ballot(key[j] == v0);
-                    const int base = __builtin_amdgcn_readlane(wc, v0);
-                    if (key[j] == v0) rk[j] = base + lane_rank(mm);
-                    if (lane == v0) wc += __popcll(mm);
-                    rem &= ~mm;
-                }
-            }
-            if (lane < NBIN) wcnt[w][lane] = wc;
-            lds_barrier();
-#pragma unroll
-            for (int j = 0; j < IT; ++j) {
-                if (key[j] < 0) continue;
-                int r = binbase[key[j]] + rk[j];
-                for (int w2 = 0; w2 < w; ++w2) r += wcnt[w2][key[j]];
-                const int64_t pos = offb[key[j]] + r;
-                if (pos < cap) {
-                    const uint32_t rel = (uint32_t)(pos - lo);
-                    ox[rel] = x[j]; ou[rel] = u[j]; ov[rel] = v[j]; ow[rel] = ww[j];
-                }
-                const int dd = key[j] - KWIN;
-                if (dd >= -MB && dd <= MB) {
-                    const double du = u[j], dv = v[j], dw = ww[j];
-                    const double e2 = 0.5 * (du * du + dv * dv + dw * dw);
-#pragma unroll
-                    for (int m = 0; m < NMB; ++m)
-                        if (dd + MB == m) {
-                            mb[m * 5 + 0] += 1.0; mb[m * 5 + 1] += du; mb[m * 5 + 2] += dv; mb[m * 5 + 3] += dw;
-                            mb[m * 5 + 4] += e2;
-                        }
+        for (int j = 0; j < IT; ++j) {
+            key[j] = -1;
+            if (i0 + wofs + j * WAVE < n) {
+                const int dest = Flight<T>::go(c, lc, X[j], U[j]);
+                if (dest >= 0) {
+                    const int d = dest - lc;
+                    if (d >= -KWIN && d <= KWIN) key[j] = d + KWIN;
+                    else atomicOr(err, ERR_RANGE);
                 } else {
-                    far = true;
+                    ++gone;
                 }
             }
-            lds_barrier();
-            for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
-                int s = 0;
-                for (int w2 = 0; w2 < nw; ++w2) s += wcnt[w2][t];
-                binbase[t] += s;
+            // next step's destination of the particle from its new place
+            if (key[j] >= 0) {
+                bool farp = false;
+                const int hb = flight_bin<T>(c, lc + key[j] - KWIN, X[j], U[j], &farp);
+                if (hb >= 0) atomicAdd(&hn[key[j] * NBIN + hb], 1);
+                if (farp) cl.fix_nx[g + key[j] - KWIN] = 1;
             }
-            lds_barrier();
+        }
+        if (gone) atomicAdd(&nout, gone);
+        // wave-level stable ranks, items in order: one ballot per near bin
+        // (wave-uniform counts cn), a loop over distinct keys for the farther
+        // ones (lane b of wc counts far bin b); the counts then go to
+        // wcnt[cb][w][b] for the cross-wave combine
+        int cn0 = 0, cn1 = 0, cn2 = 0;
+        int wc = 0;
 #pragma unroll
-            for (int j = 0; j < IT; ++j) { x[j] = px[j]; u[j] = pu[j]; v[j] = pv[j]; ww[j] = pw[j]; }
-        }
-        block_sum<NMB * 5>(mb, red);
-        const bool any_far = __syncthreads_or(far);
-        // rows of the predicted histogram: only new cells that received particles
-        for (int r = 0; r < NBIN; ++r) {
-            if (binbase[r] == bin0[r]) continue;
-            for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
-                const int v0 = hn[r * NBIN + t];
-                if (v0) {
-                    atomicAdd(&cl.hist_nx[(int64_t)(g + r - KWIN) * NBIN + t], v0);
-                    hn[r * NBIN + t] = 0;
-                }
+        for (int j = 0; j < IT; ++j) {
+            const int kk = key[j];
+            const uint64_t m0 = __ballot(kk == KWIN - 1);
+            const uint64_t m1 = __ballot(kk == KWIN);
+            const uint64_t m2 = __ballot(kk == KWIN + 1);
+            rk[j] = kk == KWIN ? cn1 + lane_rank(m1)
+                               : (kk == KWIN - 1 ? cn0 + lane_rank(m0) : cn2 + lane_rank(m2));
+            cn0 += __popcll(m0);
+            cn1 += __popcll(m1);
+            cn2 += __popcll(m2);
+            const bool kfar = kk >= 0 && (kk < KWIN - 1 || kk > KWIN + 1);
+            uint64_t rem = __ballot(kfar);
+            while (rem) {
+                const int leader = __ffsll((unsigned long long)rem) - 1;
+                const int v0 = __builtin_amdgcn_readlane(kk, leader);
+                const uint64_t mm = __ballot(kfar && kk == v0);
+                const int base = __builtin_amdgcn_readlane(wc, v0);
+                if (kfar && kk == v0) rk[j] = base + lane_rank(mm);
+                if (lane == v0) wc += __popcll(mm);
+                rem &= ~mm;
             }
         }
-        if (threadIdx.x == 0 && nout) {
-            atomicAdd((unsigned long long *)&d_nout[k], (unsigned long long)nout);
-            nout = 0;
-        }
-        // near sums of this source cell: slot m is destination g + m - MB
-        if (threadIdx.x < NMB * 5) {
-            double val = 0.0;
+        if (lane < NBIN) wcnt[cb][w][lane] = lane == KWIN ? cn1 : (lane == KWIN - 1 ? cn0 : (lane == KWIN + 1 ? cn2 : wc));
+        // the only barrier of the chunk: counts and bases are double-buffered
+        lds_barrier();
 #pragma unroll
-            for (int q = 0; q < NMB * 5; ++q)
-                if ((int)threadIdx.x == q) val = mb[q];
-            cl.mnear[(int64_t)g * (NMB * 5) + threadIdx.x] = val;
-        }
-        if (any_far) {
-            // a second pass per farther destination that received particles;
-            // the sums go to the destination's row, slot KWIN - dd
-            for (int bin = 0; bin < NBIN; ++bin) {
-                const int dd = bin - KWIN;
-                if ((dd >= -MB && dd <= MB) || binbase[bin] == bin0[bin]) continue;
-                double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-                for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                    T x = sg.x[b + i], u = sg.u[b + i];
-                    const int dest = Flight<T>::go(c, lc, x, u);
-                    if (dest >= 0 && dest - lc == dd) add_phi(a, u, sg.v[b + i], sg.w[b + i]);
-                }
-                block_sum<5>(a, red);
-                if (threadIdx.x < 5) {
-                    double val = 0.0;
+        for (int j = 0; j < IT; ++j) {
+            if (key[j] < 0) continue;
+            int r = binbase[cb][key[j]] + rk[j];
+            for (int w2 = 0; w2 < w; ++w2) r += wcnt[cb][w2][key[j]];
+            const int64_t pos = offb[key[j]] + r;
+            if (pos < cap) {
+                // 32-bit byte offset from the block-uniform destination base
+                const uint32_t bo = (uint32_t)(pos - lo) * (uint32_t)sizeof(T);
+                *(T *)((char *)ox + bo) = X[j];
+                *(T *)((char *)ou + bo) = U[j];
+                *(T *)((char *)ov + bo) = V[j];
+                *(T *)((char *)ow + bo) = W[j];
+            }
+            const int dd = key[j] - KWIN;
+            if (dd >= -MB && dd <= MB) {
+                const double du = U[j], dv = V[j], dw = W[j];
+                const double e2 = 0.5 * (du * du + dv * dv + dw * dw);
 #pragma unroll
-                    for (int q = 0; q < 5; ++q)
-                        if ((int)threadIdx.x == q) val = a[q];
-                    cl.mpart[((int64_t)(g + dd) * NBIN + (KWIN - dd)) * 5 + threadIdx.x] = val;
-                }
-                if (threadIdx.x == 0) cl.far_in[g + dd] = 1;
+                for (int m = 0; m < NMB; ++m)
+                    if (dd + MB == m) {
+                        mb[m * 5 + 0] += 1.0; mb[m * 5 + 1] += du; mb[m * 5 + 2] += dv; mb[m * 5 + 3] += dw;
+                        mb[m * 5 + 4] += e2;
+                    }
+            } else {
+                far = true;
             }
         }
-        __syncthreads();
+        for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
+            int s = 0;
+            for (int w2 = 0; w2 < nw; ++w2) s += wcnt[cb][w2][t];
+            binbase[cb ^ 1][t] = binbase[cb][t] + s;
+        }
+        cb ^= 1;
+    };
+
+    if (n > 0) {
+        T xa[IT], ua[IT], va[IT], wa[IT], xb[IT], ub[IT], vb[IT], wb[IT];
+        // the loads past the end read the last particle again (one cache line)
+        load(xa, ua, va, wa, 0);
+        for (int i0 = 0; i0 < n; i0 += 2 * CH) {
+            load(xb, ub, vb, wb, i0 + CH);
+            place(xa, ua, va, wa, i0);
+            if (i0 + CH >= n) break;
+            load(xa, ua, va, wa, i0 + 2 * CH);
+            place(xb, ub, vb, wb, i0 + CH);
+        }
+    }
+    block_sum<NMB * 5>(mb, red);
+    const bool any_far = __syncthreads_or(far);
+    // rows of the predicted histogram: only new cells that received particles
+    for (int r = 0; r < NBIN; ++r) {
+        if (binbase[cb][r] == bin0[r]) continue;
+        for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
+            const int v0 = hn[r * NBIN + t];
+            if (v0) atomicAdd(&cl.hist_nx[(int64_t)(g + r - KWIN) * NBIN + t], v0);
+        }
+    }
+    if (threadIdx.x == 0 && nout) atomicAdd((unsigned long long *)&d_nout[k], (unsigned long long)nout);
+    // near sums of this source cell: slot m is destination g + m - MB
+    if (threadIdx.x < NMB * 5) {
+        double val = 0.0;
+#pragma unroll
+        for (int q = 0; q < NMB * 5; ++q)
+            if ((int)threadIdx.x == q) val = mb[q];
+        cl.mnear[(int64_t)g * (NMB * 5) + threadIdx.x] = val;
+    }
+    if (any_far) {
+        // a second pass per farther destination that received particles; the
+        // sums go to the destination's row, slot KWIN - dd
+        for (int bin = 0; bin < NBIN; ++bin) {
+            const int dd = bin - KWIN;
+            if ((dd >= -MB && dd <= MB) || binbase[cb][bin] == bin0[bin]) continue;
+            double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                T x = gx[i], u = gu[i];
+                const int dest = Flight<T>::go(c, lc, x, u);
+                if (dest >= 0 && dest - lc == dd) add_phi(a, u, gv[i], gw[i]);
+            }
+            block_sum<5>(a, red);
+            if (threadIdx.x < 5) {
+                double val = 0.0;
+#pragma unroll
+                for (int q = 0; q < 5; ++q)
+                    if ((int)threadIdx.x == q) val = a[q];
+                cl.mpart[((int64_t)(g + dd) * NBIN + (KWIN - dd)) * 5 + threadIdx.x] = val;
+            }
+            if (threadIdx.x == 0) cl.far_in[g + dd] = 1;
+        }
     }
 }
 
@@ -1183,7 +1196,8 @@ __global__ void __launch_bounds__(512) k_moments(const DCase *__restrict__ cases
                                                   const int64_t *__restrict__ off, int G, int32_t *err)
 {
     __shared__ double red[5 * 16];
-    for (int g = blockIdx.x; g < G; g += gridDim.x) {
+    for (int gi = blockIdx.x; gi < G; gi += gridDim.x) {
+        const int g = cl.order[gi];
         const DCase &c = cases[cl.cell_case[g]];
         const int64_t b = off[g], e = off[g + 1];
         double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
