@@ -1,17 +1,19 @@
 #!/usr/bin/env python3
 """Throughput of the DUWP particle pipeline on one MI355X.
 
-Workload: Mach-8 argon shock, 4000 cells over 200 upstream mean free paths,
-5e7 simulated particles (synthetic, seeded).  The timed path stores particles
-in FP32 (position relative to its cell) with FP64 cell moments, NS wave update
-and absorption fractions; the plain FP64 path is timed on the same workload
-beside it.  A step is one full DUWP time step of every stage, replayed as a
-captured HIP graph.  Metric: particle-steps per second (particles alive at the
-start of each step, summed over the timed steps, over the wall time).
+Headline workload: Mach-8 argon shock, 4000 cells over 200 upstream mean free
+paths, 5e7 simulated particles (synthetic, seeded).  The timed path stores
+particles in FP32 (position relative to its cell) with FP64 cell moments, NS
+wave update and absorption fractions; the plain FP64 path is timed on the same
+workload beside it.  A step is one full DUWP time step of every stage, replayed
+as a captured HIP graph.  Metric: particle-steps per second (particles alive at
+the start of each step, summed over the timed steps, over the wall time).
 
-Also reported: the batched form (256 independent uneven shock and Sod cases in
-one context, one launch per stage), the roofline of the dominant kernel and the
-CPU oracle on the same state.  Prints one JSON line.
+Also reported (legs): the batched form (256 independent uneven shock and Sod
+cases in one context, against the plain FP64 path), the large near-continuum
+Mach-10 case (20000 cells, 1e9 particles, most mass in the wave part), the
+roofline of the dominant kernel, the step's effective bandwidth and the CPU
+oracle on the same state.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -26,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/sec on Mach-8 argon shock (FP32+FP64 vs FP64) + % HBM peak"
 HBM_PEAK_GBS = 8000.0
+LEGS = ("main", "fp64", "batched", "large", "cpu")
 
 # Algorithmic HBM bytes per particle of the particle-streaming kernels, per
 # element size s of the particle arrays (4 in FP32 mode, 8 in FP64 mode): the
@@ -36,13 +39,15 @@ BYTES_PER_PARTICLE = {
     "scatter": lambda s: 8 * s,
     "absorb_resample": lambda s: 8 * s,
 }
+# Algorithmic bytes of a whole step per particle when almost nothing is absorbed:
+# each particle's state (16 B in FP32 mode, 32 B in FP64 mode) is read and
+# written once by the cell pass and once by the sort, four times the state.
+STEP_BYTES_PER_PARTICLE = {"mixed": 64, "fp64": 128}
+KERNEL_SOURCES = ("duwp_kernels.hip", "duwp_physics.hpp", "duwp_device.hpp", "duwp_scan.hpp")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-KERNEL_SOURCES = ("duwp_kernels.hip", "duwp_physics.hpp", "duwp_device.hpp", "duwp_scan.hpp")
 
 
 def counted_traffic(kernel: str, workload: str):
@@ -93,6 +98,81 @@ def block_size(cases, precision, args):
     return (bc, "cache") if bc else (256, "default")
 
 
+def roofline_of(sim, profile_steps, workload):
+    """Dominant particle-streaming kernel: algorithmic bytes over its event-timed duration."""
+    kms = sim.profile(profile_steps)
+    prof_ps = sim.particle_steps(reset=True) / profile_steps
+    dom = max((k for k in kms if k in BYTES_PER_PARTICLE), key=lambda k: kms[k])
+    alg_bytes = BYTES_PER_PARTICLE[dom](4) * prof_ps
+    achieved = alg_bytes / (kms[dom] * 1e-3) / 1e9
+    kname = {"scatter": "k_scatter<float>", "absorb_resample": "k_absorb_resample<float>"}.get(dom)
+    tr = counted_traffic(kname, workload) if kname else None
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": tr[0] if tr else None,
+            "traffic_per_particle": round(tr[0] / tr[1], 2) if tr else None,
+            "bytes_per_particle": BYTES_PER_PARTICLE[dom](4), "particles_per_launch": int(prof_ps),
+            "kernel_ms": round(kms[dom], 4)}
+    return roof, {k: round(v, 4) for k, v in kms.items()}
+
+
+def leg_batched(args, graph, legs):
+    from paper_2305_12071_amd import duwp
+    from paper_2305_12071_amd import inputs as I
+    cases = I.batched_cases(args.batched_cases)
+    bcb, srcb = block_size(cases, duwp.MIXED, args)
+    ncell = sum(c.ncells for c in cases)
+    log(f"batched form: {len(cases)} cases, {ncell} cells, block_cells={bcb} ({srcb})")
+    sb, psb, dtb = run_path(cases, duwp.MIXED, args.batched_steps, 5, graph, block_cells=bcb)
+    out = {"value": psb / dtb, "unit": "particle-steps/s", "cases": len(cases), "cells": ncell,
+           "particles": sb.total_particles(), "steps": args.batched_steps,
+           "ms_per_step": dtb / args.batched_steps * 1e3,
+           "precision": "fp32 particles + fp64 cells", "block_cells": bcb}
+    out["kernels_ms"] = {k: round(v, 4) for k, v in sb.profile(args.profile_steps).items()}
+    sb.close()
+    log(f"  {out['value']:.4e} particle-steps/s, N={out['particles']}")
+    if "fp64" in legs:
+        bcf, srcf = block_size(cases, duwp.FP64, args)
+        log(f"  batched plain FP64 path, block_cells={bcf} ({srcf})")
+        sf, psf, dtf = run_path(cases, duwp.FP64, args.batched_steps, 5, graph, block_cells=bcf)
+        sf.close()
+        out["fp64_value"] = psf / dtf
+        out["mixed_over_fp64"] = out["value"] / out["fp64_value"]
+        log(f"  {out['fp64_value']:.4e} particle-steps/s")
+    if args.batched_vs_single:
+        # the same cases, one context each, plain FP64, one after another
+        tot_ps, tot_t = 0, 0.0
+        for c in cases:
+            s1, p1, t1 = run_path([c], duwp.FP64, args.batched_steps, 5, graph)
+            s1.close()
+            tot_ps += p1
+            tot_t += t1
+        out["one_by_one_fp64"] = tot_ps / tot_t
+        log(f"  one context per case, FP64: {out['one_by_one_fp64']:.4e} particle-steps/s")
+    return out
+
+
+def leg_large(args, graph):
+    from paper_2305_12071_amd import duwp
+    from paper_2305_12071_amd import inputs as I
+    c = I.mach10_large(n_kept=args.large_particles)
+    log(f"large near-continuum case: {c.name}, {args.large_particles:.0e} kept particles")
+    sl, psl, dtl = run_path([c], duwp.MIXED, args.large_steps, 3, graph)
+    out = {"value": psl / dtl, "unit": "particle-steps/s", "workload": c.name, "cells": c.ncells,
+           "particles": sl.total_particles(), "steps": args.large_steps,
+           "ms_per_step": dtl / args.large_steps * 1e3, "precision": "fp32 particles + fp64 cells"}
+    d = sl.diag()
+    out["absorbed_per_step"] = int(d["n_abs"].sum())
+    out["resampled_per_step"] = int(d["n_new"].sum())
+    out["collision_candidates_per_step"] = int(d["n_cand"].sum())
+    wave = sl.moments(0, duwp.M_PSI_W)[:, 0].sum() / sl.moments(0, duwp.M_PSI_T)[:, 0].sum()
+    out["wave_mass_fraction"] = round(float(wave), 4)
+    out["kernels_ms"] = {k: round(v, 3) for k, v in sl.profile(1).items()}
+    sl.close()
+    log(f"  {out['value']:.4e} particle-steps/s, {out['ms_per_step']:.1f} ms/step, N={out['particles']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,17 +180,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cells", type=int, default=4000)
     ap.add_argument("--particles", type=float, default=5e7)
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma list of " + ",".join(LEGS) + " (main is the headline value)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--block-cells", type=int, default=0, help="threads per block of the per-cell kernels")
     ap.add_argument("--autotune", action="store_true", help="time the block-size candidates first")
     ap.add_argument("--tune-cache", default=None, help="file --autotune writes (default: the package cache)")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
+    ap.add_argument("--no-fp64", action="store_true", help="leave out the fp64 leg")
+    ap.add_argument("--no-batched", action="store_true", help="leave out the batched leg")
+    ap.add_argument("--no-large", action="store_true", help="leave out the large leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="leave out the cpu leg")
     ap.add_argument("--batched-cases", type=int, default=256)
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--batched-vs-single", action="store_true",
-                    help="also time the batched cases one context per case")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+                    help="also time the batched cases one context per case (plain FP64)")
+    ap.add_argument("--large-particles", type=float, default=1e9)
+    ap.add_argument("--large-steps", type=int, default=5)
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -121,6 +206,11 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the pipeline would shard)", file=sys.stderr)
         sys.exit(2)
+    legs = [x for x in args.legs.split(",") if x]
+    for flag, leg in ((args.no_fp64, "fp64"), (args.no_batched, "batched"), (args.no_large, "large"),
+                      (args.no_cpu_baseline, "cpu")):
+        if flag and leg in legs:
+            legs.remove(leg)
 
     import torch
     from paper_2305_12071_amd import duwp
@@ -139,58 +229,45 @@ def main():
     case = I.mach8_shock(args.cells, args.particles)
     graph = not args.no_graph
 
-    bc, bc_src = block_size([case], duwp.MIXED, args)
-    log(f"mixed FP32+FP64 path: {case.name}, block_cells={bc} ({bc_src})")
-    sim, ps, dt = run_path([case], duwp.MIXED, args.steps, args.warmup, graph, block_cells=bc)
-    value = ps / dt
-    n_now = sim.total_particles()
-    log(f"  {args.steps} steps in {dt:.3f}s -> {value:.4e} particle-steps/s")
-
-    # per-kernel device time (HIP events on the library's stream, eager launches)
-    kms = sim.profile(args.profile_steps)
-    prof_ps = sim.particle_steps(reset=True) / args.profile_steps
-    dom = max((k for k in kms if k in BYTES_PER_PARTICLE), key=lambda k: kms[k])
-    alg_bytes = BYTES_PER_PARTICLE[dom](4) * prof_ps
-    achieved = alg_bytes / (kms[dom] * 1e-3) / 1e9
-    kname = {"scatter": "k_scatter<float>", "absorb_resample": "k_absorb_resample<float>"}.get(dom)
-    tr = counted_traffic(kname, case.name) if kname else None
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": tr[0] if tr else None,
-                "traffic_per_particle": round(tr[0] / tr[1], 2) if tr else None,
-                "bytes_per_particle": BYTES_PER_PARTICLE[dom](4), "particles_per_launch": int(prof_ps),
-                "kernel_ms": round(kms[dom], 4)}
-    log("  kernels (ms):", json.dumps({k: round(v, 4) for k, v in kms.items()}))
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        log(f"CPU oracle: {args.cpu_steps} steps from the GPU state after warm-up")
-        st = sim.get_state()
-        sim.close()
-        del sim
-        orc = O.Oracle(case, seed=1, case_id=0)
-        orc.set_state(st)
-        n0 = len(st["x"])
-        del st
-        t = time.perf_counter()
-        pst = 0
-        for _ in range(args.cpu_steps):
-            pst += orc.n
-            orc.step(1)
-        cdt = time.perf_counter() - t
-        cpu = {"value": pst / cdt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"{case.name}: {args.cpu_steps} FP64 oracle steps from the warmed-up state "
-                         f"({n0} particles), single thread, {cdt:.1f}s"}
-        log(f"  oracle {cpu['value']:.3e} particle-steps/s")
-        del orc
-    else:
-        sim.close()
-        del sim
-
-    fp64 = None
-    bc64 = None
-    if not args.no_fp64:
+    value = dt = None
+    n_now = None
+    roofline = kernels = cpu = fp64 = None
+    bc = bc64 = None
+    if "main" in legs:
+        bc, bc_src = block_size([case], duwp.MIXED, args)
+        log(f"mixed FP32+FP64 path: {case.name}, block_cells={bc} ({bc_src})")
+        sim, ps, dt = run_path([case], duwp.MIXED, args.steps, args.warmup, graph, block_cells=bc)
+        value = ps / dt
+        n_now = sim.total_particles()
+        log(f"  {args.steps} steps in {dt:.3f}s -> {value:.4e} particle-steps/s")
+        # per-kernel device time (HIP events on the library's stream, eager launches)
+        roofline, kernels = roofline_of(sim, args.profile_steps, case.name)
+        log("  kernels (ms):", json.dumps(kernels))
+        if "cpu" in legs:
+            from oracle import oracle as O
+            log(f"CPU oracle: {args.cpu_steps} steps from the GPU state after warm-up")
+            st = sim.get_state()
+            sim.close()
+            del sim
+            orc = O.Oracle(case, seed=1, case_id=0)
+            orc.set_state(st)
+            n0 = len(st["x"])
+            del st
+            t = time.perf_counter()
+            pst = 0
+            for _ in range(args.cpu_steps):
+                pst += orc.n
+                orc.step(1)
+            cdt = time.perf_counter() - t
+            cpu = {"value": pst / cdt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+                   "sample": f"{case.name}: {args.cpu_steps} FP64 oracle steps from the warmed-up state "
+                             f"({n0} particles), single thread, {cdt:.1f}s"}
+            log(f"  oracle {cpu['value']:.3e} particle-steps/s")
+            del orc
+        else:
+            sim.close()
+            del sim
+    if "fp64" in legs and "main" in legs:
         bc64, src64 = block_size([case], duwp.FP64, args)
         log(f"plain FP64 path, block_cells={bc64} ({src64})")
         s64, ps64, dt64 = run_path([case], duwp.FP64, args.steps, args.warmup, graph, block_cells=bc64)
@@ -198,29 +275,17 @@ def main():
         log(f"  {args.steps} steps in {dt64:.3f}s -> {fp64:.4e} particle-steps/s")
         s64.close()
 
-    batched = None
-    if not args.no_batched:
-        cases = I.batched_cases(args.batched_cases)
-        bcb, srcb = block_size(cases, duwp.MIXED, args)
-        ncell = sum(c.ncells for c in cases)
-        log(f"batched form: {len(cases)} cases, {ncell} cells, block_cells={bcb} ({srcb})")
-        sb, psb, dtb = run_path(cases, duwp.MIXED, args.batched_steps, 5, graph, block_cells=bcb)
-        batched = {"value": psb / dtb, "unit": "particle-steps/s", "cases": len(cases), "cells": ncell,
-                   "particles": sb.total_particles(), "steps": args.batched_steps,
-                   "ms_per_step": dtb / args.batched_steps * 1e3,
-                   "precision": "fp32 particles + fp64 cells", "block_cells": bcb}
-        batched["kernels_ms"] = {k: round(v, 4) for k, v in sb.profile(args.profile_steps).items()}
-        sb.close()
-        log(f"  {batched['value']:.4e} particle-steps/s, N={batched['particles']}")
-        if args.batched_vs_single:
-            tot_ps, tot_t = 0, 0.0
-            for c in cases:
-                s1, p1, t1 = run_path([c], duwp.MIXED, args.batched_steps, 5, graph, block_cells=bcb)
-                s1.close()
-                tot_ps += p1
-                tot_t += t1
-            batched["one_context_per_case"] = tot_ps / tot_t
-            log(f"  one context per case: {batched['one_context_per_case']:.4e} particle-steps/s")
+    extra = {}
+    for leg, fn in (("batched", lambda: leg_batched(args, graph, legs)), ("large", lambda: leg_large(args, graph))):
+        if leg not in legs:
+            extra[leg] = None
+            continue
+        try:
+            extra[leg] = fn()
+        except Exception as e:        # a failed extra leg is reported, the headline stays
+            log(f"  {leg} leg failed: {e!r}")
+            extra[leg] = {"error": repr(e)}
+        torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC,
@@ -229,7 +294,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": dt / args.steps * 1e3 if dt else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -238,10 +303,17 @@ def main():
         "config": {"workload": case.name, "cells": case.ncells, "particles": n_now,
                    "particles_target": args.particles, "precision": "fp32 particles + fp64 cells",
                    "graph": graph, "gas": "argon VHS omega=0.81", "mach": 8, "block_cells": bc},
+        "step_effective": None if value is None else {
+            "bytes_per_particle_step": STEP_BYTES_PER_PARTICLE["mixed"],
+            "gbs": round(STEP_BYTES_PER_PARTICLE["mixed"] * value / 1e9, 1),
+            "frac": round(STEP_BYTES_PER_PARTICLE["mixed"] * value / 1e9 / HBM_PEAK_GBS, 4),
+            "fp64_gbs": round(STEP_BYTES_PER_PARTICLE["fp64"] * fp64 / 1e9, 1) if fp64 else None},
         "fp64_value": fp64,
-        "mixed_over_fp64": (value / fp64) if fp64 else None,
+        "mixed_over_fp64": (value / fp64) if (fp64 and value) else None,
         "fp64_block_cells": bc64,
-        "batched": batched,
+        "kernels_ms": kernels,
+        "batched": extra["batched"],
+        "large": extra["large"],
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

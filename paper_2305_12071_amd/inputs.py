@@ -204,6 +204,23 @@ def mach8_shock(ncells: int = 4000, n_particles: float = 5e7) -> Case:
                        name=f"mach8_c{ncells}")
 
 
+def mach10_large(ncells: int = 20000, n_kept: float = 1e9, cell_kn: float = 1e-3,
+                 kept_fraction: float = 0.028) -> Case:
+    """Mach-10 argon shock in the near-continuum regime, most of the mass in the wave part.
+
+    Cells are 1/cell_kn upstream mean free paths wide (the cell-Knudsen reading of
+    "Kn = 1e-3"): 20000 cells over 2e7 mean free paths.  The particle weight puts
+    about n_kept particles in the domain when they carry the fraction kept_fraction
+    of the mass; 0.028 is the mass-weighted share that the absorbed fraction of the
+    paper's Eq. p leaves to particles at the two reservoir states of this case
+    (about 0.09 upstream and 0.012 downstream).
+    """
+    c = argon_shock(10.0, ncells, ncells / cell_kn, n_kept, name=f"mach10_c{ncells}")
+    c.m_particle = kept_fraction * c.domain_mass() / n_kept
+    c.capacity = int(1.6 * n_kept) + 4096
+    return c
+
+
 def batched_cases(n: int = 256, seed: int = 2305, ppc_scale: float = 1.0):
     """Independent uneven cases: half shocks (Mach ~ U[1.2,10]), half Sod (Kn log-U[1e-4,1]).
 
