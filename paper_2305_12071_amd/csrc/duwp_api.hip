@@ -138,6 +138,9 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &c.d_coll, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.cbase, 8 * (size_t)(G + 1)));
     TRY(dalloc(ctx, &c.cr_seen, 8 * (size_t)G));
+    TRY(dalloc(ctx, &c.ncand_w, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.big_list, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.nbig, 4));
     ctx->items_cap = std::max<int64_t>(1 << 20, 2 * (int64_t)G);
     TRY(dalloc(ctx, &ctx->item_cell, 4 * (size_t)ctx->items_cap));
     TRY(dalloc(ctx, &ctx->d_items, 16));
@@ -206,6 +209,7 @@ duwp_status upload_initial(duwp_ctx *ctx)
     HIP_OK(hipMemsetAsync(ctx->cl.cr_seen, 0, 8 * (size_t)G, s));
     HIP_OK(hipMemsetAsync(ctx->cl.mpart, 0, 8 * 5 * (size_t)G * duwp::NBIN, s));
     HIP_OK(hipMemsetAsync(ctx->cl.far_in, 0, 4 * (size_t)G, s));
+    HIP_OK(hipMemsetAsync(ctx->cl.nbig, 0, 4, s));
     for (int p = 0; p < 2; ++p) HIP_OK(hipMemsetAsync(ctx->off[p], 0, 8 * (size_t)(G + 1), s));
     HIP_OK(hipMemsetAsync(ctx->d_step, 0, 4, s));
     HIP_OK(hipMemsetAsync(ctx->d_err, 0, 4, s));
@@ -387,6 +391,7 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
             ncu = 256;
         ctx->coll_blocks = 4 * ncu;
+        ctx->big_blocks = ncu;
     }
     duwp_status s = alloc_all(ctx);
     if (s == DUWP_OK) s = upload_initial(ctx);

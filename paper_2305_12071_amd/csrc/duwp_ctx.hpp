@@ -67,6 +67,7 @@ struct duwp_ctx {
     int64_t *d_items = nullptr;    // [2] number of collision work items, candidates per item
     int64_t items_cap = 0;
     int coll_blocks = 0;
+    int big_blocks = 0;            // grid of the block-per-cell collision kernel
     int64_t *d_psteps = nullptr;   // particle-steps since init or the last reset
 
     hipGraphExec_t graph[2] = {nullptr, nullptr};

@@ -9,6 +9,8 @@ namespace duwp {
 constexpr int KWIN = 16;             // a particle may move at most KWIN cells per step
 constexpr int NBIN = 2 * KWIN + 1;   // destination bins per source cell
 constexpr int WAVE = 64;
+constexpr int BIG_N = 4096;          // a cell with at least this many particles ...
+constexpr int BIG_M = 4096;          // ... and candidates collides in the block kernel
 
 // Philox counter tags: one per kind of random draw.
 enum : uint32_t { TAG_CLS = 1, TAG_RCNT = 2, TAG_RVEL = 3, TAG_NCNT = 4, TAG_PAIR = 5,
@@ -45,7 +47,10 @@ struct Cells {
     int64_t *seg;       // [G] start of the cell's intermediate segment
     int32_t *seg_stg;   // [G] 1: segment in the staging buffer, 0: in place in the canonical buffer
     int32_t *d_abs, *d_new, *d_cand, *d_coll;  // [G] diagnostics; d_cand is also the collide work size
+    int32_t *ncand_w;   // [G] candidates in the wave kernel's list (0 for cells of the block kernel)
     int64_t *cbase;     // [G+1] first collision candidate of each cell in the step's candidate list
+    int32_t *big_list;  // [G] cells that collide in the block kernel (unordered)
+    int32_t *nbig;      // [1] their number (cleared at the end of each step)
     uint64_t *cr_seen;  // [G] largest relative speed seen this step (bits of a non-negative double)
     int32_t *hist;      // [G*NBIN] destination histogram of this step, then scatter bases
     int32_t *hist_nx;   // [G*NBIN] histogram predicted for the next step
@@ -117,6 +122,11 @@ __device__ __forceinline__ uint64_t mulhi64(uint64_t r, uint64_t n) { return __u
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+// number of set bits of m below this lane
+__device__ __forceinline__ int lane_rank_lt(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
 
 __device__ __forceinline__ double wave_sum(double v)
 {

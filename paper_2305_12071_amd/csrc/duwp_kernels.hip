@@ -101,32 +101,43 @@ __global__ void __launch_bounds__(256) k_cellstate(const DCase *__restrict__ cas
         cnt = wave_sum_i(cnt);
         if (lane == l) nabs = cnt;
     }
-    if (!in) return;
     const int lc = g - c.cell_base;
-    int32_t nnew = 0;
-    if (ok) {
-        const double Mw = c.dx * cl.psi_w[(int64_t)g * 5 + 0];
-        const U4 r = draw(c, step, (uint32_t)lc, 0, TAG_RCNT, 0);
-        double nf = floor((1.0 - P) * Mw / c.m_p + u01(r.a));
-        const double capn = floor((Mw > 0.0 ? Mw : 0.0) / c.m_p);
-        if (nf > capn) nf = capn;
-        if (nf < 0.0) nf = 0.0;
-        if (nf > 2.0e9) { atomicOr(err, ERR_CAPACITY); nf = 0.0; }
-        nnew = (int32_t)nf;
+    int32_t nnew = 0, N = 0, M = 0, ns = 0;
+    if (in) {
+        if (ok) {
+            const double Mw = c.dx * cl.psi_w[(int64_t)g * 5 + 0];
+            const U4 r = draw(c, step, (uint32_t)lc, 0, TAG_RCNT, 0);
+            double nf = floor((1.0 - P) * Mw / c.m_p + u01(r.a));
+            const double capn = floor((Mw > 0.0 ? Mw : 0.0) / c.m_p);
+            if (nf > capn) nf = capn;
+            if (nf < 0.0) nf = 0.0;
+            if (nf > 2.0e9) { atomicOr(err, ERR_CAPACITY); nf = 0.0; }
+            nnew = (int32_t)nf;
+        }
+        ns = (int32_t)(e - b) - nabs;
+        N = ns + nnew;
+        // NTC candidate count (Appendix A) over the collision share of the step
+        if (ok && N >= 2) {
+            const double dtc = c.full_dt ? c.dt : (1.0 - P) * c.dt;
+            const double cm = cl.cr_max[g];
+            const double Mr = 0.5 * (double)(N - 1) * c.coll_k * W[0] * pow(c.c_ref / cm, 2.0 * c.ups) * cm * dtc;
+            const U4 r = draw(c, step, (uint32_t)lc, 0, TAG_NCNT, 0);
+            double Mf = floor(Mr + u01(r.a));
+            if (Mf > 2.0e9) { atomicOr(err, ERR_CAPACITY); Mf = 0.0; }
+            M = (int32_t)Mf;
+        }
     }
-    const int32_t ns = (int32_t)(e - b) - nabs;
-    const int32_t N = ns + nnew;
-    // NTC candidate count (Appendix A) over the collision share of the step
-    int32_t M = 0;
-    if (ok && N >= 2) {
-        const double dtc = c.full_dt ? c.dt : (1.0 - P) * c.dt;
-        const double cm = cl.cr_max[g];
-        const double Mr = 0.5 * (double)(N - 1) * c.coll_k * W[0] * pow(c.c_ref / cm, 2.0 * c.ups) * cm * dtc;
-        const U4 r = draw(c, step, (uint32_t)lc, 0, TAG_NCNT, 0);
-        double Mf = floor(Mr + u01(r.a));
-        if (Mf > 2.0e9) { atomicOr(err, ERR_CAPACITY); Mf = 0.0; }
-        M = (int32_t)Mf;
+    // cells with many particles and many candidates collide one block each
+    // (k_collide_big); the others go to the wave kernel's candidate list
+    const bool big = in && N >= BIG_N && M >= BIG_M;
+    const uint64_t bm = __ballot(big);
+    if (bm) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(cl.nbig, __popcll(bm));
+        base = __shfl(base, 0, WAVE);
+        if (big) cl.big_list[base + lane_rank_lt(bm)] = g;
     }
+    if (!in) return;
     cl.fix_nx[g] = 0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) cl.wt[(int64_t)g * 5 + i] = W[i];
@@ -140,6 +151,7 @@ __global__ void __launch_bounds__(256) k_cellstate(const DCase *__restrict__ cas
     cl.seg_stg[g] = touched ? 1 : 0;
     cl.inj_cnt[g] = 0;
     cl.d_cand[g] = M;
+    cl.ncand_w[g] = big ? 0 : M;
     cl.d_coll[g] = 0;
     if (lc == 0) {
         d_nout[k] = 0;
@@ -525,6 +537,227 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
 }
 
 // ---------------------------------------------------------------------------
+// 4b. NTC / VHS collisions of cells with many particles and candidates: one
+// block per cell, BigCfg<T>::B candidates at a time (one per thread).
+//
+// Few cells are in flight at once (one block per compute unit), so the random
+// pair accesses of a cell stay in the caches.  For each of its particles a
+// candidate needs the last earlier candidate of the chunk that touched it: an
+// LDS hash table keyed exactly by particle index records up to BIG_LIST
+// candidates per particle, and the largest one below the candidate's own index
+// is its predecessor.  Candidates then run in block-wide rounds once their (at
+// most two) predecessors have run, taking velocities from the predecessors'
+// LDS slots.  A particle drawn by more than BIG_LIST candidates of one chunk
+// (rare) sends that chunk through a serial path.  Histogram moves are summed in
+// LDS and added once per cell.
+// ---------------------------------------------------------------------------
+constexpr int BIG_SLOTS = 4096;   // hash slots: at least twice the particles of a chunk
+constexpr int BIG_LIST = 4;
+
+template <typename T>
+struct BigCfg {
+    static constexpr int B = sizeof(T) == 4 ? 1024 : 512;
+};
+
+__device__ __forceinline__ int big_insert(uint32_t *hkey, int *hcnt, uint16_t (*hlst)[BIG_LIST], uint32_t p,
+                                          int t, int *ovf)
+{
+    uint32_t h = (p * 0x9E3779B1u) >> (32 - 12);
+    while (true) {
+        const uint32_t prev = atomicCAS(&hkey[h], 0xffffffffu, p);
+        if (prev == 0xffffffffu || prev == p) break;
+        h = (h + 1) & (BIG_SLOTS - 1);
+    }
+    const int k = atomicAdd(&hcnt[h], 1);
+    if (k < BIG_LIST) hlst[h][k] = (uint16_t)t;
+    else *ovf = 1;
+    return (int)h;
+}
+
+// last candidate before t that touched the particle of slot s: its index, and
+// 0 or 3 for its first or second particle
+__device__ __forceinline__ void big_pred(const int *hcnt, const uint16_t (*hlst)[BIG_LIST], const uint32_t *ci,
+                                         int s, uint32_t p, int t, int &pl, int &po)
+{
+    const int c = min(hcnt[s], BIG_LIST);
+    int best = -1;
+    for (int k = 0; k < c; ++k) {
+        const int l = hlst[s][k];
+        if (l < t && l > best) best = l;
+    }
+    pl = best;
+    po = (best >= 0 && ci[best] != p) ? 3 : 0;
+}
+
+template <typename T>
+__device__ __forceinline__ void big_pair(const DCase &c, uint32_t step, int lc, uint32_t q, int32_t N,
+                                         uint32_t &i, uint32_t &j, double &u2, double &u3, double &u4)
+{
+    const U4 ra = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 0);
+    const U4 rb = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 1);
+    const uint64_t r0 = ((uint64_t)ra.a << 32) | ra.b;
+    const uint64_t r1 = ((uint64_t)ra.c << 32) | ra.d;
+    i = (uint32_t)mulhi64(r0, (uint64_t)N);
+    j = (uint32_t)mulhi64(r1, (uint64_t)(N - 1));
+    if (j >= i) j += 1;
+    u2 = u01(rb.a); u3 = u01(rb.b); u4 = u01(rb.c);
+}
+
+// move the pair between destination bins of this step's histogram (summed in hd)
+template <typename T>
+__device__ __forceinline__ void big_bins(const DCase &c, int lc, T xi, T ui0, T ui, T xj, T uj0, T uj, int *hd,
+                                         bool &far)
+{
+    bool f0 = false;
+    const int a0 = flight_bin<T>(c, lc, xi, ui0, &f0), a1 = flight_bin<T>(c, lc, xi, ui, &far);
+    const int b0 = flight_bin<T>(c, lc, xj, uj0, &f0), b1 = flight_bin<T>(c, lc, xj, uj, &far);
+    if (a0 != a1) {
+        if (a0 >= 0) atomicSub(&hd[a0], 1);
+        if (a1 >= 0) atomicAdd(&hd[a1], 1);
+    }
+    if (b0 != b1) {
+        if (b0 >= 0) atomicSub(&hd[b0], 1);
+        if (b1 >= 0) atomicAdd(&hd[b1], 1);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__restrict__ cases, Cells cl,
+                                                               Soa<T> src, Soa<T> stg,
+                                                               const uint32_t *__restrict__ d_step, int64_t cap)
+{
+    constexpr int B = BigCfg<T>::B;
+    constexpr int NW = B / WAVE;
+    __shared__ uint32_t hkey[BIG_SLOTS];
+    __shared__ int hcnt[BIG_SLOTS];
+    __shared__ uint16_t hlst[BIG_SLOTS][BIG_LIST];
+    __shared__ uint32_t ci[B];
+    __shared__ int done[B];
+    __shared__ T fwd[6][B];
+    __shared__ int hd[NBIN];
+    __shared__ double redd[NW];
+    __shared__ int redi[NW];
+    __shared__ int ovf[2];           // by chunk parity
+    const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
+    const uint32_t step = *d_step;
+    const int nbig = *cl.nbig;
+    for (int s = t; s < BIG_SLOTS; s += B) { hkey[s] = 0xffffffffu; hcnt[s] = 0; }
+    for (int e = blockIdx.x; e < nbig; e += gridDim.x) {
+        const int g = cl.big_list[e];
+        const int k = cl.cell_case[g];
+        const DCase &c = cases[k];
+        const int lc = g - c.cell_base;
+        const int32_t N = cl.n_int[g];
+        const int64_t M = cl.d_cand[g];
+        int64_t sb;
+        const Soa<T> sg = segment(cl, g, src, stg, sb);
+        if (sb + N > cap) continue;   // capacity overflow, already reported (block-uniform)
+        T *pu = sg.u + sb, *pv = sg.v + sb, *pw = sg.w + sb;
+        const T *px = sg.x + sb;
+        const double cm = cl.cr_max[g];
+        const double aexp = 1.0 - 2.0 * c.ups;
+        if (t < NBIN) hd[t] = 0;
+        if (t < 2) ovf[t] = 0;
+        __syncthreads();
+        double seen = 0.0;
+        int acc = 0;
+        bool far = false;
+        int par = 0;
+        for (int64_t q0 = 0; q0 < M; q0 += B, par ^= 1) {
+            const int64_t q = q0 + t;
+            const bool act = q < M;
+            uint32_t i = 0, j = 0;
+            double u2 = 0.0, u3 = 0.0, u4 = 0.0;
+            T xi = 0, ui = 0, vi = 0, wi = 0, xj = 0, uj = 0, vj = 0, wj = 0;
+            int si = 0, sj = 0;
+            if (act) {
+                big_pair<T>(c, step, lc, (uint32_t)q, N, i, j, u2, u3, u4);
+                xi = px[i]; ui = pu[i]; vi = pv[i]; wi = pw[i];
+                xj = px[j]; uj = pu[j]; vj = pv[j]; wj = pw[j];
+                si = big_insert(hkey, hcnt, hlst, i, t, &ovf[par]);
+                sj = big_insert(hkey, hcnt, hlst, j, t, &ovf[par]);
+            }
+            ci[t] = i;
+            done[t] = act ? 0 : 1;
+            __syncthreads();
+            const bool serial = ovf[par] != 0;
+            // the next chunk's flag: its last readers were in the previous chunk
+            if (t == 0) ovf[par ^ 1] = 0;
+            if (serial) {
+                // serial path: the chunk's candidates one after another in thread 0,
+                // reading and writing the particles in memory
+                if (t == 0) {
+                    const int nq = (int)min((int64_t)B, M - q0);
+                    for (int l = 0; l < nq; ++l) {
+                        uint32_t a, bq;
+                        double v2, v3, v4;
+                        big_pair<T>(c, step, lc, (uint32_t)(q0 + l), N, a, bq, v2, v3, v4);
+                        T ua = pu[a], va = pv[a], wa = pw[a], ub = pu[bq], vb = pv[bq], wb = pw[bq];
+                        const T ua0 = ua, ub0 = ub;
+                        if (collide_vals<T>(ua, va, wa, ub, vb, wb, cm, aexp, v2, v3, v4, seen)) {
+                            ++acc;
+                            pu[a] = ua; pv[a] = va; pw[a] = wa;
+                            pu[bq] = ub; pv[bq] = vb; pw[bq] = wb;
+                            big_bins<T>(c, lc, px[a], ua0, ua, px[bq], ub0, ub, hd, far);
+                        }
+                    }
+                }
+            } else {
+                int pi = -1, pj = -1, oi = 0, oj = 0;
+                if (act) {
+                    big_pred(hcnt, hlst, ci, si, i, t, pi, oi);
+                    big_pred(hcnt, hlst, ci, sj, j, t, pj, oj);
+                }
+                // block-wide rounds: a candidate runs once its predecessors have run
+                bool mine = act;
+                while (true) {
+                    const bool ready = mine && (pi < 0 || done[pi]) && (pj < 0 || done[pj]);
+                    __syncthreads();
+                    if (ready) {
+                        if (pi >= 0) { ui = fwd[oi][pi]; vi = fwd[oi + 1][pi]; wi = fwd[oi + 2][pi]; }
+                        if (pj >= 0) { uj = fwd[oj][pj]; vj = fwd[oj + 1][pj]; wj = fwd[oj + 2][pj]; }
+                        const T ui0 = ui, uj0 = uj;
+                        if (collide_vals<T>(ui, vi, wi, uj, vj, wj, cm, aexp, u2, u3, u4, seen)) {
+                            ++acc;
+                            pu[i] = ui; pv[i] = vi; pw[i] = wi;
+                            pu[j] = uj; pv[j] = vj; pw[j] = wj;
+                            big_bins<T>(c, lc, xi, ui0, ui, xj, uj0, uj, hd, far);
+                        }
+                        fwd[0][t] = ui; fwd[1][t] = vi; fwd[2][t] = wi;
+                        fwd[3][t] = uj; fwd[4][t] = vj; fwd[5][t] = wj;
+                        done[t] = 1;
+                        mine = false;
+                    }
+                    if (!__syncthreads_or(mine)) break;
+                }
+            }
+            // empty the table for the next chunk; make this chunk's stores visible to it
+            if (act) {
+                hkey[si] = 0xffffffffu; hcnt[si] = 0;
+                hkey[sj] = 0xffffffffu; hcnt[sj] = 0;
+            }
+            __threadfence_block();
+            __syncthreads();
+        }
+        // per-cell results
+        int a = wave_sum_i(acc);
+        double m = wave_max(seen);
+        if (lane == 0) { redi[wv] = a; redd[wv] = m; }
+        const bool anyfar = __syncthreads_or(far);
+        if (t == 0) {
+            int sa = 0;
+            double sm = 0.0;
+            for (int w2 = 0; w2 < NW; ++w2) { sa += redi[w2]; sm = fmax(sm, redd[w2]); }
+            cl.d_coll[g] = sa;
+            if (sm > cm) cl.cr_seen[g] = (uint64_t)__double_as_longlong(sm);
+            if (anyfar) cl.fix[g] = 1;
+        }
+        if (t < NBIN && hd[t]) cl.hist[(int64_t)g * NBIN + t] += hd[t];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 5a. Reservoir injection candidates, in parallel over (case, side, slot):
 // a particle sampled in the ghost slab beyond a reservoir side, streamed over
 // dt; it enters when it ends inside the domain.
@@ -839,11 +1072,6 @@ __device__ __forceinline__ void add_phi(double (&a)[5], double u, double v, doub
     a[4] += 0.5 * (u * u + v * v + w * w);
 }
 
-// number of set bits of m below this lane
-__device__ __forceinline__ int lane_rank(uint64_t m)
-{
-    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
 
 template <typename T>
 __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
@@ -954,8 +1182,8 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
             const uint64_t m0 = __ballot(kk == KWIN - 1);
             const uint64_t m1 = __ballot(kk == KWIN);
             const uint64_t m2 = __ballot(kk == KWIN + 1);
-            rk[j] = kk == KWIN ? cn1 + lane_rank(m1)
-                               : (kk == KWIN - 1 ? cn0 + lane_rank(m0) : cn2 + lane_rank(m2));
+            rk[j] = kk == KWIN ? cn1 + lane_rank_lt(m1)
+                               : (kk == KWIN - 1 ? cn0 + lane_rank_lt(m0) : cn2 + lane_rank_lt(m2));
             cn0 += __popcll(m0);
             cn1 += __popcll(m1);
             cn2 += __popcll(m2);
@@ -966,7 +1194,7 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
                 const int v0 = __builtin_amdgcn_readlane(kk, leader);
                 const uint64_t mm = __ballot(kfar && kk == v0);
                 const int base = __builtin_amdgcn_readlane(wc, v0);
-                if (kfar && kk == v0) rk[j] = base + lane_rank(mm);
+                if (kfar && kk == v0) rk[j] = base + lane_rank_lt(mm);
                 if (lane == v0) wc += __popcll(mm);
                 rem &= ~mm;
             }
@@ -1218,11 +1446,13 @@ __global__ void __launch_bounds__(512) k_moments(const DCase *__restrict__ cases
 }
 
 // closes the step: particle-steps of this step (particles alive at its start), step index
-__global__ void k_finish(uint32_t *d_step, const int64_t *__restrict__ off, int G, int64_t *d_psteps)
+__global__ void k_finish(uint32_t *d_step, const int64_t *__restrict__ off, int G, int64_t *d_psteps,
+                         int32_t *nbig)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         *d_psteps += off[G];
         *d_step += 1;
+        *nbig = 0;
     }
 }
 
@@ -1308,11 +1538,13 @@ static void step_impl(duwp_ctx *ctx)
     if (fork) (void)hipEventRecord(ctx->ev_join, s2);
     {
         Mark m(ctx, "collide");
-        enqueue_scan(ctx, ctx->cl.d_cand, ctx->cl.cbase, ctx->d_total + 2, INT64_MAX);
+        enqueue_scan(ctx, ctx->cl.ncand_w, ctx->cl.cbase, ctx->d_total + 2, INT64_MAX);
         hipLaunchKernelGGL(k_items, dim3((G + 1 + 255) / 256), dim3(256), 0, st, ctx->cl.cbase, G, ctx->item_cell,
                            ctx->d_items, ctx->items_cap);
         hipLaunchKernelGGL(k_collide<T>, dim3(ctx->coll_blocks), dim3(64 * COLL_WPB), 0, st, ctx->d_cases,
                            cl, src, stg, ctx->d_step, G, ctx->cap, ctx->d_err, ctx->item_cell, ctx->d_items);
+        hipLaunchKernelGGL(k_collide_big<T>, dim3(ctx->big_blocks), dim3(BigCfg<T>::B), 0, st, ctx->d_cases,
+                           cl, src, stg, ctx->d_step, ctx->cap);
     }
     {
         Mark m(ctx, "hist_fix");
@@ -1349,7 +1581,8 @@ static void step_impl(duwp_ctx *ctx)
     }
     {
         Mark m(ctx, "finish");
-        hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, ctx->d_step, ctx->off[p], G, ctx->d_psteps);
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, ctx->d_step, ctx->off[p], G, ctx->d_psteps,
+                           ctx->cl.nbig);
     }
 }
 

@@ -139,3 +139,48 @@ def test_mach10_full_size_mixed_bookkeeping():
     wave = g.moments(0, duwp.M_PSI_W)[:, 0].sum() / m1
     assert 0.9 < wave < 0.99
     g.close()
+
+
+def _step_from_gpu_state(c, warm, seed, prec=duwp.FP64):
+    g = duwp.Sim(c, seed=seed, precision=prec, use_graph=True)
+    g.step(warm)
+    st = g.get_state()
+    o = O.Oracle(c, seed=seed, case_id=0)
+    o.set_state(st)
+    del st
+    g.step(1)
+    o.step(1)
+    return g, o
+
+
+def test_big_cells_collide_in_block_kernel_and_match_oracle():
+    """Cells of ~5e4 particles and ~6e4 candidates (the near-continuum Mach-10 case
+    on 200 cells) collide in the block-per-cell kernel; one FP64 step matches the
+    oracle."""
+    c = I.mach10_large(ncells=200, n_kept=1e7)
+    _say("big cells: mach10 on 200 cells, 1e7 particles")
+    g, o = _step_from_gpu_state(c, 2, seed=5)
+    d = g.diag()
+    assert (d["n_cand"] >= 4096).mean() > 0.9
+    compare_diag(d, o.diag(), "mach10_c200")
+    compare_states(g.get_state(), o.get_state(), label="mach10_c200", psi_t=o.cells()["psi_t"])
+    g.close()
+
+
+def test_big_cells_with_repeated_particles_match_oracle():
+    """Cells of ~4500 particles with ~5 candidates per particle: a particle is often
+    drawn more than four times within one chunk of the block kernel, which then runs
+    that chunk serially.  Three FP64 steps match the oracle."""
+    c = I.box(4, 1.0, 1.0, 18000.0, 4.0, name="box_big_repeat")
+    c.dsmc_full_dt = 1
+    _say("big cells with repeats")
+    g = duwp.Sim(c, seed=2, precision=duwp.FP64, use_graph=True)
+    o = O.Oracle(c, seed=2, case_id=0)
+    for s in range(3):
+        g.step(1)
+        o.step(1)
+        d = g.diag()
+        compare_diag(d, o.diag(), f"box_big:{s}")
+    assert (d["n_cand"] >= 4096).all() and (g.get_state()["off"][1:] - g.get_state()["off"][:-1] >= 4096).all()
+    compare_states(g.get_state(), o.get_state(), label="box_big", psi_t=o.cells()["psi_t"])
+    g.close()
