@@ -141,6 +141,8 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &c.ncand_w, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.big_list, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.nbig, 4));
+    TRY(dalloc(ctx, &c.big_base, 8 * (size_t)G));
+    TRY(dalloc(ctx, &ctx->pk, 4 * es * (size_t)ctx->cap));
     ctx->items_cap = std::max<int64_t>(1 << 20, 2 * (int64_t)G);
     TRY(dalloc(ctx, &ctx->item_cell, 4 * (size_t)ctx->items_cap));
     TRY(dalloc(ctx, &ctx->d_items, 16));

@@ -68,6 +68,7 @@ struct duwp_ctx {
     int64_t items_cap = 0;
     int coll_blocks = 0;
     int big_blocks = 0;            // grid of the block-per-cell collision kernel
+    void *pk = nullptr;            // packed (x,u,v,w) records of the cells that kernel works on
     int64_t *d_psteps = nullptr;   // particle-steps since init or the last reset
 
     hipGraphExec_t graph[2] = {nullptr, nullptr};

@@ -559,6 +559,30 @@ struct BigCfg {
     static constexpr int B = sizeof(T) == 4 ? 1024 : 512;
 };
 
+// (x, u, v, w) of one particle in one 16- or 32-byte record: a random access to
+// a particle touches one cache line instead of four
+template <typename T>
+struct alignas(4 * sizeof(T) > 16 ? 16 : 4 * sizeof(T)) P4 {
+    T x, u, v, w;
+};
+
+// start of each listed big cell's packed region: prefix of the cells' particle counts
+__global__ void __launch_bounds__(1024) k_big_bases(Cells cl)
+{
+    __shared__ int64_t lds[16];
+    const int nbig = *cl.nbig;
+    int64_t carry = 0;
+    for (int e0 = 0; e0 < nbig; e0 += blockDim.x) {
+        const int e = e0 + threadIdx.x;
+        const int64_t v = e < nbig ? (int64_t)cl.n_int[cl.big_list[e]] : 0;
+        int64_t tot;
+        const int64_t ex = block_exclusive_scan64(v, lds, &tot);
+        if (e < nbig) cl.big_base[e] = carry + ex;
+        carry += tot;
+        __syncthreads();
+    }
+}
+
 __device__ __forceinline__ int big_insert(uint32_t *hkey, int *hcnt, uint16_t (*hlst)[BIG_LIST], uint32_t p,
                                           int t, int *ovf)
 {
@@ -623,7 +647,7 @@ __device__ __forceinline__ void big_bins(const DCase &c, int lc, T xi, T ui0, T 
 
 template <typename T>
 __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__restrict__ cases, Cells cl,
-                                                               Soa<T> src, Soa<T> stg,
+                                                               Soa<T> src, Soa<T> stg, P4<T> *__restrict__ pk,
                                                                const uint32_t *__restrict__ d_step, int64_t cap)
 {
     constexpr int B = BigCfg<T>::B;
@@ -651,9 +675,14 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
         const int64_t M = cl.d_cand[g];
         int64_t sb;
         const Soa<T> sg = segment(cl, g, src, stg, sb);
-        if (sb + N > cap) continue;   // capacity overflow, already reported (block-uniform)
+        const int64_t pb = cl.big_base[e];
+        if (sb + N > cap || pb + N > cap) continue;   // capacity overflow, already reported (block-uniform)
         T *pu = sg.u + sb, *pv = sg.v + sb, *pw = sg.w + sb;
         const T *px = sg.x + sb;
+        // the cell's particles as (x,u,v,w) records for the random pair accesses
+        P4<T> *P = pk + pb;
+        for (int i = t; i < N; i += B) P[i] = P4<T>{px[i], pu[i], pv[i], pw[i]};
+        __threadfence_block();
         const double cm = cl.cr_max[g];
         const double aexp = 1.0 - 2.0 * c.ups;
         if (t < NBIN) hd[t] = 0;
@@ -672,8 +701,9 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
             int si = 0, sj = 0;
             if (act) {
                 big_pair<T>(c, step, lc, (uint32_t)q, N, i, j, u2, u3, u4);
-                xi = px[i]; ui = pu[i]; vi = pv[i]; wi = pw[i];
-                xj = px[j]; uj = pu[j]; vj = pv[j]; wj = pw[j];
+                const P4<T> a = P[i], bq = P[j];
+                xi = a.x; ui = a.u; vi = a.v; wi = a.w;
+                xj = bq.x; uj = bq.u; vj = bq.v; wj = bq.w;
                 si = big_insert(hkey, hcnt, hlst, i, t, &ovf[par]);
                 sj = big_insert(hkey, hcnt, hlst, j, t, &ovf[par]);
             }
@@ -692,13 +722,13 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
                         uint32_t a, bq;
                         double v2, v3, v4;
                         big_pair<T>(c, step, lc, (uint32_t)(q0 + l), N, a, bq, v2, v3, v4);
-                        T ua = pu[a], va = pv[a], wa = pw[a], ub = pu[bq], vb = pv[bq], wb = pw[bq];
-                        const T ua0 = ua, ub0 = ub;
-                        if (collide_vals<T>(ua, va, wa, ub, vb, wb, cm, aexp, v2, v3, v4, seen)) {
+                        P4<T> ra = P[a], rb = P[bq];
+                        const T ua0 = ra.u, ub0 = rb.u;
+                        if (collide_vals<T>(ra.u, ra.v, ra.w, rb.u, rb.v, rb.w, cm, aexp, v2, v3, v4, seen)) {
                             ++acc;
-                            pu[a] = ua; pv[a] = va; pw[a] = wa;
-                            pu[bq] = ub; pv[bq] = vb; pw[bq] = wb;
-                            big_bins<T>(c, lc, px[a], ua0, ua, px[bq], ub0, ub, hd, far);
+                            P[a] = ra;
+                            P[bq] = rb;
+                            big_bins<T>(c, lc, ra.x, ua0, ra.u, rb.x, ub0, rb.u, hd, far);
                         }
                     }
                 }
@@ -719,8 +749,8 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
                         const T ui0 = ui, uj0 = uj;
                         if (collide_vals<T>(ui, vi, wi, uj, vj, wj, cm, aexp, u2, u3, u4, seen)) {
                             ++acc;
-                            pu[i] = ui; pv[i] = vi; pw[i] = wi;
-                            pu[j] = uj; pv[j] = vj; pw[j] = wj;
+                            P[i] = P4<T>{xi, ui, vi, wi};
+                            P[j] = P4<T>{xj, uj, vj, wj};
                             big_bins<T>(c, lc, xi, ui0, ui, xj, uj0, uj, hd, far);
                         }
                         fwd[0][t] = ui; fwd[1][t] = vi; fwd[2][t] = wi;
@@ -738,6 +768,11 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
             }
             __threadfence_block();
             __syncthreads();
+        }
+        // velocities back to the cell's segment
+        for (int i = t; i < N; i += B) {
+            const P4<T> r = P[i];
+            pu[i] = r.u; pv[i] = r.v; pw[i] = r.w;
         }
         // per-cell results
         int a = wave_sum_i(acc);
@@ -1543,8 +1578,9 @@ static void step_impl(duwp_ctx *ctx)
                            ctx->d_items, ctx->items_cap);
         hipLaunchKernelGGL(k_collide<T>, dim3(ctx->coll_blocks), dim3(64 * COLL_WPB), 0, st, ctx->d_cases,
                            cl, src, stg, ctx->d_step, G, ctx->cap, ctx->d_err, ctx->item_cell, ctx->d_items);
+        hipLaunchKernelGGL(k_big_bases, dim3(1), dim3(1024), 0, st, cl);
         hipLaunchKernelGGL(k_collide_big<T>, dim3(ctx->big_blocks), dim3(BigCfg<T>::B), 0, st, ctx->d_cases,
-                           cl, src, stg, ctx->d_step, ctx->cap);
+                           cl, src, stg, (P4<T> *)ctx->pk, ctx->d_step, ctx->cap);
     }
     {
         Mark m(ctx, "hist_fix");
