@@ -43,7 +43,27 @@ BYTES_PER_PARTICLE = {
 # each particle's state (16 B in FP32 mode, 32 B in FP64 mode) is read and
 # written once by the cell pass and once by the sort, four times the state.
 STEP_BYTES_PER_PARTICLE = {"mixed": 64, "fp64": 128}
-KERNEL_SOURCES = ("duwp_kernels.hip", "duwp_physics.hpp", "duwp_device.hpp", "duwp_scan.hpp")
+# The counted traffic of a kernel stays valid while its own source and the headers
+# it uses are unchanged: the fingerprint covers the kernel's text in
+# duwp_kernels.hip (from its template line to the next numbered section) and the
+# device and physics headers.
+KERNEL_HEADERS = ("duwp_physics.hpp", "duwp_device.hpp")
+
+
+def kernel_fingerprint(kernel: str) -> str:
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2305_12071_amd", "csrc")
+    with open(os.path.join(csrc, "duwp_kernels.hip")) as fh:
+        src = fh.read()
+    name = kernel.split("<")[0]
+    i0 = src.index(f") {name}(")
+    i0 = src.rindex("template <typename T>", 0, i0) if "<" in kernel else src.rindex("__global__", 0, i0)
+    i1 = src.find("\n// ", i0 + 1)
+    h = hashlib.sha256(src[i0:i1 if i1 > 0 else len(src)].encode())
+    for f in KERNEL_HEADERS:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -55,16 +75,11 @@ def counted_traffic(kernel: str, workload: str):
     (FETCH_SIZE and WRITE_SIZE runs, each scaled by a plain copy of known size), or
     None when the kernel sources changed since the counters were taken."""
     import glob
-    import hashlib
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2305_12071_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    fp = kernel_fingerprint(kernel)
     for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
         with open(path) as fh:
             d = json.load(fh)
-        if d.get("kernel") == kernel and d.get("workload") == workload \
-                and d.get("kernel_sources_sha256") == h.hexdigest():
+        if d.get("kernel") == kernel and d.get("workload") == workload and d.get("kernel_sha256") == fp:
             return d["hbm_bytes_per_launch"], d["particles_per_launch"]
     return None
 

@@ -221,4 +221,28 @@ __device__ __forceinline__ int block_flag_prefix(bool f, int *scratch, int *tota
     return base + in_wave;
 }
 
+// Exclusive block prefix of a small per-thread count; returns this thread's
+// prefix, *total the block total.  scratch must hold blockDim/64 ints.
+__device__ __forceinline__ int block_count_prefix(int v, int *scratch, int *total)
+{
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = lane_id();
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int t = __shfl_up(incl, o, WAVE);
+        if (lane >= o) incl += t;
+    }
+    __syncthreads();
+    if (lane == WAVE - 1) scratch[w] = incl;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        const int c = scratch[i];
+        if (i < w) base += c;
+        tot += c;
+    }
+    *total = tot;
+    return base + incl - v;
+}
+
 }  // namespace duwp

@@ -236,31 +236,42 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
         bool far = false;
         __syncthreads();
         if (P > 0.0) {
-            for (int64_t k0 = b; k0 < e; k0 += blockDim.x) {
-                const int64_t kk = k0 + threadIdx.x;
-                const bool valid = kk < e;
-                T x = 0, u = 0, v = 0, w = 0;
-                bool absorbed = false;
-                if (valid) {
-                    x = src.x[kk]; u = src.u[kk]; v = src.v[kk]; w = src.w[kk];
-                    uint32_t kl = (uint32_t)(kk - pbase);
-                    U4 r = draw(c, step, kl >> 2, 0, TAG_CLS, 0);
-                    absorbed = u01(pick(r, kl & 3)) < P;
+            // one Philox block classifies the four particles of an aligned quad of
+            // case-local indices: a thread takes one quad
+            const int64_t qa = (b - pbase) >> 2, qb = (e - 1 - pbase) >> 2;
+            for (int64_t q0 = qa; q0 <= qb; q0 += blockDim.x) {
+                const int64_t qd = q0 + threadIdx.x;
+                T xs[4], us[4], vs[4], ws[4];
+                int keep = 0;
+                if (qd <= qb) {
+                    const U4 r = draw(c, step, (uint32_t)qd, 0, TAG_CLS, 0);
+                    const uint32_t wd[4] = {r.a, r.b, r.c, r.d};
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int64_t kk = pbase + 4 * qd + m;
+                        xs[m] = 0; us[m] = 0; vs[m] = 0; ws[m] = 0;
+                        if (kk < b || kk >= e) continue;
+                        xs[m] = src.x[kk]; us[m] = src.u[kk]; vs[m] = src.v[kk]; ws[m] = src.w[kk];
+                        if (u01(wd[m]) < P) {
+                            const double du = us[m], dv = vs[m], dw = ws[m];
+                            sa[0] += 1.0; sa[1] += du; sa[2] += dv; sa[3] += dw;
+                            sa[4] += 0.5 * (du * du + dv * dv + dw * dw);
+                            bool f2 = false;
+                            const int hb = flight_bin<T>(c, lc, xs[m], us[m], &f2);
+                            if (hb >= 0) atomicSub(&dh[hb], 1);
+                        } else {
+                            keep |= 1 << m;
+                        }
+                    }
                 }
-                if (absorbed) {
-                    double du = u, dv = v, dw = w;
-                    sa[0] += 1.0; sa[1] += du; sa[2] += dv; sa[3] += dw;
-                    sa[4] += 0.5 * (du * du + dv * dv + dw * dw);
-                    bool f2 = false;
-                    const int hb = flight_bin<T>(c, lc, x, u, &f2);
-                    if (hb >= 0) atomicSub(&dh[hb], 1);
-                }
+                // survivors in index order: quads in thread order, then m
                 int tot;
-                const bool keep = valid && !absorbed;
-                int pre = block_flag_prefix(keep, scr, &tot);
-                if (keep) {
-                    int64_t d = ob + written + pre;
-                    if (d < cap) { stg.x[d] = x; stg.u[d] = u; stg.v[d] = v; stg.w[d] = w; }
+                int pre = block_count_prefix(__popc(keep), scr, &tot);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    if (!((keep >> m) & 1)) continue;
+                    const int64_t d = ob + written + pre++;
+                    if (d < cap) { stg.x[d] = xs[m]; stg.u[d] = us[m]; stg.v[d] = vs[m]; stg.w[d] = ws[m]; }
                     else atomicOr(err, ERR_CAPACITY);
                 }
                 written += tot;
@@ -282,8 +293,8 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
                 U4 a = draw(c, step, (uint32_t)lc, (uint32_t)q, TAG_RVEL, 0);
                 U4 bb = draw(c, step, (uint32_t)lc, (uint32_t)q, TAG_RVEL, 1);
                 double uu[6] = {u01(a.b), u01(a.c), u01(a.d), u01(bb.a), u01(bb.b), u01(bb.c)};
-                double xi[3];
-                maxwell(Wc[1], Wc[2], Wc[3], Wc[4], c.R, uu, xi);
+                T xi[3];
+                maxwell_t<T>(Wc[1], Wc[2], Wc[3], Wc[4], c.R, uu, xi);
                 T px;
                 if constexpr (std::is_same<T, double>::value) {
                     px = c.x_lo + ((double)lc + u01(a.a)) * c.dx;
@@ -291,7 +302,7 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
                     px = (float)u01(a.a);
                     if (px >= 1.0f) px = 0.99999994f;
                 }
-                T pu = (T)xi[0], pv = (T)xi[1], pw = (T)xi[2];
+                T pu = xi[0], pv = xi[1], pw = xi[2];
                 const int hb = flight_bin<T>(c, lc, px, pu, &far);
                 if (hb >= 0) atomicAdd(&dh[hb], 1);
                 int64_t d = ob + nsurv + q;
@@ -833,8 +844,8 @@ __global__ void __launch_bounds__(256) k_inject_gen(const DCase *__restrict__ ca
             U4 a = draw(c, step, (uint32_t)side, (uint32_t)q, TAG_IVEL, 0);
             U4 bb = draw(c, step, (uint32_t)side, (uint32_t)q, TAG_IVEL, 1);
             double uu[6] = {u01(a.b), u01(a.c), u01(a.d), u01(bb.a), u01(bb.b), u01(bb.c)};
-            double xi[3];
-            maxwell(U, 0.0, 0.0, Ts, c.R, uu, xi);
+            T xi[3];
+            maxwell_t<T>(U, 0.0, 0.0, Ts, c.R, uu, xi);
             if constexpr (std::is_same<T, double>::value) {
                 double x = side == 0 ? c.x_lo - u01(a.a) * Lg : c.x_hi + u01(a.a) * Lg;
                 double u = xi[0];
@@ -842,7 +853,7 @@ __global__ void __launch_bounds__(256) k_inject_gen(const DCase *__restrict__ ca
                 dest = bc_cell_abs(c, x, u);
                 px = x; pu = u;
             } else {
-                float u = (float)xi[0];
+                float u = xi[0];
                 const float lgc = (float)(Lg / c.dx);
                 const float X0 = side == 0 ? -(float)u01(a.a) * lgc : (float)u01(a.a) * lgc;
                 const float X = X0 + u * c.dtdx_f;
@@ -851,7 +862,7 @@ __global__ void __launch_bounds__(256) k_inject_gen(const DCase *__restrict__ ca
                 dest = (fabsf(X) < 1.0e9f) ? bc_cell_rel(c, (side == 0 ? 0 : c.ncells) + (int)fl, X - fl, u, s) : -1;
                 px = s; pu = u;
             }
-            pv = (T)xi[1]; pw = (T)xi[2];
+            pv = xi[1]; pw = xi[2];
         }
         const bool ent = dest >= 0;
         int tot;

@@ -57,6 +57,30 @@ __device__ __forceinline__ void maxwell(double U, double V, double W, double T, 
         out[d] = mean[d] + sd * cos(D_TWO_PI * uu[2 * d]) * sqrt(-log(1.0 - uu[2 * d + 1]));
 }
 
+// The same draw for FP32 particles: the velocity is stored in FP32, so it is
+// computed in FP32 (1 - u' is formed in FP64 first, so its 2^-32 resolution and
+// the tail of the distribution are kept).
+__device__ __forceinline__ void maxwell_f(double U, double V, double W, double T, double R,
+                                          const double uu[6], float out[3])
+{
+    const float sd = sqrtf((float)(2.0 * R * T));
+    const float mean[3] = {(float)U, (float)V, (float)W};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        out[d] = mean[d] + sd * cosf(6.2831853f * (float)uu[2 * d]) * sqrtf(-logf((float)(1.0 - uu[2 * d + 1])));
+}
+
+template <typename T>
+__device__ __forceinline__ void maxwell_t(double U, double V, double W, double T_, double R, const double uu[6],
+                                          T out[3])
+{
+    if constexpr (std::is_same<T, double>::value) {
+        maxwell(U, V, W, T_, R, uu, out);
+    } else {
+        maxwell_f(U, V, W, T_, R, uu, out);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Free flight and boundaries.  Returns the local destination cell, -1 if the
 // particle left through a reservoir side.
