@@ -104,7 +104,15 @@ enum {
     DUWP_M_PSI_W = 2,     /* conserved wave part */
     DUWP_M_PSI_P = 3,     /* conserved particle part */
     DUWP_M_AVG_PRIM = 4,  /* (rho, U, V, W, T) of the time-averaged Psi_t */
-    DUWP_M_AVG_SUM = 5    /* running sum of Psi_t (divide by duwp_avg_count) */
+    DUWP_M_AVG_SUM = 5,   /* running sum of Psi_t (divide by duwp_avg_count) */
+    /* (Pi, Q, Pi_p, Q_p, rho_w/rho_t) of the current state: the normal stress and
+     * heat flux of Eq. gkt_moment1 (xx entry of S, x component of Q), totals and
+     * particle parts, and the wave part's share of the mass (Fig. 5f).  The
+     * particle part is taken about the cell's total mean velocity; the wave part
+     * adds the NS closure its flux carries (Sec. 3.3), -P (4/3) eps mu dU/dx and
+     * -P (15/4) R eps mu dT/dx with central differences.  Computed on demand by a
+     * kernel over the case's particles. */
+    DUWP_M_STRESS_HEAT = 6
 };
 
 /* Create a context holding ncases independent cases; all cases step together.

@@ -397,6 +397,84 @@ void orc_get_cells(const orc_state *s, double *prim, double *psi_t, double *psi_
     }
 }
 
+/* Normal stress and heat flux of the current state, per cell (Eq. gkt_moment1,
+ * xx entry of S and x component of Q for the monatomic gas of the tests):
+ * out[c*5 + 0..4] = (Pi, Q, Pi_p, Q_p, rho_w/rho_t).
+ *
+ * Particle part, about the total state's mean velocity U_t (c = xi - U_t):
+ *   Pi_p = (m_p/dx) sum (c_x^2 - |c|^2/3),  Q_p = (m_p/dx) sum c_x |c|^2 / 2.
+ * Pi_p is the xx entry of rho cc(f - g) for the particles with the trace
+ * removed.  The wave part is taken as a Maxwellian at the cell's total
+ * velocity (no deviatoric stress, no heat flux) plus the NS closure that its
+ * flux carries (Sec. 3.3), weighted like that flux by the cell's absorbed
+ * fraction P_c:
+ *   Pi_w = -P_c (4/3) eps mu dU/dx,  Q_w = -P_c (15/4) R eps mu dT/dx,
+ * with eps and P_c of the cell's state, and central differences over the
+ * neighbouring cells (the flux's ghost states beyond the ends).  A vacuum cell,
+ * or a vacuum neighbour, gives no wave term. */
+int orc_stress_heat(const orc_state *s, double *out)
+{
+    const orc_case *cs = &s->cs;
+    const int C = cs->ncells;
+    const double fac = cs->m_particle / s->dx;
+    double *W = malloc(((size_t)C + 2) * 5 * sizeof(double));
+    int *ok = malloc(((size_t)C + 2) * sizeof(int));
+    if (!W || !ok) { free(W); free(ok); return -1; }
+    /* W[1..C] the cells, W[0] and W[C+1] the ghost states */
+    for (int c = 0; c < C; ++c) {
+        double t[5];
+        for (int k = 0; k < 5; ++k) t[k] = s->psi_w[c * 5 + k] + s->psi_p[c * 5 + k];
+        ok[c + 1] = primitive(t, cs->R, W + (c + 1) * 5);
+    }
+    if (cs->bc_lo == 0) {
+        W[0] = cs->rho_L; W[1] = cs->u_L; W[2] = 0.0; W[3] = 0.0; W[4] = cs->T_L; ok[0] = 1;
+    } else {
+        memcpy(W, W + 5, 5 * sizeof(double)); W[1] = -W[6]; ok[0] = ok[1];
+    }
+    double *Wg = W + (C + 1) * 5, *Wl = W + C * 5;
+    if (cs->bc_hi == 0) {
+        Wg[0] = cs->rho_R; Wg[1] = cs->u_R; Wg[2] = 0.0; Wg[3] = 0.0; Wg[4] = cs->T_R; ok[C + 1] = 1;
+    } else {
+        memcpy(Wg, Wl, 5 * sizeof(double)); Wg[1] = -Wl[1]; ok[C + 1] = ok[C];
+    }
+    for (int c = 0; c < C; ++c) {
+        const double *Wc = W + (c + 1) * 5;
+        double *o = out + (size_t)c * 5;
+        for (int k = 0; k < 5; ++k) o[k] = 0.0;
+        if (!ok[c + 1]) continue;
+        const double U = Wc[1], V = Wc[2], Wv = Wc[3];
+        double sxx = 0.0, scc = 0.0, sq = 0.0;
+        for (int64_t k = s->off[c]; k < s->off[c + 1]; ++k) {
+            const double cx = s->u[k] - U, cy = s->v[k] - V, cz = s->w[k] - Wv;
+            const double c2 = cx * cx + cy * cy + cz * cz;
+            sxx += cx * cx;
+            scc += c2;
+            sq += cx * c2;
+        }
+        const double pip = fac * (sxx - scc / 3.0);
+        const double qp = fac * 0.5 * sq;
+        double piw = 0.0, qw = 0.0;
+        if (ok[c] && ok[c + 2]) {
+            const double mu = viscosity(s, Wc[4]);
+            const double tau = mu / (Wc[0] * cs->R * Wc[4]);
+            const double P = absorb_fraction(cs->classify_law, cs->dt, tau);
+            const double mue = orc_eps(cs->eps_law, cs->dt / tau) * mu;
+            const double dU = (W[(c + 2) * 5 + 1] - W[c * 5 + 1]) / (2.0 * s->dx);
+            const double dT = (W[(c + 2) * 5 + 4] - W[c * 5 + 4]) / (2.0 * s->dx);
+            piw = -P * (4.0 / 3.0) * mue * dU;
+            qw = -P * (15.0 / 4.0) * cs->R * mue * dT;
+        }
+        o[0] = pip + piw;
+        o[1] = qp + qw;
+        o[2] = pip;
+        o[3] = qp;
+        o[4] = s->psi_w[c * 5] / Wc[0];
+    }
+    free(W);
+    free(ok);
+    return 0;
+}
+
 void orc_get_average(const orc_state *s, double *avg_sum, int64_t *count)
 {
     if (avg_sum) memcpy(avg_sum, s->avg, (size_t)s->cs.ncells * 5 * sizeof(double));

@@ -79,6 +79,8 @@ void orc_get_cells(const orc_state *s, double *prim, double *psi_t, double *psi_
 
 /* Time average of Psi_t accumulated after each step since the last reset. */
 void orc_get_average(const orc_state *s, double *avg_sum, int64_t *count);
+/* Normal stress and heat flux per cell: out[C*5] = (Pi, Q, Pi_p, Q_p, rho_w/rho_t). */
+int orc_stress_heat(const orc_state *s, double *out);
 void orc_reset_average(orc_state *s);
 
 /* ---- Elementary operations, exposed for the closed-form checks ---- */

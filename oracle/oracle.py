@@ -76,6 +76,8 @@ def lib():
         L.orc_get_cells.argtypes = [P, dp, dp, dp]
         L.orc_get_average.argtypes = [P, dp, i64p]
         L.orc_reset_average.argtypes = [P]
+        L.orc_stress_heat.restype = C.c_int
+        L.orc_stress_heat.argtypes = [P, dp]
         L.orc_philox.argtypes = [u32p, u32p, u32p]
         L.orc_eps.restype = C.c_double
         L.orc_eps.argtypes = [C.c_int32, C.c_double]
@@ -203,6 +205,13 @@ class Oracle:
         pp = np.zeros(Cn * 5)
         lib().orc_get_cells(self.ptr, _p(prim), _p(pt), _p(pp))
         return dict(prim=prim.reshape(Cn, 5), psi_t=pt.reshape(Cn, 5), psi_p=pp.reshape(Cn, 5))
+
+    def stress_heat(self) -> np.ndarray:
+        """(Pi, Q, Pi_p, Q_p, rho_w/rho_t) per cell of the current state, shape (C, 5)."""
+        out = np.zeros((self.ncells, 5))
+        if lib().orc_stress_heat(self.ptr, _p(out)) != 0:
+            raise MemoryError("orc_stress_heat")
+        return out
 
     def average(self):
         s = np.zeros(self.ncells * 5)

@@ -143,6 +143,7 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &c.nbig, 4));
     TRY(dalloc(ctx, &c.big_base, 8 * (size_t)G));
     TRY(dalloc(ctx, &ctx->pk, 4 * es * (size_t)ctx->cap));
+    TRY(dalloc(ctx, &ctx->diag, 8 * 5 * (size_t)G));
     ctx->items_cap = std::max<int64_t>(1 << 20, 2 * (int64_t)G);
     TRY(dalloc(ctx, &ctx->item_cell, 4 * (size_t)ctx->items_cap));
     TRY(dalloc(ctx, &ctx->d_items, 16));
@@ -449,10 +450,21 @@ duwp_status duwp_counts(duwp_ctx *ctx, int32_t case_id, int64_t *n_particles, in
 duwp_status duwp_moments(duwp_ctx *ctx, int32_t case_id, int32_t what, double *out, int64_t len,
                          int32_t out_on_device)
 {
-    if (!ctx || !out || case_id < 0 || case_id >= ctx->ncases || what < 0 || what > 5) return DUWP_EINVAL;
+    if (!ctx || !out || case_id < 0 || case_id >= ctx->ncases || what < 0 || what > DUWP_M_STRESS_HEAT)
+        return DUWP_EINVAL;
     const DCase &d = ctx->hcases[case_id];
     const int C = d.ncells;
     if (len < 5 * (int64_t)C) return DUWP_EINVAL;
+    if (what == DUWP_M_STRESS_HEAT) {
+        (void)hipGetLastError();
+        duwp::enqueue_stress_heat(ctx, d.cell_base, d.cell_base + C, ctx->diag);
+        if (hipGetLastError() != hipSuccess) return DUWP_EDEVICE;
+        const double *src = ctx->diag + 5 * (size_t)d.cell_base;
+        HIP_OK(hipMemcpyAsync(out, src, 8 * 5 * (size_t)C,
+                              out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        return read_error(ctx);
+    }
     std::vector<double> w(5 * (size_t)C), p(5 * (size_t)C), a(5 * (size_t)C);
     const size_t o = 5 * (size_t)d.cell_base, nb = 8 * 5 * (size_t)C;
     HIP_OK(hipMemcpyAsync(w.data(), ctx->cl.psi_w + o, nb, hipMemcpyDeviceToHost, ctx->stream));

@@ -69,6 +69,7 @@ struct duwp_ctx {
     int coll_blocks = 0;
     int big_blocks = 0;            // grid of the block-per-cell collision kernel
     void *pk = nullptr;            // packed (x,u,v,w) records of the cells that kernel works on
+    double *diag = nullptr;        // [G*5] on-demand cell diagnostics
     int64_t *d_psteps = nullptr;   // particle-steps since init or the last reset
 
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -82,4 +83,6 @@ namespace duwp {
 void enqueue_step(duwp_ctx *ctx);
 // Recompute the particle moments of the current canonical state (no averaging).
 void enqueue_moments(duwp_ctx *ctx);
+// Normal stress and heat flux of cells [g0, g1) of the current state into out[G*5].
+void enqueue_stress_heat(duwp_ctx *ctx, int g0, int g1, double *out);
 }  // namespace duwp

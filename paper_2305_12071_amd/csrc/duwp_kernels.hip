@@ -1464,6 +1464,95 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
     if (bad) atomicOr(err, ERR_STATE);
 }
 
+// ---------------------------------------------------------------------------
+// Diagnostics: normal stress and heat flux of the current state (Eq. gkt_moment1),
+// per cell (Pi, Q, Pi_p, Q_p, rho_w/rho_t).  The particle part is taken about the
+// total state's mean velocity; the wave part, a Maxwellian at that velocity plus
+// the NS closure its flux carries (Sec. 3.3), adds -P (4/3) eps mu dU/dx and
+// -P (15/4) R eps mu dT/dx with central differences (the flux's ghost states
+// beyond the ends of a case).  Not part of the step.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int cell_prim(const Cells &cl, const DCase &c, int g, double W[5])
+{
+    double t[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) t[k] = cl.psi_w[(int64_t)g * 5 + k] + cl.psi_p[(int64_t)g * 5 + k];
+    return primitive(t, c.R, W);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_stress_heat(const DCase *__restrict__ cases, Cells cl, Soa<T> a,
+                                                     const int64_t *__restrict__ off, int g0, int g1,
+                                                     double *__restrict__ out)
+{
+    __shared__ double red[3 * 4];
+    for (int g = g0 + blockIdx.x; g < g1; g += gridDim.x) {
+        const DCase &c = cases[cl.cell_case[g]];
+        const int lc = g - c.cell_base;
+        double W[5], Wl[5], Wr[5];
+        const int ok = cell_prim(cl, c, g, W);
+        int okl, okr;
+        if (lc == 0) {
+            if (c.bc_lo == 0) { Wl[0] = c.rho_L; Wl[1] = c.u_L; Wl[2] = 0.0; Wl[3] = 0.0; Wl[4] = c.T_L; okl = 1; }
+            else {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) Wl[k] = W[k];
+                Wl[1] = -W[1];
+                okl = ok;
+            }
+        } else {
+            okl = cell_prim(cl, c, g - 1, Wl);
+        }
+        if (lc == c.ncells - 1) {
+            if (c.bc_hi == 0) { Wr[0] = c.rho_R; Wr[1] = c.u_R; Wr[2] = 0.0; Wr[3] = 0.0; Wr[4] = c.T_R; okr = 1; }
+            else {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) Wr[k] = W[k];
+                Wr[1] = -W[1];
+                okr = ok;
+            }
+        } else {
+            okr = cell_prim(cl, c, g + 1, Wr);
+        }
+        double sm[3] = {0.0, 0.0, 0.0};
+        if (ok) {
+            for (int64_t kk = off[g] + threadIdx.x; kk < off[g + 1]; kk += blockDim.x) {
+                const double cx = (double)a.u[kk] - W[1], cy = (double)a.v[kk] - W[2], cz = (double)a.w[kk] - W[3];
+                const double c2 = cx * cx + cy * cy + cz * cz;
+                sm[0] += cx * cx;
+                sm[1] += c2;
+                sm[2] += cx * c2;
+            }
+        }
+        block_sum<3>(sm, red);
+        if (threadIdx.x == 0) {
+            double o[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            if (ok) {
+                const double pip = c.fac * (sm[0] - sm[1] / 3.0);
+                const double qp = c.fac * 0.5 * sm[2];
+                double piw = 0.0, qw = 0.0;
+                if (okl && okr) {
+                    const double mu = viscosity(c, W[4]);
+                    const double tau = mu / (W[0] * c.R * W[4]);
+                    const double P = absorb_fraction(c.law, c.dt, tau);
+                    const double mue = eps_factor(c.eps_law, c.dt / tau) * mu;
+                    const double dU = (Wr[1] - Wl[1]) / (2.0 * c.dx);
+                    const double dT = (Wr[4] - Wl[4]) / (2.0 * c.dx);
+                    piw = -P * (4.0 / 3.0) * mue * dU;
+                    qw = -P * (15.0 / 4.0) * c.R * mue * dT;
+                }
+                o[0] = pip + piw;
+                o[1] = qp + qw;
+                o[2] = pip;
+                o[3] = qp;
+                o[4] = cl.psi_w[(int64_t)g * 5] / W[0];
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k) out[(int64_t)g * 5 + k] = o[k];
+        }
+    }
+}
+
 // Particle moments recomputed from a canonical array (after a state is loaded).
 template <typename T>
 __global__ void __launch_bounds__(512) k_moments(const DCase *__restrict__ cases, Cells cl, Soa<T> a,
@@ -1665,6 +1754,23 @@ void enqueue_moments(duwp_ctx *ctx)
 {
     if (ctx->precision == DUWP_MIXED) reload_impl<float>(ctx);
     else reload_impl<double>(ctx);
+}
+
+// Normal stress and heat flux of cells [g0, g1) into out (device, [G*5] by global cell).
+template <typename T>
+static void stress_heat_impl(duwp_ctx *ctx, int g0, int g1, double *out)
+{
+    const int p = ctx->step & 1;
+    const Soa<T> a = soa<T>(ctx->A[p]);
+    const int n = g1 - g0;
+    hipLaunchKernelGGL(k_stress_heat<T>, dim3(n < 65535 ? n : 65535), dim3(256), 0, ctx->stream, ctx->d_cases,
+                       ctx->cl, a, ctx->off[p], g0, g1, out);
+}
+
+void enqueue_stress_heat(duwp_ctx *ctx, int g0, int g1, double *out)
+{
+    if (ctx->precision == DUWP_MIXED) stress_heat_impl<float>(ctx, g0, g1, out);
+    else stress_heat_impl<double>(ctx, g0, g1, out);
 }
 
 }  // namespace duwp

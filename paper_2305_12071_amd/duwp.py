@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(PKG, "libduwp.so")
 
 FP64, MIXED = 0, 1
-M_PRIM, M_PSI_T, M_PSI_W, M_PSI_P, M_AVG_PRIM, M_AVG_SUM = range(6)
+M_PRIM, M_PSI_T, M_PSI_W, M_PSI_P, M_AVG_PRIM, M_AVG_SUM, M_STRESS_HEAT = range(7)
 
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ECAPACITY", -5: "ESTATE", -6: "ERANGE"}
 

@@ -219,3 +219,32 @@ def test_fused_moments_equal_recomputed_moments(prec):
         assert np.all(np.abs(a - b) <= 1e-12 * scale), k
         h.close()
     g.close()
+
+
+@pytest.mark.parametrize("prec", [duwp.FP64, duwp.MIXED])
+def test_stress_and_heat_flux_match_oracle(prec):
+    """Pi, Q (Eq. gkt_moment1), their particle parts and the wave mass share, computed
+    on the GPU and by the oracle from the same state.  Only the order of the cell sums
+    differs: each is a sum of n terms of size up to the cell's p (Pi) or p sqrt(2RT)
+    (Q), so the bound is 8 n 2^-53 times that scale, plus 1e-12 relative."""
+    names = ["mach3", "sod_kn1e-4", "box_p97", "sod_exp_epsfull"]
+    cases = [CASES[n] for n in names]
+    _say("stress/heat", prec)
+    g = duwp.Sim(cases, seed=4, precision=prec)
+    g.step(6)
+    for k, n in enumerate(names):
+        st = g.get_state(k)
+        o = O.Oracle(cases[k], seed=4, case_id=k)
+        o.set_state(st)
+        a = g.moments(k, duwp.M_STRESS_HEAT)
+        b = o.stress_heat()
+        prim = o.cells()["prim"]
+        cnt = np.diff(st["off"]).astype(float)
+        p = prim[:, 0] * cases[k].R * prim[:, 4]
+        scale = np.stack([p, p * np.sqrt(2 * cases[k].R * np.maximum(prim[:, 4], 0)), p,
+                          p * np.sqrt(2 * cases[k].R * np.maximum(prim[:, 4], 0)), np.ones_like(p)], axis=1)
+        tol = 8 * np.maximum(cnt, 1)[:, None] * 2.0 ** -53 * scale + 1e-12 * np.abs(b)
+        bad = np.abs(a - b) > tol
+        assert not bad.any(), (n, np.argwhere(bad)[:5].tolist(), np.abs(a - b)[bad][:5], tol[bad][:5])
+        assert np.any(b[:, 2] != 0.0)
+    g.close()

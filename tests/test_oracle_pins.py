@@ -521,3 +521,101 @@ def test_free_molecular_limit_matches_collisionless_solution():
     assert abs(z.mean()) < 4.0 / math.sqrt(sel.sum())
     zm = (pt[sel, 1] - mom[sel]) / sig[sel]
     assert np.abs(zm).max() < 5.0
+
+
+# --------------------------------------------------------------------------
+# Normal stress and heat flux (Eq. gkt_moment1)
+# --------------------------------------------------------------------------
+
+def _hand_state(c, cell_vel, psi_w=None):
+    """Canonical state with the given particle velocities per cell (at the cell centres)."""
+    xs, vel, off = [], [], [0]
+    for i in range(c.ncells):
+        v = np.asarray(cell_vel[i], float).reshape(-1, 3)
+        xs.append(np.full(len(v), c.x_lo + (i + 0.5) * c.dx))
+        vel.append(v)
+        off.append(off[-1] + len(v))
+    v = np.concatenate(vel)
+    return dict(x=np.concatenate(xs), u=v[:, 0].copy(), v=v[:, 1].copy(), w=v[:, 2].copy(),
+                off=np.array(off, np.int64), psi_w=np.zeros((c.ncells, 5)) if psi_w is None else psi_w,
+                cr_max=np.ones(c.ncells), step=0)
+
+
+def test_particle_stress_and_heat_flux_of_hand_built_sets():
+    c = _box(0.5, ncells=3)
+    a = 0.7
+    shift = np.array([0.3, -1.1, 0.45])
+    beam = [(a, 0, 0), (-a, 0, 0), (a, 0, 0), (-a, 0, 0)]
+    skew = np.array([(2 * a, 0, 0), (-a, 0, 0), (-a, 0, 0)]) + shift
+    import itertools
+    iso = []
+    for perm in itertools.permutations((1.0, 2.0, 3.0)):
+        for sg in itertools.product((1, -1), repeat=3):
+            iso.append(a * np.array(perm) * np.array(sg))
+    iso = np.array(iso) + shift
+    o = O.Oracle(c)
+    o.set_state(_hand_state(c, [beam, skew, iso]))
+    sh = o.stress_heat()
+    fac = c.m_particle / c.dx
+    # two opposite beams along x: P_xx = rho a^2, p = rho a^2 / 3, so Pi = 2 p, Q = 0
+    p0 = o.cells()["prim"][0]
+    assert sh[0, 2] == pytest.approx(2.0 * p0[0] * c.R * p0[4], rel=1e-13)
+    assert abs(sh[0, 3]) < 1e-14 * fac * a ** 3
+    # skewed set about its own mean (any Galilean shift): Pi = 4 a^2 m/dx, Q = 3 a^3 m/dx
+    assert sh[1, 2] == pytest.approx(4 * a * a * fac, rel=1e-12)
+    assert sh[1, 3] == pytest.approx(3 * a ** 3 * fac, rel=1e-12)
+    # all signed permutations of one vector: isotropic and symmetric, so no stress, no heat flux
+    assert abs(sh[2, 2]) < 1e-13 * fac * a * a * len(iso)
+    assert abs(sh[2, 3]) < 1e-13 * fac * a ** 3 * len(iso)
+    assert np.all(sh[:, 4] == 0.0)
+
+
+def test_stress_and_heat_flux_vanish_at_equilibrium_within_noise():
+    c = _box(0.5, ppc=3000, ncells=4)          # P = 0: no wave term
+    o = O.Oracle(c, seed=11)
+    _to_particles(o)
+    o.step(3)
+    sh = o.stress_heat()
+    st = o.get_state()
+    prim = o.cells()["prim"]
+    fac = c.m_particle / c.dx
+    for i in range(c.ncells):
+        s = slice(st["off"][i], st["off"][i + 1])
+        cx, cy, cz = st["u"][s] - prim[i, 1], st["v"][s] - prim[i, 2], st["w"][s] - prim[i, 3]
+        c2 = cx * cx + cy * cy + cz * cz
+        n = len(cx)
+        for col, terms in ((2, cx * cx - c2 / 3), (3, 0.5 * cx * c2)):
+            noise = fac * terms.std() * math.sqrt(n)
+            assert abs(sh[i, col]) < 5 * noise, (i, col, sh[i, col], noise)
+        assert sh[i, 0] == sh[i, 2] and sh[i, 1] == sh[i, 3]
+
+
+@pytest.mark.parametrize("grad", ["U", "T"])
+def test_wave_stress_and_heat_flux_are_navier_stokes_in_the_continuum_limit(grad):
+    """All mass in the wave part of argon on cells of 3e6 mean free paths (dt/tau ~ 1e5,
+    so P -> 1 and eps -> 1): Pi = -(4/3) mu dU/dx and Q = -(15/4) R mu dT/dx with
+    Bird's VHS viscosity."""
+    c = I.argon_shock(3.0, 8, 8 * 3e6, 2e4)
+    o = O.Oracle(c)
+    xc = c.x_lo + (np.arange(c.ncells) + 0.5) * c.dx
+    rho, T0, U0 = c.rho_L, 273.0, 50.0
+    k = 20.0 / (c.x_hi - c.x_lo)
+    U = U0 + (k * xc if grad == "U" else 0.0 * xc)
+    T = T0 * (1.0 + (0.2 * (xc - c.x_lo) / (c.x_hi - c.x_lo) if grad == "T" else 0.0 * xc))
+    psi = np.stack([rho + 0 * xc, rho * U, 0 * xc, 0 * xc, rho * (0.5 * U * U + 1.5 * c.R * T)], axis=1)
+    o.set_state(_hand_state(c, [np.zeros((0, 3))] * c.ncells, psi_w=psi))
+    sh = o.stress_heat()
+    w = c.omega
+    m, d = c.m_mol, c.d_ref
+    mu_bird = 15.0 * math.sqrt(math.pi * m * I.KB * c.T_ref) / (2.0 * math.pi * d * d * (5 - 2 * w) * (7 - 2 * w)) \
+        * (T / c.T_ref) ** w
+    inner = slice(1, c.ncells - 1)
+    assert np.all(sh[:, 4] == 1.0)
+    if grad == "U":
+        assert np.allclose(sh[inner, 0], -(4.0 / 3.0) * mu_bird[inner] * k, rtol=2e-4, atol=0)
+        # uniform T up to the rounding of T from the energy: no heat flux at that scale
+        assert np.all(np.abs(sh[inner, 1]) < 1e-12 * (15.0 / 4.0) * c.R * mu_bird[inner] * T0 / c.dx)
+    else:
+        dT = 0.2 * T0 / (c.x_hi - c.x_lo)
+        assert np.allclose(sh[inner, 1], -(15.0 / 4.0) * c.R * mu_bird[inner] * dT, rtol=2e-4, atol=0)
+        assert np.all(np.abs(sh[inner, 0]) < 1e-12 * (4.0 / 3.0) * mu_bird[inner] * U0 / c.dx)
