@@ -69,6 +69,8 @@ typedef struct {
     int32_t classify_law;         /* DUWP_P_* */
     int32_t eps_law;              /* DUWP_EPS_* */
     int32_t dsmc_full_dt;         /* 0: collide over (1-P) dt (default); 1: over dt */
+    int32_t flux_order;           /* 2: the wave flux's inviscid part takes MUSCL face states
+                                     (minmod slopes of (rho,U,V,W,T)); else first order */
     int64_t capacity;             /* particle capacity of this case; 0 = derived from the mass */
 } duwp_case;
 

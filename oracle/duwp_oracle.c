@@ -179,6 +179,15 @@ static int valid_state(const double W[5]) { return W[0] > 0.0 && W[4] > 0.0 && i
 
 void orc_wave_flux(const orc_state *s, const double Wl[5], const double Wr[5], double F[5])
 {
+    orc_wave_flux2(s, Wl, Wr, Wl, Wr, F);
+}
+
+/* The flux with separate inviscid face states: the KFVS part uses (ql, qr), the
+ * weight P_m, the viscosity and the central gradients use the cell states
+ * (Wl, Wr).  First order: ql = Wl, qr = Wr. */
+void orc_wave_flux2(const orc_state *s, const double Wl[5], const double Wr[5], const double ql[5],
+                    const double qr[5], double F[5])
+{
     const orc_case *c = &s->cs;
     for (int k = 0; k < 5; ++k) F[k] = 0.0;
     if (!valid_state(Wl) || !valid_state(Wr)) return;
@@ -190,8 +199,8 @@ void orc_wave_flux(const orc_state *s, const double Wl[5], const double Wr[5], d
     double Pm = absorb_fraction(c->classify_law, c->dt, tau);
     if (!(Pm > 0.0)) return;
     double Hp[5], Hm[5];
-    orc_kfvs_half(Wl, c->R, +1, Hp);
-    orc_kfvs_half(Wr, c->R, -1, Hm);
+    orc_kfvs_half(ql, c->R, +1, Hp);
+    orc_kfvs_half(qr, c->R, -1, Hm);
     double mue = orc_eps(c->eps_law, xr) * mu;
     double dU = (Wr[1] - Wl[1]) / s->dx;
     double dV = (Wr[2] - Wl[2]) / s->dx;
@@ -203,7 +212,29 @@ void orc_wave_flux(const orc_state *s, const double Wl[5], const double Wr[5], d
     double q = -(15.0 / 4.0) * c->R * mue * dT;
     double visc[5] = { 0.0, sxx, sxy, sxz, Wm[1] * sxx + Wm[2] * sxy + Wm[3] * sxz - q };
     for (int k = 0; k < 5; ++k)
-        F[k] = Pm * ((Wl[0] * Hp[k] + Wr[0] * Hm[k]) - visc[k]);
+        F[k] = Pm * ((ql[0] * Hp[k] + qr[0] * Hm[k]) - visc[k]);
+}
+
+static double minmod(double a, double b)
+{
+    if (a * b <= 0.0) return 0.0;
+    return fabs(a) < fabs(b) ? a : b;
+}
+
+/* Ghost states beyond the two ends: the reservoir state, or the mirror image of
+ * the boundary cell at a wall. */
+static void ghost_state(const orc_case *cs, int side, const double Wb[5], double G[5])
+{
+    const int res = side == 0 ? cs->bc_lo == 0 : cs->bc_hi == 0;
+    if (res) {
+        G[0] = side == 0 ? cs->rho_L : cs->rho_R;
+        G[1] = side == 0 ? cs->u_L : cs->u_R;
+        G[2] = 0.0; G[3] = 0.0;
+        G[4] = side == 0 ? cs->T_L : cs->T_R;
+    } else {
+        memcpy(G, Wb, 5 * sizeof(double));
+        G[1] = -Wb[1];
+    }
 }
 
 /* Equal-mass binary collision with isotropic scattering (Appendix A):
@@ -727,26 +758,44 @@ int orc_step_masked(orc_state *s, int32_t mask)
      * mirror image of the boundary cell at a wall. ---- */
     if (mask & ORC_WAVE) {
         double *F = calloc(((size_t)C + 1) * 5, sizeof(double));
-        if (!F) return -1;
-        for (int f = 0; f <= C; ++f) {
-            double Wl[5], Wr[5];
-            if (f == 0) {
-                memcpy(Wr, Wt, sizeof Wr);
-                if (cs->bc_lo == 0) { Wl[0] = cs->rho_L; Wl[1] = cs->u_L; Wl[2] = 0; Wl[3] = 0; Wl[4] = cs->T_L; }
-                else { memcpy(Wl, Wr, sizeof Wl); Wl[1] = -Wr[1]; }
-            } else if (f == C) {
-                memcpy(Wl, Wt + (C - 1) * 5, sizeof Wl);
-                if (cs->bc_hi == 0) { Wr[0] = cs->rho_R; Wr[1] = cs->u_R; Wr[2] = 0; Wr[3] = 0; Wr[4] = cs->T_R; }
-                else { memcpy(Wr, Wl, sizeof Wr); Wr[1] = -Wl[1]; }
-            } else {
-                memcpy(Wl, Wt + (f - 1) * 5, sizeof Wl);
-                memcpy(Wr, Wt + f * 5, sizeof Wr);
+        double *D = calloc((size_t)C * 5, sizeof(double));
+        if (!F || !D) { free(F); free(D); return -1; }
+        double G0[5], G1[5];
+        ghost_state(cs, 0, Wt, G0);
+        ghost_state(cs, 1, Wt + (C - 1) * 5, G1);
+        const int okg0 = cs->bc_lo == 0 || ok[0], okg1 = cs->bc_hi == 0 || ok[C - 1];
+        /* second order (flux_order 2): minmod slopes of the primitive state of each
+         * cell from its two neighbours (the ghost states beyond the ends); a vacuum
+         * cell or neighbour gives no slope */
+        if (cs->flux_order == 2) {
+            for (int c = 0; c < C; ++c) {
+                const double *Wm = c == 0 ? G0 : Wt + (c - 1) * 5;
+                const double *Wp = c == C - 1 ? G1 : Wt + (c + 1) * 5;
+                const int okm = c == 0 ? okg0 : ok[c - 1], okp = c == C - 1 ? okg1 : ok[c + 1];
+                if (!(ok[c] && okm && okp)) continue;
+                for (int k = 0; k < 5; ++k)
+                    D[c * 5 + k] = minmod(Wt[c * 5 + k] - Wm[k], Wp[k] - Wt[c * 5 + k]);
             }
-            /* an interface touching a vacuum cell carries no wave flux */
-            int okl = (f == 0) ? (cs->bc_lo == 0 || ok[0]) : ok[f - 1];
-            int okr = (f == C) ? (cs->bc_hi == 0 || ok[C - 1]) : ok[f];
-            if (okl && okr) orc_wave_flux(s, Wl, Wr, F + f * 5);
         }
+        for (int f = 0; f <= C; ++f) {
+            double Wl[5], Wr[5], ql[5], qr[5];
+            memcpy(Wl, f == 0 ? G0 : Wt + (f - 1) * 5, sizeof Wl);
+            memcpy(Wr, f == C ? G1 : Wt + f * 5, sizeof Wr);
+            /* inviscid face states: the cells' reconstructions; a reservoir ghost
+             * has none, and at a wall the ghost's face state is the mirror image
+             * of the boundary cell's, so that no mass or energy crosses the wall */
+            for (int k = 0; k < 5; ++k) {
+                ql[k] = f == 0 ? Wl[k] : Wl[k] + 0.5 * D[(f - 1) * 5 + k];
+                qr[k] = f == C ? Wr[k] : Wr[k] - 0.5 * D[f * 5 + k];
+            }
+            if (f == 0 && cs->bc_lo != 0) { memcpy(ql, qr, sizeof ql); ql[1] = -qr[1]; }
+            if (f == C && cs->bc_hi != 0) { memcpy(qr, ql, sizeof qr); qr[1] = -ql[1]; }
+            /* an interface touching a vacuum cell carries no wave flux */
+            int okl = (f == 0) ? okg0 : ok[f - 1];
+            int okr = (f == C) ? okg1 : ok[f];
+            if (okl && okr) orc_wave_flux2(s, Wl, Wr, ql, qr, F + f * 5);
+        }
+        free(D);
         double r = dt / dx;
         for (int c = 0; c < C; ++c)
             for (int k = 0; k < 5; ++k)

@@ -36,6 +36,7 @@ typedef struct {
     int32_t classify_law;       /* 0 P = max(0,1-tau/dt) (Eq. p); 1 P = 1-exp(-dt/tau) */
     int32_t eps_law;            /* 0 eps_1, 1 eps_12, 2 eps_0, 3 eps of Eq. vp */
     int32_t dsmc_full_dt;       /* 1: collide over dt instead of (1-P) dt */
+    int32_t flux_order;         /* 2: MUSCL-minmod inviscid face states; else first order */
 } orc_case;
 
 typedef struct orc_state orc_state;
@@ -90,6 +91,8 @@ double orc_eps(int32_t law, double x);
 void orc_kfvs_half(const double W[5], double R, int32_t sign, double H[5]);
 /* Wave flux at one interface from left/right primitive states. */
 void orc_wave_flux(const orc_state *s, const double Wl[5], const double Wr[5], double F[5]);
+void orc_wave_flux2(const orc_state *s, const double Wl[5], const double Wr[5], const double ql[5],
+                    const double qr[5], double F[5]);
 /* Post-collision velocities of an equal-mass pair for given uniforms (u3: cos theta, u4: phi). */
 void orc_scatter_pair(const double xi_i[3], const double xi_j[3], double u3, double u4,
                       double out_i[3], double out_j[3]);

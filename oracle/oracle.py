@@ -42,6 +42,7 @@ class _Case(C.Structure):
         ("m_particle", C.c_double), ("dt", C.c_double),
         ("bc_lo", C.c_int32), ("bc_hi", C.c_int32),
         ("classify_law", C.c_int32), ("eps_law", C.c_int32), ("dsmc_full_dt", C.c_int32),
+        ("flux_order", C.c_int32),
     ]
 
 
@@ -97,7 +98,7 @@ def make_case(case) -> _Case:
     d = case.to_dict() if hasattr(case, "to_dict") else dict(case)
     c = _Case()
     for name, _ in _Case._fields_:
-        setattr(c, name, d[name])
+        setattr(c, name, d.get(name, 0))
     return c
 
 

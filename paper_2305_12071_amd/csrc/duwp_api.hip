@@ -48,6 +48,7 @@ DCase derive(const duwp_case &c, int cell_base, uint64_t seed, int case_id)
     d.law = c.classify_law;
     d.eps_law = c.eps_law;
     d.full_dt = c.dsmc_full_dt;
+    d.flux2 = c.flux_order == 2;
     d.key0 = (uint32_t)seed;
     d.key1 = (uint32_t)(seed >> 32) + (uint32_t)case_id;
     d.x_lo = c.x_lo;

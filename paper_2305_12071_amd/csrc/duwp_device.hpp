@@ -22,7 +22,7 @@ enum : int32_t { ERR_CAPACITY = 1, ERR_RANGE = 2, ERR_STATE = 4 };
 // Per-case constants, derived on the host once.
 struct DCase {
     int32_t ncells, cell_base;
-    int32_t bc_lo, bc_hi, law, eps_law, full_dt, pad0;
+    int32_t bc_lo, bc_hi, law, eps_law, full_dt, flux2;   // flux2: MUSCL inviscid face states
     uint32_t key0, key1;
     int64_t inj_base, inj_cap;       // slot range of this case's entrants in the injection buffer
     int64_t cand_base[2], cand_cap[2];  // injection candidate slots per side

@@ -225,7 +225,11 @@ __device__ __forceinline__ double eps_factor(int law, double x)
 
 __device__ __forceinline__ bool valid_state(const double W[5]) { return W[0] > 0.0 && W[4] > 0.0 && isfinite(W[4]); }
 
-__device__ inline void face_flux(const DCase &c, const double Wl[5], const double Wr[5], double F[5])
+// Flux through a face with cell states (Wl, Wr): P_m, the viscosity and the
+// central gradients come from them; the KFVS part takes the inviscid face
+// states (ql, qr), which are (Wl, Wr) at first order.
+__device__ inline void face_flux(const DCase &c, const double Wl[5], const double Wr[5], const double ql[5],
+                                 const double qr[5], double F[5])
 {
 #pragma unroll
     for (int k = 0; k < 5; ++k) F[k] = 0.0;
@@ -239,8 +243,8 @@ __device__ inline void face_flux(const DCase &c, const double Wl[5], const doubl
     const double Pm = absorb_fraction(c.law, c.dt, tau);
     if (!(Pm > 0.0)) return;
     double Hp[5], Hm[5];
-    kfvs_half(Wl, c.R, +1, Hp);
-    kfvs_half(Wr, c.R, -1, Hm);
+    kfvs_half(ql, c.R, +1, Hp);
+    kfvs_half(qr, c.R, -1, Hm);
     const double mue = eps_factor(c.eps_law, xr) * mu;
     const double dU = (Wr[1] - Wl[1]) / c.dx;
     const double dV = (Wr[2] - Wl[2]) / c.dx;
@@ -252,50 +256,92 @@ __device__ inline void face_flux(const DCase &c, const double Wl[5], const doubl
     const double q = -(15.0 / 4.0) * c.R * mue * dT;
     const double visc[5] = {0.0, sxx, sxy, sxz, Wm[1] * sxx + Wm[2] * sxy + Wm[3] * sxz - q};
 #pragma unroll
-    for (int k = 0; k < 5; ++k) F[k] = Pm * ((Wl[0] * Hp[k] + Wr[0] * Hm[k]) - visc[k]);
+    for (int k = 0; k < 5; ++k) F[k] = Pm * ((ql[0] * Hp[k] + qr[0] * Hm[k]) - visc[k]);
+}
+
+// State of local cell lc of a case at step start, lc in [-1, C]: -1 and C are the
+// ghost states (the reservoir state, or the mirror image of the boundary cell at
+// a wall).  Returns 0 for a vacuum cell.
+__device__ inline int case_cell_state(const DCase &c, const Cells &cl, int lc, double W[5])
+{
+    const int C = c.ncells, base = c.cell_base;
+    if (lc >= 0 && lc < C) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) W[k] = cl.wt[(int64_t)(base + lc) * 5 + k];
+        return cl.okc[base + lc];
+    }
+    const int side = lc < 0 ? 0 : 1;
+    if ((side == 0 ? c.bc_lo : c.bc_hi) == 0) {
+        W[0] = side == 0 ? c.rho_L : c.rho_R;
+        W[1] = side == 0 ? c.u_L : c.u_R;
+        W[2] = 0.0; W[3] = 0.0;
+        W[4] = side == 0 ? c.T_L : c.T_R;
+        return 1;
+    }
+    const int b = side == 0 ? base : base + C - 1;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) W[k] = cl.wt[(int64_t)b * 5 + k];
+    W[1] = -W[1];
+    return cl.okc[b];
+}
+
+__device__ __forceinline__ double minmod(double a, double b)
+{
+    if (a * b <= 0.0) return 0.0;
+    return fabs(a) < fabs(b) ? a : b;
+}
+
+// Minmod slope of the primitive state of local cell lc (zero for a ghost, or
+// when the cell or a neighbour is vacuum)
+__device__ inline void case_slope(const DCase &c, const Cells &cl, int lc, double D[5])
+{
+#pragma unroll
+    for (int k = 0; k < 5; ++k) D[k] = 0.0;
+    if (lc < 0 || lc >= c.ncells) return;
+    double W[5], Wm[5], Wp[5];
+    const int ok = case_cell_state(c, cl, lc, W);
+    const int okm = case_cell_state(c, cl, lc - 1, Wm);
+    const int okp = case_cell_state(c, cl, lc + 1, Wp);
+    if (!(ok && okm && okp)) return;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) D[k] = minmod(W[k] - Wm[k], Wp[k] - W[k]);
 }
 
 // flux through local face f (between local cells f-1 and f) of a case
 __device__ inline void case_face_flux(const DCase &c, const Cells &cl, int f, double F[5])
 {
-    const int C = c.ncells, base = c.cell_base;
     double Wl[5], Wr[5];
-    int okl, okr;
-    if (f == 0) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) Wr[k] = cl.wt[(int64_t)base * 5 + k];
-        if (c.bc_lo == 0) { Wl[0] = c.rho_L; Wl[1] = c.u_L; Wl[2] = 0.0; Wl[3] = 0.0; Wl[4] = c.T_L; }
-        else {
-#pragma unroll
-            for (int k = 0; k < 5; ++k) Wl[k] = Wr[k];
-            Wl[1] = -Wr[1];
-        }
-        okl = (c.bc_lo == 0) || cl.okc[base];
-        okr = cl.okc[base];
-    } else if (f == C) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) Wl[k] = cl.wt[(int64_t)(base + C - 1) * 5 + k];
-        if (c.bc_hi == 0) { Wr[0] = c.rho_R; Wr[1] = c.u_R; Wr[2] = 0.0; Wr[3] = 0.0; Wr[4] = c.T_R; }
-        else {
-#pragma unroll
-            for (int k = 0; k < 5; ++k) Wr[k] = Wl[k];
-            Wr[1] = -Wl[1];
-        }
-        okl = cl.okc[base + C - 1];
-        okr = (c.bc_hi == 0) || cl.okc[base + C - 1];
-    } else {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            Wl[k] = cl.wt[(int64_t)(base + f - 1) * 5 + k];
-            Wr[k] = cl.wt[(int64_t)(base + f) * 5 + k];
-        }
-        okl = cl.okc[base + f - 1];
-        okr = cl.okc[base + f];
-    }
-    if (okl && okr) face_flux(c, Wl, Wr, F);
-    else {
+    const int okl = case_cell_state(c, cl, f - 1, Wl);
+    const int okr = case_cell_state(c, cl, f, Wr);
+    if (!(okl && okr)) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) F[k] = 0.0;
+        return;
+    }
+    if (c.flux2) {
+        double Dl[5], Dr[5], ql[5], qr[5];
+        case_slope(c, cl, f - 1, Dl);
+        case_slope(c, cl, f, Dr);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            ql[k] = Wl[k] + 0.5 * Dl[k];
+            qr[k] = Wr[k] - 0.5 * Dr[k];
+        }
+        // at a wall the ghost's face state mirrors the boundary cell's (no mass or
+        // energy through the wall); a reservoir ghost keeps its own state
+        if (f == 0 && c.bc_lo != 0) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) ql[k] = qr[k];
+            ql[1] = -qr[1];
+        }
+        if (f == c.ncells && c.bc_hi != 0) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) qr[k] = ql[k];
+            qr[1] = -ql[1];
+        }
+        face_flux(c, Wl, Wr, ql, qr, F);
+    } else {
+        face_flux(c, Wl, Wr, Wl, Wr, F);
     }
 }
 

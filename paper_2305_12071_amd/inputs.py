@@ -72,6 +72,7 @@ class Case:
     classify_law: int = CLASSIFY_RATIONAL
     eps_law: int = EPS1
     dsmc_full_dt: int = 0    # 1: DSMC collides over the full dt instead of (1-P) dt
+    flux_order: int = 1      # 2: MUSCL-minmod inviscid face states in the wave flux
     capacity: int = 0        # particle capacity hint (0 = derive)
     name: str = ""
 

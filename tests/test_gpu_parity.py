@@ -41,6 +41,16 @@ def _cases():
     out["sod_eps12_fulldt"] = c
     c = I.box(7, 0.8, 2.0, 150, 0.5, u=0.3)
     out["box_ragged"] = c
+    # second-order (MUSCL-minmod) wave flux: walls, reservoirs, noisy slopes
+    c = I.sod_paper(1e-5)
+    c.flux_order = 2
+    out["sod_kn1e-5_muscl"] = c
+    c = I.argon_shock(3.0, 60, 60 * 20.0, 3e4, name="shock_dx20_muscl")
+    c.flux_order = 2
+    out["shock_dx20_muscl"] = c
+    c = I.box(7, 0.8, 2.0, 150, 3.0, u=0.3)
+    c.flux_order = 2
+    out["box_ragged_muscl"] = c
     return out
 
 
