@@ -57,7 +57,7 @@ def kernel_fingerprint(kernel: str) -> str:
         src = fh.read()
     name = kernel.split("<")[0]
     i0 = src.index(f") {name}(")
-    i0 = src.rindex("template <typename T>", 0, i0) if "<" in kernel else src.rindex("__global__", 0, i0)
+    i0 = src.rindex("template <typename T", 0, i0) if "<" in kernel else src.rindex("__global__", 0, i0)
     i1 = src.find("\n// ", i0 + 1)
     h = hashlib.sha256(src[i0:i1 if i1 > 0 else len(src)].encode())
     for f in KERNEL_HEADERS:
@@ -113,14 +113,16 @@ def block_size(cases, precision, args):
     return (bc, "cache") if bc else (256, "default")
 
 
-def roofline_of(sim, profile_steps, workload):
+def roofline_of(sim, profile_steps, workload, block_cells):
     """Dominant particle-streaming kernel: algorithmic bytes over its event-timed duration."""
     kms = sim.profile(profile_steps)
     prof_ps = sim.particle_steps(reset=True) / profile_steps
     dom = max((k for k in kms if k in BYTES_PER_PARTICLE), key=lambda k: kms[k])
     alg_bytes = BYTES_PER_PARTICLE[dom](4) * prof_ps
     achieved = alg_bytes / (kms[dom] * 1e-3) / 1e9
-    kname = {"scatter": "k_scatter<float>", "absorb_resample": "k_absorb_resample<float>"}.get(dom)
+    # the scatter's instance: one-wave blocks get the small-LDS variant
+    scat = "k_scatter<float, 1>" if block_cells == 64 else "k_scatter<float, 8>"
+    kname = {"scatter": scat, "absorb_resample": "k_absorb_resample<float>"}.get(dom)
     tr = counted_traffic(kname, workload) if kname else None
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -211,7 +213,7 @@ def main():
                     help="also time the batched cases one context per case (plain FP64)")
     ap.add_argument("--large-particles", type=float, default=1e9)
     ap.add_argument("--large-steps", type=int, default=5)
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -256,7 +258,7 @@ def main():
         n_now = sim.total_particles()
         log(f"  {args.steps} steps in {dt:.3f}s -> {value:.4e} particle-steps/s")
         # per-kernel device time (HIP events on the library's stream, eager launches)
-        roofline, kernels = roofline_of(sim, args.profile_steps, case.name)
+        roofline, kernels = roofline_of(sim, args.profile_steps, case.name, bc)
         log("  kernels (ms):", json.dumps(kernels))
         if "cpu" in legs:
             from oracle import oracle as O

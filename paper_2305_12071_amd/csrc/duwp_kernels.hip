@@ -374,6 +374,45 @@ __global__ void __launch_bounds__(256) k_items(const int64_t *__restrict__ cbase
     for (int64_t w = lo / S + 1; w * S <= hi && w < nitems; ++w) item_cell[w] = g;
 }
 
+// The candidate scan and k_items in one block of 1024 threads (G <= SCAN1_MAX):
+// cbase[g] = candidates of the cells before g; the thread holding cell g writes
+// the items w with cbase[g] < w S <= cbase[g + 1], which start at cell g + 1.
+__global__ void __launch_bounds__(1024) k_scan_items(const int32_t *__restrict__ in, int G, int64_t *cbase,
+                                                     int64_t *total, int32_t *item_cell, int64_t *d_items,
+                                                     int64_t items_cap)
+{
+    __shared__ int64_t lds[16];
+    const int t0 = threadIdx.x * SCAN1_ITEMS;
+    int64_t v[SCAN1_ITEMS];
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN1_ITEMS; ++i) {
+        v[i] = (t0 + i < G) ? in[t0 + i] : 0;
+        s += v[i];
+    }
+    int64_t tot;
+    int64_t run = block_exclusive_scan64(s, lds, &tot);
+    int64_t S = (tot + items_cap - 2) / (items_cap - 1);   // at most items_cap - 1 items
+    S = S < WAVE ? WAVE : (S + WAVE - 1) / WAVE * WAVE;
+    const int64_t nitems = (tot + S - 1) / S;
+    if (threadIdx.x == 0) {
+        d_items[0] = nitems;
+        d_items[1] = S;
+        *total = tot;
+        cbase[G] = tot;
+        if (nitems > 0) item_cell[0] = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < SCAN1_ITEMS; ++i) {
+        const int g = t0 + i;
+        if (g < G) {
+            cbase[g] = run;
+            for (int64_t w = run / S + 1; w * S <= run + v[i] && w < nitems; ++w) item_cell[w] = g + 1;
+        }
+        run += v[i];
+    }
+}
+
 __device__ __forceinline__ uint32_t coll_slot(int g, uint32_t i)
 {
     return ((uint32_t)g * 0x9E3779B1u ^ i * 0x85EBCA77u) * 0xC2B2AE3Du >> (32 - COLL_HBITS);
@@ -1119,7 +1158,7 @@ __device__ __forceinline__ void add_phi(double (&a)[5], double u, double v, doub
 }
 
 
-template <typename T>
+template <typename T, int MAXW>
 __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
                                                  Soa<T> stg, Soa<T> dst, const int64_t *__restrict__ off_new,
                                                  int G, int64_t cap, int32_t *err, int64_t *d_nout)
@@ -1136,8 +1175,9 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
     // chunk behind a single barrier.  Two register sets alternate: the next
     // chunk is loaded into one while the other is placed, with no copy between
     // them (a copy would wait for the loads just issued).
+    // MAXW: the most waves a block has (blockDim <= 64 MAXW); a one-wave block
+    // keeps its LDS small so that more blocks fit on a CU
     constexpr int IT = 4;
-    constexpr int MAXW = 8;
     __shared__ int binbase[2][NBIN];     // by chunk parity
     __shared__ int bin0[NBIN];
     __shared__ int64_t offb[NBIN];
@@ -1401,10 +1441,19 @@ __global__ void __launch_bounds__(256) k_wave(const DCase *__restrict__ cases, C
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict__ cases, Cells cl, Soa<T> dst,
-                                                        const int64_t *__restrict__ off_new, int G, int32_t *err)
+                                                        const int64_t *__restrict__ off_new, int G, int32_t *err,
+                                                        uint32_t *d_step, const int64_t *__restrict__ off_old,
+                                                        int64_t *d_psteps)
 {
     const int lane = lane_id();
     const int d = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * WAVE + lane;
+    // the step's close: particle-steps (particles alive at its start), step
+    // index, and the big-cell list emptied for the next step
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *d_psteps += off_old[G];
+        *d_step += 1;
+        *cl.nbig = 0;
+    }
     if ((d - lane) >= G) return;
     const bool in = d < G;
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1581,15 +1630,6 @@ __global__ void __launch_bounds__(512) k_moments(const DCase *__restrict__ cases
 }
 
 // closes the step: particle-steps of this step (particles alive at its start), step index
-__global__ void k_finish(uint32_t *d_step, const int64_t *__restrict__ off, int G, int64_t *d_psteps,
-                         int32_t *nbig)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        *d_psteps += off[G];
-        *d_step += 1;
-        *nbig = 0;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Step sequence
@@ -1670,24 +1710,34 @@ static void step_impl(duwp_ctx *ctx)
         Mark m(ctx, "wave");
         hipLaunchKernelGGL(k_wave, dim3(gthreads), dim3(256), 0, s2, ctx->d_cases, cl, G);
     }
+    {
+        // cells with many particles and candidates (their own list): disjoint
+        // from the cells of k_collide, so the two run side by side
+        Mark m(ctx, "collide_big");
+        hipLaunchKernelGGL(k_big_bases, dim3(1), dim3(1024), 0, s2, cl);
+        hipLaunchKernelGGL(k_collide_big<T>, dim3(ctx->big_blocks), dim3(BigCfg<T>::B), 0, s2, ctx->d_cases,
+                           cl, src, stg, (P4<T> *)ctx->pk, ctx->d_step, ctx->cap);
+    }
     if (fork) (void)hipEventRecord(ctx->ev_join, s2);
     {
         Mark m(ctx, "collide");
-        enqueue_scan(ctx, ctx->cl.ncand_w, ctx->cl.cbase, ctx->d_total + 2, INT64_MAX);
-        hipLaunchKernelGGL(k_items, dim3((G + 1 + 255) / 256), dim3(256), 0, st, ctx->cl.cbase, G, ctx->item_cell,
-                           ctx->d_items, ctx->items_cap);
+        if (G <= SCAN1_MAX)
+            hipLaunchKernelGGL(k_scan_items, dim3(1), dim3(1024), 0, st, ctx->cl.ncand_w, G, ctx->cl.cbase,
+                               ctx->d_total + 2, ctx->item_cell, ctx->d_items, ctx->items_cap);
+        else {
+            enqueue_scan(ctx, ctx->cl.ncand_w, ctx->cl.cbase, ctx->d_total + 2, INT64_MAX);
+            hipLaunchKernelGGL(k_items, dim3((G + 1 + 255) / 256), dim3(256), 0, st, ctx->cl.cbase, G,
+                               ctx->item_cell, ctx->d_items, ctx->items_cap);
+        }
         hipLaunchKernelGGL(k_collide<T>, dim3(ctx->coll_blocks), dim3(64 * COLL_WPB), 0, st, ctx->d_cases,
                            cl, src, stg, ctx->d_step, G, ctx->cap, ctx->d_err, ctx->item_cell, ctx->d_items);
-        hipLaunchKernelGGL(k_big_bases, dim3(1), dim3(1024), 0, st, cl);
-        hipLaunchKernelGGL(k_collide_big<T>, dim3(ctx->big_blocks), dim3(BigCfg<T>::B), 0, st, ctx->d_cases,
-                           cl, src, stg, (P4<T> *)ctx->pk, ctx->d_step, ctx->cap);
     }
+    if (fork) (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
     {
         Mark m(ctx, "hist_fix");
         hipLaunchKernelGGL(k_hist_build<T>, dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg, ctx->off[p], G,
                            ctx->cap, 0);
     }
-    if (fork) (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
     {
         Mark m(ctx, "count_new");
         hipLaunchKernelGGL(k_count_new, dim3((G + 3) / 4), dim3(256), 0, st, cl, G);
@@ -1702,8 +1752,12 @@ static void step_impl(duwp_ctx *ctx)
     }
     {
         Mark m(ctx, "scatter");
-        hipLaunchKernelGGL(k_scatter<T>, dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg, dst,
-                           ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout);
+        if (bc == WAVE)
+            hipLaunchKernelGGL((k_scatter<T, 1>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg, dst,
+                               ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout);
+        else
+            hipLaunchKernelGGL((k_scatter<T, 8>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg, dst,
+                               ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout);
     }
     {
         Mark m(ctx, "scatter_inj");
@@ -1713,12 +1767,7 @@ static void step_impl(duwp_ctx *ctx)
     {
         Mark m(ctx, "gather_moments");
         hipLaunchKernelGGL(k_gather_moments<T>, dim3((G + 255) / 256), dim3(256), 0, st, ctx->d_cases, cl, dst,
-                           ctx->off[p ^ 1], G, ctx->d_err);
-    }
-    {
-        Mark m(ctx, "finish");
-        hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, ctx->d_step, ctx->off[p], G, ctx->d_psteps,
-                           ctx->cl.nbig);
+                           ctx->off[p ^ 1], G, ctx->d_err, ctx->d_step, ctx->off[p], ctx->d_psteps);
     }
 }
 
