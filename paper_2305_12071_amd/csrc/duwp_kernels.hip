@@ -590,23 +590,30 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
 // 4b. NTC / VHS collisions of cells with many particles and candidates: one
 // block per cell, BigCfg<T>::B candidates at a time (one per thread).
 //
-// Few cells are in flight at once (one block per compute unit), so the random
-// pair accesses of a cell stay in the caches.  For each of its particles a
-// candidate needs the last earlier candidate of the chunk that touched it: an
-// LDS hash table keyed exactly by particle index records up to BIG_LIST
-// candidates per particle, and the largest one below the candidate's own index
-// is its predecessor.  Candidates then run in block-wide rounds once their (at
-// most two) predecessors have run, taking velocities from the predecessors'
-// LDS slots.  A particle drawn by more than BIG_LIST candidates of one chunk
-// (rare) sends that chunk through a serial path.  Histogram moves are summed in
-// LDS and added once per cell.
+// For each of its particles a candidate needs the last earlier candidate of the
+// chunk that touched it: an LDS hash table keyed exactly by particle index
+// records up to BIG_LIST candidates per particle, and the largest one below the
+// candidate's own index is its predecessor.  Candidates then run in block-wide
+// rounds once their (at most two) predecessors have run, taking velocities from
+// the predecessors' LDS slots.  A particle drawn by more than BIG_LIST
+// candidates of one chunk (rare) sends that chunk through a serial path.
+//
+// The random particle reads dominate: two blocks share a compute unit, and the
+// rounds' barriers order LDS only, so that the stores of a round do not hold up
+// the next.  The histogram moves of the collisions telescope: each particle
+// moves once, from the bin of its velocity before the collide stage to the bin
+// of its final one, summed in LDS when the velocities are written back.
 // ---------------------------------------------------------------------------
-constexpr int BIG_SLOTS = 4096;   // hash slots: at least twice the particles of a chunk
 constexpr int BIG_LIST = 4;
 
+// B threads (candidates per chunk), 2^HBITS hash slots (at least twice the
+// particles a chunk draws), PER_CU blocks resident per compute unit (LDS bound)
 template <typename T>
 struct BigCfg {
-    static constexpr int B = sizeof(T) == 4 ? 1024 : 512;
+    static constexpr int B = sizeof(T) == 4 ? 512 : 256;
+    static constexpr int HBITS = sizeof(T) == 4 ? 11 : 10;
+    static constexpr int SLOTS = 1 << HBITS;
+    static constexpr int PER_CU = 2;
 };
 
 // (x, u, v, w) of one particle in one 16- or 32-byte record: a random access to
@@ -633,14 +640,15 @@ __global__ void __launch_bounds__(1024) k_big_bases(Cells cl)
     }
 }
 
+template <int HBITS>
 __device__ __forceinline__ int big_insert(uint32_t *hkey, int *hcnt, uint16_t (*hlst)[BIG_LIST], uint32_t p,
                                           int t, int *ovf)
 {
-    uint32_t h = (p * 0x9E3779B1u) >> (32 - 12);
+    uint32_t h = (p * 0x9E3779B1u) >> (32 - HBITS);
     while (true) {
         const uint32_t prev = atomicCAS(&hkey[h], 0xffffffffu, p);
         if (prev == 0xffffffffu || prev == p) break;
-        h = (h + 1) & (BIG_SLOTS - 1);
+        h = (h + 1) & ((1u << HBITS) - 1);
     }
     const int k = atomicAdd(&hcnt[h], 1);
     if (k < BIG_LIST) hlst[h][k] = (uint16_t)t;
@@ -677,24 +685,6 @@ __device__ __forceinline__ void big_pair(const DCase &c, uint32_t step, int lc, 
     u2 = u01(rb.a); u3 = u01(rb.b); u4 = u01(rb.c);
 }
 
-// move the pair between destination bins of this step's histogram (summed in hd)
-template <typename T>
-__device__ __forceinline__ void big_bins(const DCase &c, int lc, T xi, T ui0, T ui, T xj, T uj0, T uj, int *hd,
-                                         bool &far)
-{
-    bool f0 = false;
-    const int a0 = flight_bin<T>(c, lc, xi, ui0, &f0), a1 = flight_bin<T>(c, lc, xi, ui, &far);
-    const int b0 = flight_bin<T>(c, lc, xj, uj0, &f0), b1 = flight_bin<T>(c, lc, xj, uj, &far);
-    if (a0 != a1) {
-        if (a0 >= 0) atomicSub(&hd[a0], 1);
-        if (a1 >= 0) atomicAdd(&hd[a1], 1);
-    }
-    if (b0 != b1) {
-        if (b0 >= 0) atomicSub(&hd[b0], 1);
-        if (b1 >= 0) atomicAdd(&hd[b1], 1);
-    }
-}
-
 template <typename T>
 __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__restrict__ cases, Cells cl,
                                                                Soa<T> src, Soa<T> stg, P4<T> *__restrict__ pk,
@@ -702,9 +692,11 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
 {
     constexpr int B = BigCfg<T>::B;
     constexpr int NW = B / WAVE;
-    __shared__ uint32_t hkey[BIG_SLOTS];
-    __shared__ int hcnt[BIG_SLOTS];
-    __shared__ uint16_t hlst[BIG_SLOTS][BIG_LIST];
+    constexpr int SLOTS = BigCfg<T>::SLOTS;
+    constexpr int HB = BigCfg<T>::HBITS;
+    __shared__ uint32_t hkey[SLOTS];
+    __shared__ int hcnt[SLOTS];
+    __shared__ uint16_t hlst[SLOTS][BIG_LIST];
     __shared__ uint32_t ci[B];
     __shared__ int done[B];
     __shared__ T fwd[6][B];
@@ -712,10 +704,22 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
     __shared__ double redd[NW];
     __shared__ int redi[NW];
     __shared__ int ovf[2];           // by chunk parity
+    __shared__ int rflag[NW];        // per-wave "still waiting" flags of a round
     const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
     const uint32_t step = *d_step;
     const int nbig = *cl.nbig;
-    for (int s = t; s < BIG_SLOTS; s += B) { hkey[s] = 0xffffffffu; hcnt[s] = 0; }
+    for (int s = t; s < SLOTS; s += B) { hkey[s] = 0xffffffffu; hcnt[s] = 0; }
+    // barrier over LDS only (the rounds exchange nothing else through memory),
+    // true when any thread of the block passes v
+    auto lds_any = [&](bool v) {
+        const uint64_t b = __ballot(v);
+        if (lane == 0) rflag[wv] = b != 0;
+        lds_barrier();
+        bool r = false;
+#pragma unroll
+        for (int w2 = 0; w2 < NW; ++w2) r |= rflag[w2] != 0;
+        return r;
+    };
     for (int e = blockIdx.x; e < nbig; e += gridDim.x) {
         const int g = cl.big_list[e];
         const int k = cl.cell_case[g];
@@ -729,9 +733,10 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
         if (sb + N > cap || pb + N > cap) continue;   // capacity overflow, already reported (block-uniform)
         T *pu = sg.u + sb, *pv = sg.v + sb, *pw = sg.w + sb;
         const T *px = sg.x + sb;
-        // the cell's particles as (x,u,v,w) records for the random pair accesses
+        // the cell's velocities as one record per particle for the random pair
+        // accesses (the x slot is not used)
         P4<T> *P = pk + pb;
-        for (int i = t; i < N; i += B) P[i] = P4<T>{px[i], pu[i], pv[i], pw[i]};
+        for (int i = t; i < N; i += B) P[i] = P4<T>{T(0), pu[i], pv[i], pw[i]};
         __threadfence_block();
         const double cm = cl.cr_max[g];
         const double aexp = 1.0 - 2.0 * c.ups;
@@ -740,26 +745,25 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
         __syncthreads();
         double seen = 0.0;
         int acc = 0;
-        bool far = false;
         int par = 0;
         for (int64_t q0 = 0; q0 < M; q0 += B, par ^= 1) {
             const int64_t q = q0 + t;
             const bool act = q < M;
             uint32_t i = 0, j = 0;
             double u2 = 0.0, u3 = 0.0, u4 = 0.0;
-            T xi = 0, ui = 0, vi = 0, wi = 0, xj = 0, uj = 0, vj = 0, wj = 0;
+            T ui = 0, vi = 0, wi = 0, uj = 0, vj = 0, wj = 0;
             int si = 0, sj = 0;
             if (act) {
                 big_pair<T>(c, step, lc, (uint32_t)q, N, i, j, u2, u3, u4);
                 const P4<T> a = P[i], bq = P[j];
-                xi = a.x; ui = a.u; vi = a.v; wi = a.w;
-                xj = bq.x; uj = bq.u; vj = bq.v; wj = bq.w;
-                si = big_insert(hkey, hcnt, hlst, i, t, &ovf[par]);
-                sj = big_insert(hkey, hcnt, hlst, j, t, &ovf[par]);
+                ui = a.u; vi = a.v; wi = a.w;
+                uj = bq.u; vj = bq.v; wj = bq.w;
+                si = big_insert<HB>(hkey, hcnt, hlst, i, t, &ovf[par]);
+                sj = big_insert<HB>(hkey, hcnt, hlst, j, t, &ovf[par]);
             }
             ci[t] = i;
             done[t] = act ? 0 : 1;
-            __syncthreads();
+            lds_barrier();
             const bool serial = ovf[par] != 0;
             // the next chunk's flag: its last readers were in the previous chunk
             if (t == 0) ovf[par ^ 1] = 0;
@@ -773,12 +777,10 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
                         double v2, v3, v4;
                         big_pair<T>(c, step, lc, (uint32_t)(q0 + l), N, a, bq, v2, v3, v4);
                         P4<T> ra = P[a], rb = P[bq];
-                        const T ua0 = ra.u, ub0 = rb.u;
                         if (collide_vals<T>(ra.u, ra.v, ra.w, rb.u, rb.v, rb.w, cm, aexp, v2, v3, v4, seen)) {
                             ++acc;
                             P[a] = ra;
                             P[bq] = rb;
-                            big_bins<T>(c, lc, ra.x, ua0, ra.u, rb.x, ub0, rb.u, hd, far);
                         }
                     }
                 }
@@ -792,23 +794,21 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
                 bool mine = act;
                 while (true) {
                     const bool ready = mine && (pi < 0 || done[pi]) && (pj < 0 || done[pj]);
-                    __syncthreads();
+                    lds_barrier();
                     if (ready) {
                         if (pi >= 0) { ui = fwd[oi][pi]; vi = fwd[oi + 1][pi]; wi = fwd[oi + 2][pi]; }
                         if (pj >= 0) { uj = fwd[oj][pj]; vj = fwd[oj + 1][pj]; wj = fwd[oj + 2][pj]; }
-                        const T ui0 = ui, uj0 = uj;
                         if (collide_vals<T>(ui, vi, wi, uj, vj, wj, cm, aexp, u2, u3, u4, seen)) {
                             ++acc;
-                            P[i] = P4<T>{xi, ui, vi, wi};
-                            P[j] = P4<T>{xj, uj, vj, wj};
-                            big_bins<T>(c, lc, xi, ui0, ui, xj, uj0, uj, hd, far);
+                            P[i] = P4<T>{T(0), ui, vi, wi};
+                            P[j] = P4<T>{T(0), uj, vj, wj};
                         }
                         fwd[0][t] = ui; fwd[1][t] = vi; fwd[2][t] = wi;
                         fwd[3][t] = uj; fwd[4][t] = vj; fwd[5][t] = wj;
                         done[t] = 1;
                         mine = false;
                     }
-                    if (!__syncthreads_or(mine)) break;
+                    if (!lds_any(mine)) break;
                 }
             }
             // empty the table for the next chunk; make this chunk's stores visible to it
@@ -819,9 +819,21 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
             __threadfence_block();
             __syncthreads();
         }
-        // velocities back to the cell's segment
+        // velocities back to the cell's segment; a particle whose x velocity
+        // changed moves between destination bins of this step's histogram
+        bool far = false;
         for (int i = t; i < N; i += B) {
             const P4<T> r = P[i];
+            const T u0 = pu[i];
+            if (r.u != u0) {
+                bool f0 = false;
+                const T x = px[i];
+                const int a0 = flight_bin<T>(c, lc, x, u0, &f0), a1 = flight_bin<T>(c, lc, x, r.u, &far);
+                if (a0 != a1) {
+                    if (a0 >= 0) atomicSub(&hd[a0], 1);
+                    if (a1 >= 0) atomicAdd(&hd[a1], 1);
+                }
+            }
             pu[i] = r.u; pv[i] = r.v; pw[i] = r.w;
         }
         // per-cell results
@@ -1715,7 +1727,8 @@ static void step_impl(duwp_ctx *ctx)
         // from the cells of k_collide, so the two run side by side
         Mark m(ctx, "collide_big");
         hipLaunchKernelGGL(k_big_bases, dim3(1), dim3(1024), 0, s2, cl);
-        hipLaunchKernelGGL(k_collide_big<T>, dim3(ctx->big_blocks), dim3(BigCfg<T>::B), 0, s2, ctx->d_cases,
+        hipLaunchKernelGGL(k_collide_big<T>, dim3(ctx->big_blocks * BigCfg<T>::PER_CU), dim3(BigCfg<T>::B), 0, s2,
+                           ctx->d_cases,
                            cl, src, stg, (P4<T> *)ctx->pk, ctx->d_step, ctx->cap);
     }
     if (fork) (void)hipEventRecord(ctx->ev_join, s2);
