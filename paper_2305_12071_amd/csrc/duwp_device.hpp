@@ -34,6 +34,24 @@ struct DCase {
     float dtdx_f, pad1;              // dt/dx for the cell-relative FP32 positions
 };
 
+// The constants a per-cell loop reads for every particle (free flight, random
+// draws, sampling), held in registers: a reference into global memory is read
+// again after each fence inside the loop.
+struct CaseK {
+    const DCase *pc;                 // the whole case, for the rare paths
+    double x_lo, x_hi, dx, dt, R;
+    float dtdx_f;
+    int ncells;
+    uint32_t key0, key1;
+    __device__ explicit CaseK(const DCase &c)
+        : pc(&c), x_lo(c.x_lo), x_hi(c.x_hi), dx(c.dx), dt(c.dt), R(c.R), dtdx_f(c.dtdx_f), ncells(c.ncells),
+          key0(c.key0), key1(c.key1)
+    {
+    }
+};
+__device__ __forceinline__ const DCase &case_of(const DCase &c) { return c; }
+__device__ __forceinline__ const DCase &case_of(const CaseK &k) { return *k.pc; }
+
 // Per-step, per-cell work arrays shared by the stage kernels.
 struct Cells {
     double *psi_w;      // [G*5] wave part
@@ -106,8 +124,8 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     return U4{c0, c1, c2, c3};
 }
 
-__device__ __forceinline__ U4 draw(const DCase &cs, uint32_t step, uint32_t a, uint32_t b,
-                                   uint32_t tag, uint32_t j)
+template <typename K>
+__device__ __forceinline__ U4 draw(const K &cs, uint32_t step, uint32_t a, uint32_t b, uint32_t tag, uint32_t j)
 {
     return philox(step, a, b, (tag << 16) | j, cs.key0, cs.key1);
 }
@@ -199,6 +217,57 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double *red)
         v[k] = s;
     }
     __syncthreads();
+}
+
+// Wave sums of N <= 16 doubles by recursive halving: at each of the steps 32,
+// 16, 8, 4 a lane keeps the half of its values chosen by that bit of its index
+// and adds the partner's copy, so the sum of value q ends in lanes 4q..4q+3
+// (the last two steps add those four).  Returns the sum of value lane/4 (0 for
+// q >= N).  17 exchanges instead of 6 per value.
+template <int N>
+__device__ __forceinline__ double wave_sum_spread(const double (&v)[N])
+{
+    static_assert(N <= 16, "at most 16 values");
+    const int lane = lane_id();
+    double a[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) a[q] = q < N ? v[q] : 0.0;
+#pragma unroll
+    for (int h = 8, o = 32; h >= 1; h >>= 1, o >>= 1) {
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int q = 0; q < h; ++q) {
+            const double keep = up ? a[h + q] : a[q];
+            const double send = up ? a[q] : a[h + q];
+            a[q] = keep + __shfl_xor(send, o, WAVE);
+        }
+    }
+    double e = a[0];
+    e += __shfl_xor(e, 2, WAVE);
+    e += __shfl_xor(e, 1, WAVE);
+    return e;
+}
+
+// Block sum of value q of N <= 16 doubles per thread, returned in thread q
+// (q < N; other threads get 0).  red must hold N * (blockDim/64) doubles.
+// Deterministic: a fixed tree inside each wave, then the waves in order.
+template <int N>
+__device__ __forceinline__ double block_sum_to_thread(const double (&v)[N], double *red)
+{
+    const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const double e = wave_sum_spread<N>(v);
+    if (nw == 1) {
+        const double r = __shfl(e, (lane & 15) * 4, WAVE);
+        return lane < N ? r : 0.0;
+    }
+    __syncthreads();
+    if ((lane & 3) == 0 && (lane >> 2) < N) red[(lane >> 2) * nw + w] = e;
+    __syncthreads();
+    double s = 0.0;
+    if ((int)threadIdx.x < N)
+        for (int i = 0; i < nw; ++i) s += red[threadIdx.x * nw + i];
+    __syncthreads();
+    return s;
 }
 
 // Exclusive block prefix of a 0/1 flag; returns this thread's prefix, *total the block total.

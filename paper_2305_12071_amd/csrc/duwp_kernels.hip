@@ -179,8 +179,8 @@ static void enqueue_scan(duwp_ctx *ctx, const int32_t *in, int64_t *out, int64_t
 // Destination bin (d + KWIN) of a particle of local cell lc after free flight;
 // -1 when it leaves through a reservoir (or moves farther than the window,
 // then *far is set).
-template <typename T>
-__device__ __forceinline__ int flight_bin(const DCase &c, int lc, T x, T u, bool *far)
+template <typename T, typename K>
+__device__ __forceinline__ int flight_bin(const K &c, int lc, T x, T u, bool *far)
 {
     const int dest = Flight<T>::go(c, lc, x, u);
     if (dest < 0) return -1;
@@ -223,6 +223,7 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
         }
         const int k = cl.cell_case[g];
         const DCase &c = cases[k];
+        const CaseK ck(c);
         const int lc = g - c.cell_base;
         const double P = cl.pc[g];
         const int64_t b = off[g], e = off[g + 1];
@@ -244,7 +245,7 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
                 T xs[4], us[4], vs[4], ws[4];
                 int keep = 0;
                 if (qd <= qb) {
-                    const U4 r = draw(c, step, (uint32_t)qd, 0, TAG_CLS, 0);
+                    const U4 r = draw(ck, step, (uint32_t)qd, 0, TAG_CLS, 0);
                     const uint32_t wd[4] = {r.a, r.b, r.c, r.d};
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
@@ -257,7 +258,7 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
                             sa[0] += 1.0; sa[1] += du; sa[2] += dv; sa[3] += dw;
                             sa[4] += 0.5 * (du * du + dv * dv + dw * dw);
                             bool f2 = false;
-                            const int hb = flight_bin<T>(c, lc, xs[m], us[m], &f2);
+                            const int hb = flight_bin<T>(ck, lc, xs[m], us[m], &f2);
                             if (hb >= 0) atomicSub(&dh[hb], 1);
                         } else {
                             keep |= 1 << m;
@@ -290,20 +291,20 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
         if (nnew > 0) {
             const double *Wc = cl.wt + (int64_t)g * 5;
             for (int q = threadIdx.x; q < nnew; q += blockDim.x) {
-                U4 a = draw(c, step, (uint32_t)lc, (uint32_t)q, TAG_RVEL, 0);
-                U4 bb = draw(c, step, (uint32_t)lc, (uint32_t)q, TAG_RVEL, 1);
+                U4 a = draw(ck, step, (uint32_t)lc, (uint32_t)q, TAG_RVEL, 0);
+                U4 bb = draw(ck, step, (uint32_t)lc, (uint32_t)q, TAG_RVEL, 1);
                 double uu[6] = {u01(a.b), u01(a.c), u01(a.d), u01(bb.a), u01(bb.b), u01(bb.c)};
                 T xi[3];
-                maxwell_t<T>(Wc[1], Wc[2], Wc[3], Wc[4], c.R, uu, xi);
+                maxwell_t<T>(Wc[1], Wc[2], Wc[3], Wc[4], ck.R, uu, xi);
                 T px;
                 if constexpr (std::is_same<T, double>::value) {
-                    px = c.x_lo + ((double)lc + u01(a.a)) * c.dx;
+                    px = ck.x_lo + ((double)lc + u01(a.a)) * ck.dx;
                 } else {
                     px = (float)u01(a.a);
                     if (px >= 1.0f) px = 0.99999994f;
                 }
                 T pu = xi[0], pv = xi[1], pw = xi[2];
-                const int hb = flight_bin<T>(c, lc, px, pu, &far);
+                const int hb = flight_bin<T>(ck, lc, px, pu, &far);
                 if (hb >= 0) atomicAdd(&dh[hb], 1);
                 int64_t d = ob + nsurv + q;
                 if (d < cap) { stg.x[d] = px; stg.u[d] = pu; stg.v[d] = pv; stg.w[d] = pw; }
@@ -672,7 +673,7 @@ __device__ __forceinline__ void big_pred(const int *hcnt, const uint16_t (*hlst)
 }
 
 template <typename T>
-__device__ __forceinline__ void big_pair(const DCase &c, uint32_t step, int lc, uint32_t q, int32_t N,
+__device__ __forceinline__ void big_pair(const CaseK &c, uint32_t step, int lc, uint32_t q, int32_t N,
                                          uint32_t &i, uint32_t &j, double &u2, double &u3, double &u4)
 {
     const U4 ra = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 0);
@@ -724,6 +725,7 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
         const int g = cl.big_list[e];
         const int k = cl.cell_case[g];
         const DCase &c = cases[k];
+        const CaseK ck(c);
         const int lc = g - c.cell_base;
         const int32_t N = cl.n_int[g];
         const int64_t M = cl.d_cand[g];
@@ -754,7 +756,7 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
             T ui = 0, vi = 0, wi = 0, uj = 0, vj = 0, wj = 0;
             int si = 0, sj = 0;
             if (act) {
-                big_pair<T>(c, step, lc, (uint32_t)q, N, i, j, u2, u3, u4);
+                big_pair<T>(ck, step, lc, (uint32_t)q, N, i, j, u2, u3, u4);
                 const P4<T> a = P[i], bq = P[j];
                 ui = a.u; vi = a.v; wi = a.w;
                 uj = bq.u; vj = bq.v; wj = bq.w;
@@ -775,7 +777,7 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
                     for (int l = 0; l < nq; ++l) {
                         uint32_t a, bq;
                         double v2, v3, v4;
-                        big_pair<T>(c, step, lc, (uint32_t)(q0 + l), N, a, bq, v2, v3, v4);
+                        big_pair<T>(ck, step, lc, (uint32_t)(q0 + l), N, a, bq, v2, v3, v4);
                         P4<T> ra = P[a], rb = P[bq];
                         if (collide_vals<T>(ra.u, ra.v, ra.w, rb.u, rb.v, rb.w, cm, aexp, v2, v3, v4, seen)) {
                             ++acc;
@@ -828,7 +830,7 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
             if (r.u != u0) {
                 bool f0 = false;
                 const T x = px[i];
-                const int a0 = flight_bin<T>(c, lc, x, u0, &f0), a1 = flight_bin<T>(c, lc, x, r.u, &far);
+                const int a0 = flight_bin<T>(ck, lc, x, u0, &f0), a1 = flight_bin<T>(ck, lc, x, r.u, &far);
                 if (a0 != a1) {
                     if (a0 >= 0) atomicSub(&hd[a0], 1);
                     if (a1 >= 0) atomicAdd(&hd[a1], 1);
@@ -1170,7 +1172,10 @@ __device__ __forceinline__ void add_phi(double (&a)[5], double u, double v, doub
 }
 
 
-template <typename T, int MAXW>
+// items per thread and chunk of one-wave scatter blocks (small cells)
+constexpr int SCAT_IT1 = 4;
+
+template <typename T, int MAXW, int IT>
 __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
                                                  Soa<T> stg, Soa<T> dst, const int64_t *__restrict__ off_new,
                                                  int G, int64_t cap, int32_t *err, int64_t *d_nout)
@@ -1187,13 +1192,15 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
     // chunk behind a single barrier.  Two register sets alternate: the next
     // chunk is loaded into one while the other is placed, with no copy between
     // them (a copy would wait for the loads just issued).
-    // MAXW: the most waves a block has (blockDim <= 64 MAXW); a one-wave block
-    // keeps its LDS small so that more blocks fit on a CU
-    constexpr int IT = 4;
-    __shared__ int binbase[2][NBIN];     // by chunk parity
+    // MAXW: the most waves a block has (blockDim <= 64 MAXW).  A one-wave block
+    // keeps the bin bases in registers (lane b: bin b) and needs no barrier
+    // inside the chunk loop; blocks of several waves combine their counts in
+    // LDS.  IT: items per thread and chunk.
+    constexpr bool ONE = MAXW == 1;
+    __shared__ int binbase[ONE ? 1 : 2][NBIN];     // by chunk parity
     __shared__ int bin0[NBIN];
     __shared__ int64_t offb[NBIN];
-    __shared__ int wcnt[2][MAXW][NBIN];  // by chunk parity
+    __shared__ int wcnt[ONE ? 1 : 2][MAXW][NBIN];  // by chunk parity
     __shared__ double red[NMB * 5 * MAXW];
     __shared__ int hn[NBIN * NBIN];
     __shared__ int nout;
@@ -1205,11 +1212,25 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
     const int k = cl.cell_case[g];
     const DCase &c = cases[k];
     const int lc = g - c.cell_base;
-    for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
-        binbase[0][t] = cl.hist[(int64_t)g * NBIN + t];
-        bin0[t] = binbase[0][t];
-        const int d = g + t - KWIN;
-        offb[t] = (d >= 0 && d < G) ? off_new[d] : 0;
+    const CaseK fk(c);
+    // lane b of a one-wave block: running base of bin b, its first value, and
+    // the bin's destination start relative to lo (set once lo is known)
+    int bbr = 0, bb0r = 0, obr = 0;
+    int64_t offr = 0;
+    if constexpr (ONE) {
+        if (lane < NBIN) {
+            bbr = cl.hist[(int64_t)g * NBIN + lane];
+            bb0r = bbr;
+            const int d = g + lane - KWIN;
+            offr = (d >= 0 && d < G) ? off_new[d] : 0;
+        }
+    } else {
+        for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
+            binbase[0][t] = cl.hist[(int64_t)g * NBIN + t];
+            bin0[t] = binbase[0][t];
+            const int d = g + t - KWIN;
+            offb[t] = (d >= 0 && d < G) ? off_new[d] : 0;
+        }
     }
     __syncthreads();
     int64_t b;
@@ -1219,12 +1240,27 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
     const T *__restrict__ gx = sg.x + b, *__restrict__ gu = sg.u + b;
     const T *__restrict__ gv = sg.v + b, *__restrict__ gw = sg.w + b;
     const int64_t lo = off_new[max(g - KWIN, 0)];     // no destination of this cell starts lower
+    // element offsets from the uniform bases are 32-bit byte offsets: a block
+    // whose source cell or destination window holds more elements than that
+    // addresses reports a capacity error instead
+    constexpr int64_t LIM = ((int64_t)1 << 32) / (int64_t)sizeof(T);
+    if ((int64_t)cl.n_int[g] >= LIM || off_new[min(g + KWIN + 1, G)] - lo >= LIM) {
+        if (threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
+        return;
+    }
+    // destination index relative to lo below which stores stay inside the capacity
+    const int64_t dlim = min(cap - lo, (int64_t)INT32_MAX);
+    if constexpr (ONE) obr = (int)(offr - lo);
     T *__restrict__ ox = dst.x + lo, *__restrict__ ou = dst.u + lo;
     T *__restrict__ ov = dst.v + lo, *__restrict__ ow = dst.w + lo;
     // moment sums of the particles moving |d| <= MB cells, per destination
-    double mb[NMB * 5];
+    // (the counts as integers: exact, and half the registers of a double)
+    double mb[NMB * 4];
+    int mc[NMB];
 #pragma unroll
-    for (int i = 0; i < NMB * 5; ++i) mb[i] = 0.0;
+    for (int i = 0; i < NMB * 4; ++i) mb[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NMB; ++i) mc[i] = 0;
     bool far = false;
     const int CH = IT * (int)blockDim.x;
     const int wofs = w * IT * WAVE + lane;
@@ -1250,7 +1286,7 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
         for (int j = 0; j < IT; ++j) {
             key[j] = -1;
             if (i0 + wofs + j * WAVE < n) {
-                const int dest = Flight<T>::go(c, lc, X[j], U[j]);
+                const int dest = Flight<T>::go(fk, lc, X[j], U[j]);
                 if (dest >= 0) {
                     const int d = dest - lc;
                     if (d >= -KWIN && d <= KWIN) key[j] = d + KWIN;
@@ -1262,7 +1298,7 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
             // next step's destination of the particle from its new place
             if (key[j] >= 0) {
                 bool farp = false;
-                const int hb = flight_bin<T>(c, lc + key[j] - KWIN, X[j], U[j], &farp);
+                const int hb = flight_bin<T>(fk, lc + key[j] - KWIN, X[j], U[j], &farp);
                 if (hb >= 0) atomicAdd(&hn[key[j] * NBIN + hb], 1);
                 if (farp) cl.fix_nx[g + key[j] - KWIN] = 1;
             }
@@ -1280,8 +1316,10 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
             const uint64_t m0 = __ballot(kk == KWIN - 1);
             const uint64_t m1 = __ballot(kk == KWIN);
             const uint64_t m2 = __ballot(kk == KWIN + 1);
-            rk[j] = kk == KWIN ? cn1 + lane_rank_lt(m1)
-                               : (kk == KWIN - 1 ? cn0 + lane_rank_lt(m0) : cn2 + lane_rank_lt(m2));
+            // the three ranks with the masks as scalar operands, then one select
+            // (selecting the masks first would copy them into vector registers)
+            const int r0 = cn0 + lane_rank_lt(m0), r1 = cn1 + lane_rank_lt(m1), r2 = cn2 + lane_rank_lt(m2);
+            rk[j] = kk == KWIN ? r1 : (kk == KWIN - 1 ? r0 : r2);
             cn0 += __popcll(m0);
             cn1 += __popcll(m1);
             cn2 += __popcll(m2);
@@ -1297,18 +1335,32 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
                 rem &= ~mm;
             }
         }
-        if (lane < NBIN) wcnt[cb][w][lane] = lane == KWIN ? cn1 : (lane == KWIN - 1 ? cn0 : (lane == KWIN + 1 ? cn2 : wc));
-        // the only barrier of the chunk: counts and bases are double-buffered
-        lds_barrier();
+        const int cntl = lane == KWIN ? cn1 : (lane == KWIN - 1 ? cn0 : (lane == KWIN + 1 ? cn2 : wc));
+        // this wave's first destination index of each bin, relative to lo, in
+        // lane b for bin b: the bin's running base plus the earlier waves' counts
+        int wb = 0;
+        if constexpr (ONE) {
+            wb = obr + bbr;
+            if (lane < NBIN) bbr += cntl;
+        } else {
+            if (lane < NBIN) wcnt[cb][w][lane] = cntl;
+            // the only barrier of the chunk: counts and bases are double-buffered
+            lds_barrier();
+            if (lane < NBIN) {
+                int r = binbase[cb][lane];
+                for (int w2 = 0; w2 < w; ++w2) r += wcnt[cb][w2][lane];
+                wb = (int)(offb[lane] - lo) + r;
+            }
+        }
+        int di[IT];
+#pragma unroll
+        for (int j = 0; j < IT; ++j) di[j] = __shfl(wb, max(key[j], 0), WAVE) + rk[j];
 #pragma unroll
         for (int j = 0; j < IT; ++j) {
             if (key[j] < 0) continue;
-            int r = binbase[cb][key[j]] + rk[j];
-            for (int w2 = 0; w2 < w; ++w2) r += wcnt[cb][w2][key[j]];
-            const int64_t pos = offb[key[j]] + r;
-            if (pos < cap) {
+            if (di[j] < dlim) {
                 // 32-bit byte offset from the block-uniform destination base
-                const uint32_t bo = (uint32_t)(pos - lo) * (uint32_t)sizeof(T);
+                const uint32_t bo = (uint32_t)di[j] * (uint32_t)sizeof(T);
                 *(T *)((char *)ox + bo) = X[j];
                 *(T *)((char *)ou + bo) = U[j];
                 *(T *)((char *)ov + bo) = V[j];
@@ -1321,19 +1373,21 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
 #pragma unroll
                 for (int m = 0; m < NMB; ++m)
                     if (dd + MB == m) {
-                        mb[m * 5 + 0] += 1.0; mb[m * 5 + 1] += du; mb[m * 5 + 2] += dv; mb[m * 5 + 3] += dw;
-                        mb[m * 5 + 4] += e2;
+                        mc[m] += 1; mb[m * 4 + 0] += du; mb[m * 4 + 1] += dv; mb[m * 4 + 2] += dw;
+                        mb[m * 4 + 3] += e2;
                     }
             } else {
                 far = true;
             }
         }
-        for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
-            int s = 0;
-            for (int w2 = 0; w2 < nw; ++w2) s += wcnt[cb][w2][t];
-            binbase[cb ^ 1][t] = binbase[cb][t] + s;
+        if constexpr (!ONE) {
+            for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
+                int s = 0;
+                for (int w2 = 0; w2 < nw; ++w2) s += wcnt[cb][w2][t];
+                binbase[cb ^ 1][t] = binbase[cb][t] + s;
+            }
+            cb ^= 1;
         }
-        cb ^= 1;
     };
 
     if (n > 0) {
@@ -1348,11 +1402,22 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
             place(xb, ub, vb, wb, i0 + CH);
         }
     }
-    block_sum<NMB * 5>(mb, red);
+    double ms[NMB * 5];
+#pragma unroll
+    for (int m = 0; m < NMB; ++m) {
+        ms[m * 5] = (double)mc[m];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ms[m * 5 + 1 + q] = mb[m * 4 + q];
+    }
+    const double mnear_q = block_sum_to_thread<NMB * 5>(ms, red);
     const bool any_far = __syncthreads_or(far);
+    // destinations (bins) that received particles, one bit each
+    uint64_t rows;
+    if constexpr (ONE) rows = __ballot(lane < NBIN && bbr != bb0r);
+    else rows = __ballot(lane < NBIN && binbase[cb][lane] != bin0[lane]);
     // rows of the predicted histogram: only new cells that received particles
-    for (int r = 0; r < NBIN; ++r) {
-        if (binbase[cb][r] == bin0[r]) continue;
+    for (uint64_t rm = rows; rm; rm &= rm - 1) {
+        const int r = __ffsll((unsigned long long)rm) - 1;
         for (int t = threadIdx.x; t < NBIN; t += blockDim.x) {
             const int v0 = hn[r * NBIN + t];
             if (v0) atomicAdd(&cl.hist_nx[(int64_t)(g + r - KWIN) * NBIN + t], v0);
@@ -1360,33 +1425,21 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
     }
     if (threadIdx.x == 0 && nout) atomicAdd((unsigned long long *)&d_nout[k], (unsigned long long)nout);
     // near sums of this source cell: slot m is destination g + m - MB
-    if (threadIdx.x < NMB * 5) {
-        double val = 0.0;
-#pragma unroll
-        for (int q = 0; q < NMB * 5; ++q)
-            if ((int)threadIdx.x == q) val = mb[q];
-        cl.mnear[(int64_t)g * (NMB * 5) + threadIdx.x] = val;
-    }
+    if (threadIdx.x < NMB * 5) cl.mnear[(int64_t)g * (NMB * 5) + threadIdx.x] = mnear_q;
     if (any_far) {
         // a second pass per farther destination that received particles; the
         // sums go to the destination's row, slot KWIN - dd
         for (int bin = 0; bin < NBIN; ++bin) {
             const int dd = bin - KWIN;
-            if ((dd >= -MB && dd <= MB) || binbase[cb][bin] == bin0[bin]) continue;
+            if ((dd >= -MB && dd <= MB) || !((rows >> bin) & 1)) continue;
             double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
                 T x = gx[i], u = gu[i];
                 const int dest = Flight<T>::go(c, lc, x, u);
                 if (dest >= 0 && dest - lc == dd) add_phi(a, u, gv[i], gw[i]);
             }
-            block_sum<5>(a, red);
-            if (threadIdx.x < 5) {
-                double val = 0.0;
-#pragma unroll
-                for (int q = 0; q < 5; ++q)
-                    if ((int)threadIdx.x == q) val = a[q];
-                cl.mpart[((int64_t)(g + dd) * NBIN + (KWIN - dd)) * 5 + threadIdx.x] = val;
-            }
+            const double aq = block_sum_to_thread<5>(a, red);
+            if (threadIdx.x < 5) cl.mpart[((int64_t)(g + dd) * NBIN + (KWIN - dd)) * 5 + threadIdx.x] = aq;
             if (threadIdx.x == 0) cl.far_in[g + dd] = 1;
         }
     }
@@ -1766,10 +1819,10 @@ static void step_impl(duwp_ctx *ctx)
     {
         Mark m(ctx, "scatter");
         if (bc == WAVE)
-            hipLaunchKernelGGL((k_scatter<T, 1>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg, dst,
-                               ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout);
+            hipLaunchKernelGGL((k_scatter<T, 1, SCAT_IT1>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
+                               dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout);
         else
-            hipLaunchKernelGGL((k_scatter<T, 8>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg, dst,
+            hipLaunchKernelGGL((k_scatter<T, 8, 4>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg, dst,
                                ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout);
     }
     {

@@ -114,7 +114,8 @@ __device__ __noinline__ FlightD bc_cell_abs_slow(const DCase &c, double x, doubl
     return FlightD{x, u, -1};
 }
 
-__device__ __forceinline__ int bc_cell_abs(const DCase &c, double &x, double &u)
+template <typename K>
+__device__ __forceinline__ int bc_cell_abs(const K &c, double &x, double &u)
 {
     if (x >= c.x_lo && x <= c.x_hi) {
         const double f = floor((x - c.x_lo) / c.dx);
@@ -122,7 +123,7 @@ __device__ __forceinline__ int bc_cell_abs(const DCase &c, double &x, double &u)
         if (ci > c.ncells - 1) ci = c.ncells - 1;
         return ci;
     }
-    const FlightD r = bc_cell_abs_slow(c, x, u);
+    const FlightD r = bc_cell_abs_slow(case_of(c), x, u);
     x = r.x;
     u = r.u;
     return r.dest;
@@ -151,14 +152,15 @@ __device__ __noinline__ FlightF bc_cell_rel_slow(const DCase &c, int I, float f,
     return FlightF{f, u, -1};
 }
 
-__device__ __forceinline__ int bc_cell_rel(const DCase &c, int I, float f, float &u, float &s)
+template <typename K>
+__device__ __forceinline__ int bc_cell_rel(const K &c, int I, float f, float &u, float &s)
 {
     if (f >= 1.0f) { f -= 1.0f; I += 1; }
     if (I >= 0 && I < c.ncells) {
         s = f;
         return I;
     }
-    const FlightF r = bc_cell_rel_slow(c, I, f, u);
+    const FlightF r = bc_cell_rel_slow(case_of(c), I, f, u);
     s = r.s;
     u = r.u;
     return r.dest;
@@ -170,7 +172,8 @@ struct Flight;
 template <>
 struct Flight<double> {
     // stream a particle of local cell lc; x is absolute
-    __device__ static int go(const DCase &c, int /*lc*/, double &x, double &u)
+    template <typename K>
+    __device__ static int go(const K &c, int /*lc*/, double &x, double &u)
     {
         x = x + u * c.dt;
         return bc_cell_abs(c, x, u);
@@ -180,7 +183,8 @@ struct Flight<double> {
 template <>
 struct Flight<float> {
     // stream a particle of local cell lc; x is the position inside the cell, in cells
-    __device__ static int go(const DCase &c, int lc, float &s, float &u)
+    template <typename K>
+    __device__ static int go(const K &c, int lc, float &s, float &u)
     {
         const float X = s + u * c.dtdx_f;
         if (!(fabsf(X) < 1.0e9f)) return -1;

@@ -16,7 +16,7 @@ from oracle import oracle as O
 from paper_2305_12071_amd import duwp
 from paper_2305_12071_amd import inputs as I
 
-from _parity import compare_diag, compare_states
+from _parity import assert_close, compare_diag, compare_states
 
 pytestmark = pytest.mark.gpu
 
@@ -32,10 +32,12 @@ def _built():
     duwp.lib()
 
 
-def test_batched_generator_cases_match_oracles():
+@pytest.mark.parametrize("bc", [0, 64])
+def test_batched_generator_cases_match_oracles(bc):
+    """bc 64: the one-wave blocks of the batched benchmark's launch configuration."""
     cases = I.batched_cases(32, ppc_scale=0.2)
-    _say("batched 32 cases", sum(c.ncells for c in cases), "cells")
-    g = duwp.Sim(cases, seed=1, precision=duwp.FP64, use_graph=True)
+    _say("batched 32 cases", sum(c.ncells for c in cases), "cells, block size", bc)
+    g = duwp.Sim(cases, seed=1, precision=duwp.FP64, use_graph=True, block_cells=bc)
     ors = [O.Oracle(c, seed=1, case_id=k) for k, c in enumerate(cases)]
     for s in range(3):
         g.step(1)
@@ -46,6 +48,29 @@ def test_batched_generator_cases_match_oracles():
         compare_states(g.get_state(k), o.get_state(), rtol=1e-11, label=cases[k].name,
                        psi_t=o.cells()["psi_t"])
     g.close()
+
+
+def test_batched_mixed_block_size_changes_no_particle():
+    """The mixed path at the batched benchmark's block size (64) and at 256: the same
+    cell structure and particles after three steps.  The block size only changes
+    the order of the FP64 cell sums; an FP32 value sampled from a cell state that
+    differs in its last FP64 bit can round the other way (rarely), so particles
+    are compared to FP32 rounding and the cell state to FP64 rounding."""
+    cases = I.batched_cases(32, ppc_scale=0.2)
+    out = []
+    for bc in (64, 256):
+        g = duwp.Sim(cases, seed=4, precision=duwp.MIXED, use_graph=True, block_cells=bc)
+        g.step(3)
+        out.append([g.get_state(k) for k in range(len(cases))])
+        g.close()
+    for k, (a, b) in enumerate(zip(*out)):
+        assert np.array_equal(a["off"], b["off"]), cases[k].name
+        speed = np.sqrt(b["u"] ** 2 + b["v"] ** 2 + b["w"] ** 2) + 1e-30
+        assert_close(a["x"], b["x"], 2.0 ** -22, f"{cases[k].name}:x", scale=1.0)
+        for f in ("u", "v", "w"):
+            assert_close(a[f], b[f], 2.0 ** -22, f"{cases[k].name}:{f}", scale=speed)
+        sc = np.abs(b["psi_w"]).max(axis=0) + 1e-300
+        assert np.all(np.abs(a["psi_w"] - b["psi_w"]) <= 1e-12 * sc), cases[k].name
 
 
 def test_mach8_full_size_fp64_step_matches_oracle():

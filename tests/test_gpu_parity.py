@@ -106,6 +106,25 @@ def test_step_from_identical_developed_state(name):
     g.close()
 
 
+@pytest.mark.parametrize("bc", [64, 128, 512])
+def test_block_sizes_match_oracle(bc):
+    """The per-cell kernels at other block sizes (64: one-wave blocks, the scatter's
+    register-only variant) from a developed state, against the oracle."""
+    for name in ("mach3", "sod_kn1e-4", "box_ragged", "sod_kn1e-5_muscl"):
+        c = CASES[name]
+        _say("case", name, "block size", bc)
+        o = O.Oracle(c, seed=5, case_id=0)
+        o.step(10)
+        g = duwp.Sim(c, seed=5, precision=duwp.FP64, block_cells=bc)
+        g.set_state(o.get_state())
+        for k in range(2):
+            g.step(1)
+            o.step(1)
+            compare_diag(g.diag(), o.diag(), f"{name}:{bc}:{k}")
+            compare_states(g.get_state(), o.get_state(), label=f"{name}:{bc}:{k}", psi_t=o.cells()["psi_t"])
+        g.close()
+
+
 @pytest.mark.parametrize("name", ["mach3", "sod_kn1e-4", "box_p97"])
 def test_twenty_steps_from_initial_state(name):
     c = CASES[name]
