@@ -121,7 +121,7 @@ def roofline_of(sim, profile_steps, workload, block_cells):
     alg_bytes = BYTES_PER_PARTICLE[dom](4) * prof_ps
     achieved = alg_bytes / (kms[dom] * 1e-3) / 1e9
     # the scatter's instance: one-wave blocks get the small-LDS variant
-    scat = "k_scatter<float, 1, 4>" if block_cells == 64 else "k_scatter<float, 8, 4>"
+    scat = "k_scatter<float, 1, 2>" if block_cells == 64 else "k_scatter<float, 8, 4>"
     kname = {"scatter": scat, "absorb_resample": "k_absorb_resample<float>"}.get(dom)
     tr = counted_traffic(kname, workload) if kname else None
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

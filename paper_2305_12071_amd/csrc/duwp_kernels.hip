@@ -1172,11 +1172,13 @@ __device__ __forceinline__ void add_phi(double (&a)[5], double u, double v, doub
 }
 
 
-// items per thread and chunk of one-wave scatter blocks (small cells)
-constexpr int SCAT_IT1 = 4;
+// Items per thread and chunk, and the waves per SIMD the register budget is cut
+// for (FP32 particles): one-wave blocks (small cells) and blocks of several waves.
+constexpr int SCAT_IT1 = 2, SCAT_W1 = 5;
+constexpr int SCAT_ITN = 4, SCAT_WN = 1;
 
 template <typename T, int MAXW, int IT>
-__global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
+__global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1 : SCAT_WN)) k_scatter(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
                                                  Soa<T> stg, Soa<T> dst, const int64_t *__restrict__ off_new,
                                                  int G, int64_t cap, int32_t *err, int64_t *d_nout)
 {
@@ -1202,11 +1204,12 @@ __global__ void __launch_bounds__(512) k_scatter(const DCase *__restrict__ cases
     __shared__ int64_t offb[NBIN];
     __shared__ int wcnt[ONE ? 1 : 2][MAXW][NBIN];  // by chunk parity
     __shared__ double red[NMB * 5 * MAXW];
-    __shared__ int hn[NBIN * NBIN];
+    __shared__ __attribute__((aligned(16))) int hn[(NBIN * NBIN + 3) / 4 * 4];
     __shared__ int nout;
     if ((int)blockIdx.x >= G) return;
     const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int t = threadIdx.x; t < NBIN * NBIN; t += blockDim.x) hn[t] = 0;
+    for (int t = threadIdx.x; t < (NBIN * NBIN + 3) / 4; t += blockDim.x)
+        reinterpret_cast<int4 *>(hn)[t] = int4{0, 0, 0, 0};
     if (threadIdx.x == 0) nout = 0;
     const int g = cl.order[blockIdx.x];
     const int k = cl.cell_case[g];
@@ -1822,7 +1825,7 @@ static void step_impl(duwp_ctx *ctx)
             hipLaunchKernelGGL((k_scatter<T, 1, SCAT_IT1>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
                                dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout);
         else
-            hipLaunchKernelGGL((k_scatter<T, 8, 4>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg, dst,
+            hipLaunchKernelGGL((k_scatter<T, 8, SCAT_ITN>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg, dst,
                                ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout);
     }
     {
