@@ -104,9 +104,9 @@ duwp_status alloc_all(duwp_ctx *ctx)
 {
     const int G = ctx->G;
     const size_t es = ctx->precision == DUWP_MIXED ? sizeof(float) : sizeof(double);
-    for (int p = 0; p < 2; ++p)
-        for (int a = 0; a < 4; ++a) TRY(dalloc(ctx, &ctx->A[p][a], es * (size_t)ctx->cap));
-    for (int a = 0; a < 4; ++a) TRY(dalloc(ctx, &ctx->S[a], es * (size_t)ctx->cap));
+    // particles as (x,u,v,w) records: one vector access and one cache line each
+    for (int p = 0; p < 2; ++p) TRY(dalloc(ctx, &ctx->A[p], 4 * es * (size_t)ctx->cap));
+    TRY(dalloc(ctx, &ctx->S, 4 * es * (size_t)ctx->cap));
     for (int a = 0; a < 4; ++a) TRY(dalloc(ctx, &ctx->J[a], es * (size_t)ctx->inj_total));
     TRY(dalloc(ctx, &ctx->j_dest, 4 * (size_t)ctx->inj_total));
     TRY(dalloc(ctx, &ctx->j_rank, 4 * (size_t)ctx->inj_total));
@@ -142,8 +142,6 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &c.ncand_w, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.big_list, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.nbig, 4));
-    TRY(dalloc(ctx, &c.big_base, 8 * (size_t)G));
-    TRY(dalloc(ctx, &ctx->pk, 4 * es * (size_t)ctx->cap));
     TRY(dalloc(ctx, &ctx->diag, 8 * 5 * (size_t)G));
     ctx->items_cap = std::max<int64_t>(1 << 20, 2 * (int64_t)G);
     TRY(dalloc(ctx, &ctx->item_cell, 4 * (size_t)ctx->items_cap));
@@ -277,16 +275,20 @@ duwp_status host_offsets(duwp_ctx *ctx, std::vector<int64_t> &off)
     return DUWP_OK;
 }
 
+// records [b, b+n) of the canonical array, as four host arrays x, u, v, w
 template <typename T>
 duwp_status download_particles(duwp_ctx *ctx, int64_t b, int64_t n, std::vector<T> (&out)[4])
 {
     const int p = ctx->step & 1;
+    std::vector<T> rec(4 * (size_t)n);
+    if (n)
+        HIP_OK(hipMemcpyAsync(rec.data(), (T *)ctx->A[p] + 4 * b, 4 * sizeof(T) * n, hipMemcpyDeviceToHost,
+                              ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
     for (int a = 0; a < 4; ++a) {
         out[a].resize((size_t)n);
-        if (n) HIP_OK(hipMemcpyAsync(out[a].data(), (T *)ctx->A[p][a] + b, sizeof(T) * n, hipMemcpyDeviceToHost,
-                                     ctx->stream));
+        for (int64_t q = 0; q < n; ++q) out[a][q] = rec[4 * q + a];
     }
-    HIP_OK(hipStreamSynchronize(ctx->stream));
     return DUWP_OK;
 }
 
@@ -599,20 +601,22 @@ duwp_status duwp_set_state(duwp_ctx *ctx, int32_t case_id, const duwp_state *st)
     if (total > ctx->cap) return DUWP_ECAPACITY;
     // rebuild the whole canonical array on the host: earlier cases, this case, later cases
     const bool mixed = ctx->precision == DUWP_MIXED;
-    const size_t es = mixed ? 4 : 8;
-    std::vector<char> hh[4];
-    for (int a = 0; a < 4; ++a) {
-        hh[a].resize(es * (size_t)total);
-        std::vector<char> old(es * (size_t)off[G]);
-        if (off[G]) HIP_OK(hipMemcpyAsync(old.data(), ctx->A[p][a], old.size(), hipMemcpyDeviceToHost, ctx->stream));
+    const size_t es = mixed ? 4 : 8, rs = 4 * es;   // element and record sizes
+    std::vector<char> hh(rs * (size_t)total);
+    {
+        std::vector<char> old(rs * (size_t)off[G]);
+        if (off[G]) HIP_OK(hipMemcpyAsync(old.data(), ctx->A[p], old.size(), hipMemcpyDeviceToHost, ctx->stream));
         HIP_OK(hipStreamSynchronize(ctx->stream));
-        std::memcpy(hh[a].data(), old.data(), es * (size_t)b);
-        std::memcpy(hh[a].data() + es * (size_t)(b + st->n_particles), old.data() + es * (size_t)(b + nold),
-                    es * (size_t)(off[G] - b - nold));
-        const double *srcv[4] = {st->x, st->u, st->v, st->w};
-        for (int i = 0; i < d.ncells; ++i)
-            for (int64_t q = st->off[i]; q < st->off[i + 1]; ++q) {
+        std::memcpy(hh.data(), old.data(), rs * (size_t)b);
+        std::memcpy(hh.data() + rs * (size_t)(b + st->n_particles), old.data() + rs * (size_t)(b + nold),
+                    rs * (size_t)(off[G] - b - nold));
+    }
+    const double *srcv[4] = {st->x, st->u, st->v, st->w};
+    for (int i = 0; i < d.ncells; ++i)
+        for (int64_t q = st->off[i]; q < st->off[i + 1]; ++q)
+            for (int a = 0; a < 4; ++a) {
                 double val = srcv[a][q];
+                char *slot = hh.data() + rs * (size_t)(b + q) + es * (size_t)a;
                 if (mixed) {
                     float f;
                     if (a == 0) {
@@ -623,14 +627,13 @@ duwp_status duwp_set_state(duwp_ctx *ctx, int32_t case_id, const duwp_state *st)
                     } else {
                         f = (float)val;
                     }
-                    std::memcpy(hh[a].data() + 4 * (size_t)(b + q), &f, 4);
+                    std::memcpy(slot, &f, 4);
                 } else {
-                    std::memcpy(hh[a].data() + 8 * (size_t)(b + q), &val, 8);
+                    std::memcpy(slot, &val, 8);
                 }
             }
-        if (total) HIP_OK(hipMemcpyAsync(ctx->A[p][a], hh[a].data(), hh[a].size(), hipMemcpyHostToDevice, ctx->stream));
-        HIP_OK(hipStreamSynchronize(ctx->stream));
-    }
+    if (total) HIP_OK(hipMemcpyAsync(ctx->A[p], hh.data(), hh.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
     std::vector<int64_t> noff((size_t)G + 1);
     const int64_t delta = st->n_particles - nold;
     for (int g = 0; g <= G; ++g) {
@@ -645,9 +648,7 @@ duwp_status duwp_set_state(duwp_ctx *ctx, int32_t case_id, const duwp_state *st)
     HIP_OK(hipMemcpyAsync(ctx->cl.cr_max + d.cell_base, st->cr_max, 8 * (size_t)d.ncells, hipMemcpyHostToDevice, s));
     // the step index is shared by all cases; the parity of the buffers follows it
     if ((st->step & 1u) != (ctx->step & 1u)) {
-        for (int a = 0; a < 4; ++a)
-            if (total)
-                HIP_OK(hipMemcpyAsync(ctx->A[p ^ 1][a], ctx->A[p][a], es * (size_t)total, hipMemcpyDeviceToDevice, s));
+        if (total) HIP_OK(hipMemcpyAsync(ctx->A[p ^ 1], ctx->A[p], rs * (size_t)total, hipMemcpyDeviceToDevice, s));
         HIP_OK(hipMemcpyAsync(ctx->off[p ^ 1], ctx->off[p], 8 * (size_t)(G + 1), hipMemcpyDeviceToDevice, s));
     }
     ctx->step = st->step;

@@ -40,8 +40,8 @@ struct duwp_ctx {
     int64_t avg_count = 0;
 
     duwp::DCase *d_cases = nullptr;
-    void *A[2][4] = {{nullptr}};   // canonical particle arrays, by step parity
-    void *S[4] = {nullptr};        // staging (intermediate) arrays
+    void *A[2] = {nullptr};        // canonical particle records (x,u,v,w), by step parity
+    void *S = nullptr;             // staging (intermediate) records
     void *J[4] = {nullptr};        // injected entrants
     int32_t *j_dest = nullptr, *j_rank = nullptr, *j_count = nullptr;
     void *K[4] = {nullptr};        // injection candidates
@@ -68,7 +68,6 @@ struct duwp_ctx {
     int64_t items_cap = 0;
     int coll_blocks = 0;
     int big_blocks = 0;            // grid of the block-per-cell collision kernel
-    void *pk = nullptr;            // packed (x,u,v,w) records of the cells that kernel works on
     double *diag = nullptr;        // [G*5] on-demand cell diagnostics
     int64_t *d_psteps = nullptr;   // particle-steps since init or the last reset
 

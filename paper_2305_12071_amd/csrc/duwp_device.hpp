@@ -69,7 +69,6 @@ struct Cells {
     int64_t *cbase;     // [G+1] first collision candidate of each cell in the step's candidate list
     int32_t *big_list;  // [G] cells that collide in the block kernel (unordered)
     int32_t *nbig;      // [1] their number (cleared at the end of each step)
-    int64_t *big_base;  // [G] start of each listed cell's packed (x,u,v,w) region
     uint64_t *cr_seen;  // [G] largest relative speed seen this step (bits of a non-negative double)
     int32_t *hist;      // [G*NBIN] destination histogram of this step, then scatter bases
     int32_t *hist_nx;   // [G*NBIN] histogram predicted for the next step
@@ -100,9 +99,12 @@ struct Inj {
     int32_t *cchunk;    // entrants per 256-slot candidate chunk (entrants compacted to the chunk front)
 };
 
+// One particle: position and velocity in one record (16 B with FP32 particles,
+// 32 B with FP64), so that a particle is one vector access and one cache line.
+// With FP32 particles x is the position inside the cell, in cells.
 template <typename T>
-struct Soa {
-    T *x, *u, *v, *w;
+struct alignas(4 * sizeof(T) > 16 ? 16 : 4 * sizeof(T)) P4 {
+    T x, u, v, w;
 };
 
 // ---------------------------------------------------------------------------

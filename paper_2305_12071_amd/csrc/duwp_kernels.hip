@@ -191,8 +191,7 @@ __device__ __forceinline__ int flight_bin(const K &c, int lc, T x, T u, bool *fa
 
 // Cell segment of the intermediate array: staging buffer or in place.
 template <typename T>
-__device__ __forceinline__ Soa<T> segment(const Cells &cl, int g, const Soa<T> &src, const Soa<T> &stg,
-                                          int64_t &base)
+__device__ __forceinline__ P4<T> *segment(const Cells &cl, int g, P4<T> *src, P4<T> *stg, int64_t &base)
 {
     base = cl.seg[g];
     return cl.seg_stg[g] ? stg : src;
@@ -204,8 +203,9 @@ __device__ __forceinline__ Soa<T> segment(const Cells &cl, int g, const Soa<T> &
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict__ cases, Cells cl,
-                                                          Soa<T> src, const int64_t *__restrict__ off,
-                                                          Soa<T> stg, const int64_t *__restrict__ sbase,
+                                                          const P4<T> *__restrict__ src,
+                                                          const int64_t *__restrict__ off, P4<T> *__restrict__ stg,
+                                                          const int64_t *__restrict__ sbase,
                                                           const uint32_t *__restrict__ d_step, int G,
                                                           int64_t cap, int32_t *err)
 {
@@ -252,7 +252,8 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
                         const int64_t kk = pbase + 4 * qd + m;
                         xs[m] = 0; us[m] = 0; vs[m] = 0; ws[m] = 0;
                         if (kk < b || kk >= e) continue;
-                        xs[m] = src.x[kk]; us[m] = src.u[kk]; vs[m] = src.v[kk]; ws[m] = src.w[kk];
+                        const P4<T> r = src[kk];
+                        xs[m] = r.x; us[m] = r.u; vs[m] = r.v; ws[m] = r.w;
                         if (u01(wd[m]) < P) {
                             const double du = us[m], dv = vs[m], dw = ws[m];
                             sa[0] += 1.0; sa[1] += du; sa[2] += dv; sa[3] += dw;
@@ -272,7 +273,7 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
                 for (int m = 0; m < 4; ++m) {
                     if (!((keep >> m) & 1)) continue;
                     const int64_t d = ob + written + pre++;
-                    if (d < cap) { stg.x[d] = xs[m]; stg.u[d] = us[m]; stg.v[d] = vs[m]; stg.w[d] = ws[m]; }
+                    if (d < cap) stg[d] = P4<T>{xs[m], us[m], vs[m], ws[m]};
                     else atomicOr(err, ERR_CAPACITY);
                 }
                 written += tot;
@@ -281,7 +282,7 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
         } else {
             for (int64_t kk = b + threadIdx.x; kk < e; kk += blockDim.x) {
                 int64_t d = ob + (kk - b);
-                if (d < cap) { stg.x[d] = src.x[kk]; stg.u[d] = src.u[kk]; stg.v[d] = src.v[kk]; stg.w[d] = src.w[kk]; }
+                if (d < cap) stg[d] = src[kk];
                 else atomicOr(err, ERR_CAPACITY);
             }
         }
@@ -307,7 +308,7 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
                 const int hb = flight_bin<T>(ck, lc, px, pu, &far);
                 if (hb >= 0) atomicAdd(&dh[hb], 1);
                 int64_t d = ob + nsurv + q;
-                if (d < cap) { stg.x[d] = px; stg.u[d] = pu; stg.v[d] = pv; stg.w[d] = pw; }
+                if (d < cap) stg[d] = P4<T>{px, pu, pv, pw};
                 else atomicOr(err, ERR_CAPACITY);
                 // moments of the particle as stored, so Psi_t is unchanged exactly
                 double du = pu, dv = pv, dw = pw;
@@ -420,8 +421,8 @@ __device__ __forceinline__ uint32_t coll_slot(int g, uint32_t i)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
-                                                 Soa<T> stg, const uint32_t *__restrict__ d_step, int G,
+__global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases, Cells cl, P4<T> *src,
+                                                 P4<T> *stg, const uint32_t *__restrict__ d_step, int G,
                                                  int64_t cap, int32_t *err, const int32_t *__restrict__ item_cell,
                                                  const int64_t *__restrict__ d_items)
 {
@@ -474,7 +475,7 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
             uint32_t i = 0, j = 0;
             double u2 = 0.0, u3 = 0.0, u4 = 0.0, cm = 1.0, aexp = 0.0;
             T xi = 0, ui = 0, vi = 0, wi = 0, xj = 0, uj = 0, vj = 0, wj = 0;
-            T *pu = nullptr, *pv = nullptr, *pw = nullptr;
+            P4<T> *pr = nullptr;
             int lc = 0, k = 0;
             if (act) {
                 const int32_t N = cl.n_int[g];
@@ -485,7 +486,7 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
                 if (sb + N > cap) {
                     act = false;   // capacity overflow, already reported
                 } else {
-                    const Soa<T> sg = cl.seg_stg[g] ? stg : src;
+                    P4<T> *sg = cl.seg_stg[g] ? stg : src;
                     cm = cl.cr_max[g];
                     aexp = 1.0 - 2.0 * c.ups;
                     const uint32_t q = (uint32_t)(Q - gstart);
@@ -497,10 +498,10 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
                     j = (uint32_t)mulhi64(r1, (uint64_t)(N - 1));
                     if (j >= i) j += 1;
                     u2 = u01(rb.a); u3 = u01(rb.b); u4 = u01(rb.c);
-                    const T *px = sg.x + sb;
-                    pu = sg.u + sb; pv = sg.v + sb; pw = sg.w + sb;
-                    xi = px[i]; ui = pu[i]; vi = pv[i]; wi = pw[i];
-                    xj = px[j]; uj = pu[j]; vj = pv[j]; wj = pw[j];
+                    pr = sg + sb;
+                    const P4<T> a = pr[i], bq = pr[j];
+                    xi = a.x; ui = a.u; vi = a.v; wi = a.w;
+                    xj = bq.x; uj = bq.u; vj = bq.v; wj = bq.w;
                 }
             }
             if (!act) g = -1;
@@ -543,8 +544,8 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
                     const T ui0 = ui, uj0 = uj;
                     if (collide_vals<T>(ui, vi, wi, uj, vj, wj, cm, aexp, u2, u3, u4, seen)) {
                         acc = 1;
-                        pu[i] = ui; pv[i] = vi; pw[i] = wi;
-                        pu[j] = uj; pv[j] = vj; pw[j] = wj;
+                        pr[i] = P4<T>{xi, ui, vi, wi};
+                        pr[j] = P4<T>{xj, uj, vj, wj};
                         // move the pair between destination bins of this step's histogram
                         const DCase &c = cases[k];
                         int32_t *hg = cl.hist + (int64_t)g * NBIN;
@@ -599,11 +600,11 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
 // the predecessors' LDS slots.  A particle drawn by more than BIG_LIST
 // candidates of one chunk (rare) sends that chunk through a serial path.
 //
-// The random particle reads dominate: two blocks share a compute unit, and the
+// The random particle reads dominate: the block works on the cell's records in
+// place (one cache line per access), two blocks share a compute unit, and the
 // rounds' barriers order LDS only, so that the stores of a round do not hold up
-// the next.  The histogram moves of the collisions telescope: each particle
-// moves once, from the bin of its velocity before the collide stage to the bin
-// of its final one, summed in LDS when the velocities are written back.
+// the next.  Histogram moves of accepted collisions are summed in LDS and added
+// once per cell.
 // ---------------------------------------------------------------------------
 constexpr int BIG_LIST = 4;
 
@@ -617,29 +618,6 @@ struct BigCfg {
     static constexpr int PER_CU = 2;
 };
 
-// (x, u, v, w) of one particle in one 16- or 32-byte record: a random access to
-// a particle touches one cache line instead of four
-template <typename T>
-struct alignas(4 * sizeof(T) > 16 ? 16 : 4 * sizeof(T)) P4 {
-    T x, u, v, w;
-};
-
-// start of each listed big cell's packed region: prefix of the cells' particle counts
-__global__ void __launch_bounds__(1024) k_big_bases(Cells cl)
-{
-    __shared__ int64_t lds[16];
-    const int nbig = *cl.nbig;
-    int64_t carry = 0;
-    for (int e0 = 0; e0 < nbig; e0 += blockDim.x) {
-        const int e = e0 + threadIdx.x;
-        const int64_t v = e < nbig ? (int64_t)cl.n_int[cl.big_list[e]] : 0;
-        int64_t tot;
-        const int64_t ex = block_exclusive_scan64(v, lds, &tot);
-        if (e < nbig) cl.big_base[e] = carry + ex;
-        carry += tot;
-        __syncthreads();
-    }
-}
 
 template <int HBITS>
 __device__ __forceinline__ int big_insert(uint32_t *hkey, int *hcnt, uint16_t (*hlst)[BIG_LIST], uint32_t p,
@@ -686,9 +664,27 @@ __device__ __forceinline__ void big_pair(const CaseK &c, uint32_t step, int lc, 
     u2 = u01(rb.a); u3 = u01(rb.b); u4 = u01(rb.c);
 }
 
+// move the pair between destination bins of this step's histogram (summed in hd)
+template <typename T>
+__device__ __forceinline__ void big_bins(const CaseK &c, int lc, T xi, T ui0, T ui, T xj, T uj0, T uj, int *hd,
+                                         bool &far)
+{
+    bool f0 = false;
+    const int a0 = flight_bin<T>(c, lc, xi, ui0, &f0), a1 = flight_bin<T>(c, lc, xi, ui, &far);
+    const int b0 = flight_bin<T>(c, lc, xj, uj0, &f0), b1 = flight_bin<T>(c, lc, xj, uj, &far);
+    if (a0 != a1) {
+        if (a0 >= 0) atomicSub(&hd[a0], 1);
+        if (a1 >= 0) atomicAdd(&hd[a1], 1);
+    }
+    if (b0 != b1) {
+        if (b0 >= 0) atomicSub(&hd[b0], 1);
+        if (b1 >= 0) atomicAdd(&hd[b1], 1);
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__restrict__ cases, Cells cl,
-                                                               Soa<T> src, Soa<T> stg, P4<T> *__restrict__ pk,
+                                                               P4<T> *src, P4<T> *stg,
                                                                const uint32_t *__restrict__ d_step, int64_t cap)
 {
     constexpr int B = BigCfg<T>::B;
@@ -730,16 +726,10 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
         const int32_t N = cl.n_int[g];
         const int64_t M = cl.d_cand[g];
         int64_t sb;
-        const Soa<T> sg = segment(cl, g, src, stg, sb);
-        const int64_t pb = cl.big_base[e];
-        if (sb + N > cap || pb + N > cap) continue;   // capacity overflow, already reported (block-uniform)
-        T *pu = sg.u + sb, *pv = sg.v + sb, *pw = sg.w + sb;
-        const T *px = sg.x + sb;
-        // the cell's velocities as one record per particle for the random pair
-        // accesses (the x slot is not used)
-        P4<T> *P = pk + pb;
-        for (int i = t; i < N; i += B) P[i] = P4<T>{T(0), pu[i], pv[i], pw[i]};
-        __threadfence_block();
+        P4<T> *sg = segment(cl, g, src, stg, sb);
+        if (sb + N > cap) continue;   // capacity overflow, already reported (block-uniform)
+        P4<T> *P = sg + sb;           // the cell's records
+        bool far = false;
         const double cm = cl.cr_max[g];
         const double aexp = 1.0 - 2.0 * c.ups;
         if (t < NBIN) hd[t] = 0;
@@ -753,13 +743,13 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
             const bool act = q < M;
             uint32_t i = 0, j = 0;
             double u2 = 0.0, u3 = 0.0, u4 = 0.0;
-            T ui = 0, vi = 0, wi = 0, uj = 0, vj = 0, wj = 0;
+            T xi = 0, ui = 0, vi = 0, wi = 0, xj = 0, uj = 0, vj = 0, wj = 0;
             int si = 0, sj = 0;
             if (act) {
                 big_pair<T>(ck, step, lc, (uint32_t)q, N, i, j, u2, u3, u4);
                 const P4<T> a = P[i], bq = P[j];
-                ui = a.u; vi = a.v; wi = a.w;
-                uj = bq.u; vj = bq.v; wj = bq.w;
+                xi = a.x; ui = a.u; vi = a.v; wi = a.w;
+                xj = bq.x; uj = bq.u; vj = bq.v; wj = bq.w;
                 si = big_insert<HB>(hkey, hcnt, hlst, i, t, &ovf[par]);
                 sj = big_insert<HB>(hkey, hcnt, hlst, j, t, &ovf[par]);
             }
@@ -779,10 +769,12 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
                         double v2, v3, v4;
                         big_pair<T>(ck, step, lc, (uint32_t)(q0 + l), N, a, bq, v2, v3, v4);
                         P4<T> ra = P[a], rb = P[bq];
+                        const T ua0 = ra.u, ub0 = rb.u;
                         if (collide_vals<T>(ra.u, ra.v, ra.w, rb.u, rb.v, rb.w, cm, aexp, v2, v3, v4, seen)) {
                             ++acc;
                             P[a] = ra;
                             P[bq] = rb;
+                            big_bins<T>(ck, lc, ra.x, ua0, ra.u, rb.x, ub0, rb.u, hd, far);
                         }
                     }
                 }
@@ -800,10 +792,12 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
                     if (ready) {
                         if (pi >= 0) { ui = fwd[oi][pi]; vi = fwd[oi + 1][pi]; wi = fwd[oi + 2][pi]; }
                         if (pj >= 0) { uj = fwd[oj][pj]; vj = fwd[oj + 1][pj]; wj = fwd[oj + 2][pj]; }
+                        const T ui0 = ui, uj0 = uj;
                         if (collide_vals<T>(ui, vi, wi, uj, vj, wj, cm, aexp, u2, u3, u4, seen)) {
                             ++acc;
-                            P[i] = P4<T>{T(0), ui, vi, wi};
-                            P[j] = P4<T>{T(0), uj, vj, wj};
+                            P[i] = P4<T>{xi, ui, vi, wi};
+                            P[j] = P4<T>{xj, uj, vj, wj};
+                            big_bins<T>(ck, lc, xi, ui0, ui, xj, uj0, uj, hd, far);
                         }
                         fwd[0][t] = ui; fwd[1][t] = vi; fwd[2][t] = wi;
                         fwd[3][t] = uj; fwd[4][t] = vj; fwd[5][t] = wj;
@@ -820,23 +814,6 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
             }
             __threadfence_block();
             __syncthreads();
-        }
-        // velocities back to the cell's segment; a particle whose x velocity
-        // changed moves between destination bins of this step's histogram
-        bool far = false;
-        for (int i = t; i < N; i += B) {
-            const P4<T> r = P[i];
-            const T u0 = pu[i];
-            if (r.u != u0) {
-                bool f0 = false;
-                const T x = px[i];
-                const int a0 = flight_bin<T>(ck, lc, x, u0, &f0), a1 = flight_bin<T>(ck, lc, x, r.u, &far);
-                if (a0 != a1) {
-                    if (a0 >= 0) atomicSub(&hd[a0], 1);
-                    if (a1 >= 0) atomicAdd(&hd[a1], 1);
-                }
-            }
-            pu[i] = r.u; pv[i] = r.v; pw[i] = r.w;
         }
         // per-cell results
         int a = wave_sum_i(acc);
@@ -1070,8 +1047,8 @@ __global__ void __launch_bounds__(256) k_inject_rank(const DCase *__restrict__ c
 // 6. Free flight of the intermediate particles: destination histogram per source cell
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(512) k_hist_build(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
-                                                     Soa<T> stg, const int64_t *__restrict__ off, int G,
+__global__ void __launch_bounds__(512) k_hist_build(const DCase *__restrict__ cases, Cells cl, P4<T> *src,
+                                                     P4<T> *stg, const int64_t *__restrict__ off, int G,
                                                      int64_t cap, int all)
 {
     // Recount of the destination histogram of a cell from its particles: every
@@ -1087,7 +1064,7 @@ __global__ void __launch_bounds__(512) k_hist_build(const DCase *__restrict__ ca
         for (int t = threadIdx.x; t < NBIN; t += blockDim.x) h[t] = 0;
         __syncthreads();
         int64_t b;
-        Soa<T> sg;
+        P4<T> *sg;
         int32_t n;
         if (all) {
             sg = src;
@@ -1104,7 +1081,10 @@ __global__ void __launch_bounds__(512) k_hist_build(const DCase *__restrict__ ca
             for (int j = 0; j < IT; ++j) {
                 const int i = i0 + j * blockDim.x + threadIdx.x;
                 x[j] = 0; u[j] = 0;
-                if (i < n) { x[j] = sg.x[b + i]; u[j] = sg.u[b + i]; }
+                if (i < n) {
+                    const P4<T> r = sg[b + i];
+                    x[j] = r.x; u[j] = r.u;
+                }
             }
 #pragma unroll
             for (int j = 0; j < IT; ++j) {
@@ -1178,8 +1158,8 @@ constexpr int SCAT_IT1 = 2, SCAT_W1 = 5;
 constexpr int SCAT_ITN = 4, SCAT_WN = 1;
 
 template <typename T, int MAXW, int IT>
-__global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1 : SCAT_WN)) k_scatter(const DCase *__restrict__ cases, Cells cl, Soa<T> src,
-                                                 Soa<T> stg, Soa<T> dst, const int64_t *__restrict__ off_new,
+__global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1 : SCAT_WN)) k_scatter(const DCase *__restrict__ cases, Cells cl, P4<T> *src,
+                                                 P4<T> *stg, P4<T> *dst, const int64_t *__restrict__ off_new,
                                                  int G, int64_t cap, int32_t *err, int64_t *d_nout)
 {
     // One block per cell (grid = G, visiting order cl.order).  Besides placing
@@ -1237,16 +1217,15 @@ __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1
     }
     __syncthreads();
     int64_t b;
-    const Soa<T> sg = segment(cl, g, src, stg, b);
+    P4<T> *sg = segment(cl, g, src, stg, b);
     const int32_t n = (int32_t)min((int64_t)cl.n_int[g], cap - b);
-    // cell-uniform base pointers: per-particle offsets are unsigned 32-bit
-    const T *__restrict__ gx = sg.x + b, *__restrict__ gu = sg.u + b;
-    const T *__restrict__ gv = sg.v + b, *__restrict__ gw = sg.w + b;
+    // cell-uniform base pointer: per-particle offsets are unsigned 32-bit
+    const P4<T> *__restrict__ gp = sg + b;
     const int64_t lo = off_new[max(g - KWIN, 0)];     // no destination of this cell starts lower
-    // element offsets from the uniform bases are 32-bit byte offsets: a block
-    // whose source cell or destination window holds more elements than that
+    // record offsets from the uniform bases are 32-bit byte offsets: a block
+    // whose source cell or destination window holds more records than that
     // addresses reports a capacity error instead
-    constexpr int64_t LIM = ((int64_t)1 << 32) / (int64_t)sizeof(T);
+    constexpr int64_t LIM = ((int64_t)1 << 32) / (int64_t)sizeof(P4<T>);
     if ((int64_t)cl.n_int[g] >= LIM || off_new[min(g + KWIN + 1, G)] - lo >= LIM) {
         if (threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
         return;
@@ -1254,8 +1233,7 @@ __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1
     // destination index relative to lo below which stores stay inside the capacity
     const int64_t dlim = min(cap - lo, (int64_t)INT32_MAX);
     if constexpr (ONE) obr = (int)(offr - lo);
-    T *__restrict__ ox = dst.x + lo, *__restrict__ ou = dst.u + lo;
-    T *__restrict__ ov = dst.v + lo, *__restrict__ ow = dst.w + lo;
+    P4<T> *__restrict__ op = dst + lo;
     // moment sums of the particles moving |d| <= MB cells, per destination
     // (the counts as integers: exact, and half the registers of a double)
     double mb[NMB * 4];
@@ -1275,11 +1253,9 @@ __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1
 #pragma unroll
         for (int j = 0; j < IT; ++j) {
             // 32-bit byte offset from a wave-uniform base
-            const uint32_t bo = (uint32_t)min(i0 + wofs + j * WAVE, n - 1) * (uint32_t)sizeof(T);
-            X[j] = *(const T *)((const char *)gx + bo);
-            U[j] = *(const T *)((const char *)gu + bo);
-            V[j] = *(const T *)((const char *)gv + bo);
-            W[j] = *(const T *)((const char *)gw + bo);
+            const uint32_t bo = (uint32_t)min(i0 + wofs + j * WAVE, n - 1) * (uint32_t)sizeof(P4<T>);
+            const P4<T> r = *(const P4<T> *)((const char *)gp + bo);
+            X[j] = r.x; U[j] = r.u; V[j] = r.v; W[j] = r.w;
         }
     };
     auto place = [&](T (&X)[IT], T (&U)[IT], T (&V)[IT], T (&W)[IT], int i0) {
@@ -1363,11 +1339,8 @@ __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1
             if (key[j] < 0) continue;
             if (di[j] < dlim) {
                 // 32-bit byte offset from the block-uniform destination base
-                const uint32_t bo = (uint32_t)di[j] * (uint32_t)sizeof(T);
-                *(T *)((char *)ox + bo) = X[j];
-                *(T *)((char *)ou + bo) = U[j];
-                *(T *)((char *)ov + bo) = V[j];
-                *(T *)((char *)ow + bo) = W[j];
+                const uint32_t bo = (uint32_t)di[j] * (uint32_t)sizeof(P4<T>);
+                *(P4<T> *)((char *)op + bo) = P4<T>{X[j], U[j], V[j], W[j]};
             }
             const int dd = key[j] - KWIN;
             if (dd >= -MB && dd <= MB) {
@@ -1437,9 +1410,10 @@ __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1
             if ((dd >= -MB && dd <= MB) || !((rows >> bin) & 1)) continue;
             double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                T x = gx[i], u = gu[i];
+                const P4<T> r = gp[i];
+                T x = r.x, u = r.u;
                 const int dest = Flight<T>::go(c, lc, x, u);
-                if (dest >= 0 && dest - lc == dd) add_phi(a, u, gv[i], gw[i]);
+                if (dest >= 0 && dest - lc == dd) add_phi(a, u, r.v, r.w);
             }
             const double aq = block_sum_to_thread<5>(a, red);
             if (threadIdx.x < 5) cl.mpart[((int64_t)(g + dd) * NBIN + (KWIN - dd)) * 5 + threadIdx.x] = aq;
@@ -1452,7 +1426,7 @@ __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1
 // their next-step destinations join the predicted histogram
 template <typename T>
 __global__ void __launch_bounds__(256) k_scatter_inj(const DCase *__restrict__ cases, Cells cl, Inj<T> inj,
-                                                     Soa<T> dst, int64_t cap)
+                                                     P4<T> *dst, int64_t cap)
 {
     const int k = blockIdx.y;
     const DCase &c = cases[k];
@@ -1466,7 +1440,7 @@ __global__ void __launch_bounds__(256) k_scatter_inj(const DCase *__restrict__ c
             const int d = inj.dest[sl];
             const int64_t pos = cl.inj_start[d] + inj.rank[sl];
             const T x = inj.x[sl], u = inj.u[sl];
-            if (pos < cap) { dst.x[pos] = x; dst.u[pos] = u; dst.v[pos] = inj.v[sl]; dst.w[pos] = inj.w[sl]; }
+            if (pos < cap) dst[pos] = P4<T>{x, u, inj.v[sl], inj.w[sl]};
             bool farp = false;
             const int hb = flight_bin<T>(c, d - c.cell_base, x, u, &farp);
             if (hb >= 0) key = d * NBIN + hb;
@@ -1508,7 +1482,7 @@ __global__ void __launch_bounds__(256) k_wave(const DCase *__restrict__ cases, C
 // One lane per destination cell; the entrants of a cell are summed by the whole wave.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict__ cases, Cells cl, Soa<T> dst,
+__global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict__ cases, Cells cl, const P4<T> *dst,
                                                         const int64_t *__restrict__ off_new, int G, int32_t *err,
                                                         uint32_t *d_step, const int64_t *__restrict__ off_old,
                                                         int64_t *d_psteps)
@@ -1555,8 +1529,10 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
         todo &= todo - 1;
         const int64_t bl = readlane64(ib, l), el = readlane64(ie, l);
         double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int64_t kk = bl + lane; kk < el; kk += WAVE)
-            add_phi(a, (double)dst.u[kk], (double)dst.v[kk], (double)dst.w[kk]);
+        for (int64_t kk = bl + lane; kk < el; kk += WAVE) {
+            const P4<T> r = dst[kk];
+            add_phi(a, (double)r.u, (double)r.v, (double)r.w);
+        }
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             a[q] = wave_sum(a[q]);
@@ -1598,7 +1574,7 @@ __device__ __forceinline__ int cell_prim(const Cells &cl, const DCase &c, int g,
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_stress_heat(const DCase *__restrict__ cases, Cells cl, Soa<T> a,
+__global__ void __launch_bounds__(256) k_stress_heat(const DCase *__restrict__ cases, Cells cl, const P4<T> *a,
                                                      const int64_t *__restrict__ off, int g0, int g1,
                                                      double *__restrict__ out)
 {
@@ -1634,7 +1610,8 @@ __global__ void __launch_bounds__(256) k_stress_heat(const DCase *__restrict__ c
         double sm[3] = {0.0, 0.0, 0.0};
         if (ok) {
             for (int64_t kk = off[g] + threadIdx.x; kk < off[g + 1]; kk += blockDim.x) {
-                const double cx = (double)a.u[kk] - W[1], cy = (double)a.v[kk] - W[2], cz = (double)a.w[kk] - W[3];
+                const P4<T> r = a[kk];
+                const double cx = (double)r.u - W[1], cy = (double)r.v - W[2], cz = (double)r.w - W[3];
                 const double c2 = cx * cx + cy * cy + cz * cz;
                 sm[0] += cx * cx;
                 sm[1] += c2;
@@ -1672,7 +1649,7 @@ __global__ void __launch_bounds__(256) k_stress_heat(const DCase *__restrict__ c
 
 // Particle moments recomputed from a canonical array (after a state is loaded).
 template <typename T>
-__global__ void __launch_bounds__(512) k_moments(const DCase *__restrict__ cases, Cells cl, Soa<T> a,
+__global__ void __launch_bounds__(512) k_moments(const DCase *__restrict__ cases, Cells cl, const P4<T> *a,
                                                   const int64_t *__restrict__ off, int G, int32_t *err)
 {
     __shared__ double red[5 * 16];
@@ -1681,8 +1658,10 @@ __global__ void __launch_bounds__(512) k_moments(const DCase *__restrict__ cases
         const DCase &c = cases[cl.cell_case[g]];
         const int64_t b = off[g], e = off[g + 1];
         double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int64_t kk = b + threadIdx.x; kk < e; kk += blockDim.x)
-            add_phi(s, (double)a.u[kk], (double)a.v[kk], (double)a.w[kk]);
+        for (int64_t kk = b + threadIdx.x; kk < e; kk += blockDim.x) {
+            const P4<T> r = a[kk];
+            add_phi(s, (double)r.u, (double)r.v, (double)r.w);
+        }
         block_sum<5>(s, red);
         if (threadIdx.x == 0) {
             bool bad = false;
@@ -1703,9 +1682,9 @@ __global__ void __launch_bounds__(512) k_moments(const DCase *__restrict__ cases
 // Step sequence
 // ---------------------------------------------------------------------------
 template <typename T>
-static Soa<T> soa(void *const p[4])
+static P4<T> *recs(void *p)
 {
-    return Soa<T>{(T *)p[0], (T *)p[1], (T *)p[2], (T *)p[3]};
+    return (P4<T> *)p;
 }
 
 struct Mark {
@@ -1733,7 +1712,7 @@ static void step_impl(duwp_ctx *ctx)
     const int G = ctx->G, p = ctx->step & 1;
     const int bc = ctx->block_cells;
     hipStream_t st = ctx->stream;
-    const Soa<T> src = soa<T>(ctx->A[p]), dst = soa<T>(ctx->A[p ^ 1]), stg = soa<T>(ctx->S);
+    P4<T> *const src = recs<T>(ctx->A[p]), *const dst = recs<T>(ctx->A[p ^ 1]), *const stg = recs<T>(ctx->S);
     const Inj<T> inj{(T *)ctx->J[0], (T *)ctx->J[1], (T *)ctx->J[2], (T *)ctx->J[3], ctx->j_dest, ctx->j_rank,
                      ctx->j_count, (T *)ctx->K[0], (T *)ctx->K[1], (T *)ctx->K[2], (T *)ctx->K[3], ctx->k_dest,
                      ctx->k_n, ctx->k_chunk};
@@ -1782,10 +1761,8 @@ static void step_impl(duwp_ctx *ctx)
         // cells with many particles and candidates (their own list): disjoint
         // from the cells of k_collide, so the two run side by side
         Mark m(ctx, "collide_big");
-        hipLaunchKernelGGL(k_big_bases, dim3(1), dim3(1024), 0, s2, cl);
         hipLaunchKernelGGL(k_collide_big<T>, dim3(ctx->big_blocks * BigCfg<T>::PER_CU), dim3(BigCfg<T>::B), 0, s2,
-                           ctx->d_cases,
-                           cl, src, stg, (P4<T> *)ctx->pk, ctx->d_step, ctx->cap);
+                           ctx->d_cases, cl, src, stg, ctx->d_step, ctx->cap);
     }
     if (fork) (void)hipEventRecord(ctx->ev_join, s2);
     {
@@ -1860,7 +1837,7 @@ static void reload_impl(duwp_ctx *ctx)
     Cells cl = ctx->cl;
     cl.hist = ctx->hist_buf[p];
     cl.fix = ctx->fix_buf[p];
-    const Soa<T> a = soa<T>(ctx->A[p]);
+    P4<T> *const a = recs<T>(ctx->A[p]);
     hipLaunchKernelGGL(k_moments<T>, dim3(G), dim3(ctx->block_cells), 0, ctx->stream, ctx->d_cases, cl, a,
                        ctx->off[p], G, ctx->d_err);
     hipLaunchKernelGGL(k_hist_build<T>, dim3(G), dim3(ctx->block_cells), 0, ctx->stream, ctx->d_cases, cl, a, a,
@@ -1879,7 +1856,7 @@ template <typename T>
 static void stress_heat_impl(duwp_ctx *ctx, int g0, int g1, double *out)
 {
     const int p = ctx->step & 1;
-    const Soa<T> a = soa<T>(ctx->A[p]);
+    P4<T> *const a = recs<T>(ctx->A[p]);
     const int n = g1 - g0;
     hipLaunchKernelGGL(k_stress_heat<T>, dim3(n < 65535 ? n : 65535), dim3(256), 0, ctx->stream, ctx->d_cases,
                        ctx->cl, a, ctx->off[p], g0, g1, out);
