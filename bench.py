@@ -66,6 +66,33 @@ def kernel_fingerprint(kernel: str) -> str:
     return h.hexdigest()
 
 
+def sources_fingerprint() -> str:
+    """sha256 over every source file of the library (the counted traffic of a whole
+    step stays valid while none of them changed)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2305_12071_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def counted_step(workload: str):
+    """HBM bytes of one whole step (all kernels, FETCH_SIZE + WRITE_SIZE scaled as
+    for the dominant kernel) and the particles of that step, from the committed
+    counter summary, or None when any library source changed since."""
+    import glob
+    fp = sources_fingerprint()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
+        with open(path) as fh:
+            d = json.load(fh)
+        if d.get("workload") == workload and d.get("sources_sha256") == fp and "step_hbm_bytes" in d:
+            return d["step_hbm_bytes"], d["particles_per_launch"]
+    return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -304,6 +331,7 @@ def main():
             extra[leg] = {"error": repr(e)}
         torch.cuda.empty_cache()
 
+    step_tr = counted_step(case.name) if value is not None else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -324,7 +352,12 @@ def main():
             "bytes_per_particle_step": STEP_BYTES_PER_PARTICLE["mixed"],
             "gbs": round(STEP_BYTES_PER_PARTICLE["mixed"] * value / 1e9, 1),
             "frac": round(STEP_BYTES_PER_PARTICLE["mixed"] * value / 1e9 / HBM_PEAK_GBS, 4),
-            "fp64_gbs": round(STEP_BYTES_PER_PARTICLE["fp64"] * fp64 / 1e9, 1) if fp64 else None},
+            "fp64_gbs": round(STEP_BYTES_PER_PARTICLE["fp64"] * fp64 / 1e9, 1) if fp64 else None,
+            "note": "nominal: a cell pass and a sort each read and write every particle; this path "
+                    "streams inside the sort and skips the cell pass where nothing is absorbed or "
+                    "resampled, so the nominal rate can exceed the HBM peak",
+            "counted_bytes_per_particle_step": round(step_tr[0] / step_tr[1], 2) if step_tr else None,
+            "counted_gbs": round(step_tr[0] / step_tr[1] * value / 1e9, 1) if step_tr else None},
         "fp64_value": fp64,
         "mixed_over_fp64": (value / fp64) if (fp64 and value) else None,
         "fp64_block_cells": bc64,
