@@ -142,6 +142,8 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &c.ncand_w, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.big_list, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.nbig, 4));
+    TRY(dalloc(ctx, &c.touch_list, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.ntouch, 4));
     TRY(dalloc(ctx, &ctx->diag, 8 * 5 * (size_t)G));
     ctx->items_cap = std::max<int64_t>(1 << 20, 2 * (int64_t)G);
     TRY(dalloc(ctx, &ctx->item_cell, 4 * (size_t)ctx->items_cap));
@@ -212,6 +214,7 @@ duwp_status upload_initial(duwp_ctx *ctx)
     HIP_OK(hipMemsetAsync(ctx->cl.mpart, 0, 8 * 5 * (size_t)G * duwp::NBIN, s));
     HIP_OK(hipMemsetAsync(ctx->cl.far_in, 0, 4 * (size_t)G, s));
     HIP_OK(hipMemsetAsync(ctx->cl.nbig, 0, 4, s));
+    HIP_OK(hipMemsetAsync(ctx->cl.ntouch, 0, 4, s));
     for (int p = 0; p < 2; ++p) HIP_OK(hipMemsetAsync(ctx->off[p], 0, 8 * (size_t)(G + 1), s));
     HIP_OK(hipMemsetAsync(ctx->d_step, 0, 4, s));
     HIP_OK(hipMemsetAsync(ctx->d_err, 0, 4, s));

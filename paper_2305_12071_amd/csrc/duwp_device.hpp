@@ -69,6 +69,8 @@ struct Cells {
     int64_t *cbase;     // [G+1] first collision candidate of each cell in the step's candidate list
     int32_t *big_list;  // [G] cells that collide in the block kernel (unordered)
     int32_t *nbig;      // [1] their number (cleared at the end of each step)
+    int32_t *touch_list;  // [G] cells that absorb or resample this step (any order)
+    int32_t *ntouch;      // [1] their number (cleared at the end of each step)
     uint64_t *cr_seen;  // [G] largest relative speed seen this step (bits of a non-negative double)
     int32_t *hist;      // [G*NBIN] destination histogram of this step, then scatter bases
     int32_t *hist_nx;   // [G*NBIN] histogram predicted for the next step

@@ -137,7 +137,22 @@ __global__ void __launch_bounds__(256) k_cellstate(const DCase *__restrict__ cas
         base = __shfl(base, 0, WAVE);
         if (big) cl.big_list[base + lane_rank_lt(bm)] = g;
     }
+    // cells that absorb or resample are listed for k_absorb_resample; the others
+    // keep their segment in place
+    const bool touched = in && (nabs > 0 || nnew > 0);
+    const uint64_t tm = __ballot(touched);
+    if (tm) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(cl.ntouch, __popcll(tm));
+        base = __shfl(base, 0, WAVE);
+        if (touched) cl.touch_list[base + lane_rank_lt(tm)] = g;
+    }
     if (!in) return;
+    if (!touched) {
+        cl.seg[g] = b;
+        cl.d_abs[g] = 0;
+        cl.d_new[g] = 0;
+    }
     cl.fix_nx[g] = 0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) cl.wt[(int64_t)g * 5 + i] = W[i];
@@ -146,7 +161,6 @@ __global__ void __launch_bounds__(256) k_cellstate(const DCase *__restrict__ cas
     cl.n_surv[g] = ns;
     cl.n_new[g] = nnew;
     cl.n_int[g] = N;
-    const bool touched = nabs > 0 || nnew > 0;
     cl.n_stage[g] = touched ? N : 0;
     cl.seg_stg[g] = touched ? 1 : 0;
     cl.inj_cnt[g] = 0;
@@ -213,14 +227,10 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
     __shared__ int scr[16];
     __shared__ int dh[NBIN];
     const uint32_t step = *d_step;
-    for (int gi = blockIdx.x; gi < G; gi += gridDim.x) {
-        const int g = cl.order[gi];
-        const int touched = cl.seg_stg[g];
-        if (threadIdx.x == 0) cl.seg[g] = touched ? sbase[g] : off[g];
-        if (!touched) {
-            if (threadIdx.x == 0) { cl.d_abs[g] = 0; cl.d_new[g] = 0; }
-            continue;
-        }
+    const int ntouch = *cl.ntouch;
+    for (int e0 = blockIdx.x; e0 < ntouch; e0 += gridDim.x) {
+        const int g = cl.touch_list[e0];
+        if (threadIdx.x == 0) cl.seg[g] = sbase[g];
         const int k = cl.cell_case[g];
         const DCase &c = cases[k];
         const CaseK ck(c);
@@ -354,6 +364,7 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
 // ---------------------------------------------------------------------------
 constexpr int COLL_HBITS = 8;
 constexpr int COLL_WPB = 4;      // waves per block
+constexpr int COLL_BY_CELL_MAX = 8192;    // up to this many cells: a wave per cell
 
 // item_cell[w] = first cell of item w; d_items = {number of items, S}
 __global__ void __launch_bounds__(256) k_items(const int64_t *__restrict__ cbase, int G, int32_t *item_cell,
@@ -376,45 +387,6 @@ __global__ void __launch_bounds__(256) k_items(const int64_t *__restrict__ cbase
     for (int64_t w = lo / S + 1; w * S <= hi && w < nitems; ++w) item_cell[w] = g;
 }
 
-// The candidate scan and k_items in one block of 1024 threads (G <= SCAN1_MAX):
-// cbase[g] = candidates of the cells before g; the thread holding cell g writes
-// the items w with cbase[g] < w S <= cbase[g + 1], which start at cell g + 1.
-__global__ void __launch_bounds__(1024) k_scan_items(const int32_t *__restrict__ in, int G, int64_t *cbase,
-                                                     int64_t *total, int32_t *item_cell, int64_t *d_items,
-                                                     int64_t items_cap)
-{
-    __shared__ int64_t lds[16];
-    const int t0 = threadIdx.x * SCAN1_ITEMS;
-    int64_t v[SCAN1_ITEMS];
-    int64_t s = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN1_ITEMS; ++i) {
-        v[i] = (t0 + i < G) ? in[t0 + i] : 0;
-        s += v[i];
-    }
-    int64_t tot;
-    int64_t run = block_exclusive_scan64(s, lds, &tot);
-    int64_t S = (tot + items_cap - 2) / (items_cap - 1);   // at most items_cap - 1 items
-    S = S < WAVE ? WAVE : (S + WAVE - 1) / WAVE * WAVE;
-    const int64_t nitems = (tot + S - 1) / S;
-    if (threadIdx.x == 0) {
-        d_items[0] = nitems;
-        d_items[1] = S;
-        *total = tot;
-        cbase[G] = tot;
-        if (nitems > 0) item_cell[0] = 0;
-    }
-#pragma unroll
-    for (int i = 0; i < SCAN1_ITEMS; ++i) {
-        const int g = t0 + i;
-        if (g < G) {
-            cbase[g] = run;
-            for (int64_t w = run / S + 1; w * S <= run + v[i] && w < nitems; ++w) item_cell[w] = g + 1;
-        }
-        run += v[i];
-    }
-}
-
 __device__ __forceinline__ uint32_t coll_slot(int g, uint32_t i)
 {
     return ((uint32_t)g * 0x9E3779B1u ^ i * 0x85EBCA77u) * 0xC2B2AE3Du >> (32 - COLL_HBITS);
@@ -424,16 +396,141 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases, Cells cl, P4<T> *src,
                                                  P4<T> *stg, const uint32_t *__restrict__ d_step, int G,
                                                  int64_t cap, int32_t *err, const int32_t *__restrict__ item_cell,
-                                                 const int64_t *__restrict__ d_items)
+                                                 const int64_t *__restrict__ d_items, int by_cell)
 {
     __shared__ uint64_t hmask[COLL_WPB][1 << COLL_HBITS];
     __shared__ T fwd[COLL_WPB][6][WAVE];     // (u,v,w) of particle i, then of j, per lane
     const int wv = threadIdx.x >> 6, lane = lane_id();
     const uint32_t step = *d_step;
-    const int64_t nitems = d_items[0];
     for (int t = lane; t < (1 << COLL_HBITS); t += WAVE) hmask[wv][t] = 0ull;
     lds_fence();
     const uint64_t lt = lanemask_lt();
+    // One chunk: lane l runs candidate q of cell g (act false: no candidate);
+    // more: another chunk of the same work follows and reads what this one stored.
+    auto chunk = [&](int g, uint32_t q, bool act, bool more) {
+        // the cell's particles, constants and pair
+        uint32_t i = 0, j = 0;
+        double u2 = 0.0, u3 = 0.0, u4 = 0.0, cm = 1.0, aexp = 0.0;
+        T xi = 0, ui = 0, vi = 0, wi = 0, xj = 0, uj = 0, vj = 0, wj = 0;
+        P4<T> *pr = nullptr;
+        int lc = 0, k = 0;
+        if (act) {
+            const int32_t N = cl.n_int[g];
+            const int64_t sb = cl.seg[g];
+            k = cl.cell_case[g];
+            const DCase &c = cases[k];
+            lc = g - c.cell_base;
+            if (sb + N > cap) {
+                act = false;   // capacity overflow, already reported
+            } else {
+                P4<T> *sg = cl.seg_stg[g] ? stg : src;
+                cm = cl.cr_max[g];
+                aexp = 1.0 - 2.0 * c.ups;
+                const U4 ra = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 0);
+                const U4 rb = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 1);
+                const uint64_t r0 = ((uint64_t)ra.a << 32) | ra.b;
+                const uint64_t r1 = ((uint64_t)ra.c << 32) | ra.d;
+                i = (uint32_t)mulhi64(r0, (uint64_t)N);
+                j = (uint32_t)mulhi64(r1, (uint64_t)(N - 1));
+                if (j >= i) j += 1;
+                u2 = u01(rb.a); u3 = u01(rb.b); u4 = u01(rb.c);
+                pr = sg + sb;
+                const P4<T> a = pr[i], bq = pr[j];
+                xi = a.x; ui = a.u; vi = a.v; wi = a.w;
+                xj = bq.x; uj = bq.u; vj = bq.v; wj = bq.w;
+            }
+        }
+        if (!act) g = -1;
+        // last earlier lane touching each of this lane's particles
+        const uint32_t si = coll_slot(g, i), sj = coll_slot(g, j);
+        if (act) {
+            atomicOr(&hmask[wv][si], 1ull << lane);
+            atomicOr(&hmask[wv][sj], 1ull << lane);
+        }
+        lds_fence();
+        uint64_t ci = act ? (hmask[wv][si] & lt) : 0ull, cj = act ? (hmask[wv][sj] & lt) : 0ull;
+        lds_fence();
+        if (act) { hmask[wv][si] = 0ull; hmask[wv][sj] = 0ull; }
+        int pi = -1, pj = -1, oi = 0, oj = 0;
+        while (__ballot(ci != 0ull || cj != 0ull)) {
+            const int li = ci ? 63 - __clzll((long long)ci) : lane;
+            const int lj = cj ? 63 - __clzll((long long)cj) : lane;
+            const int gli = __shfl(g, li, WAVE), glj = __shfl(g, lj, WAVE);
+            const uint32_t ii = __shfl(i, li, WAVE), ji = __shfl(j, li, WAVE);
+            const uint32_t ij = __shfl(i, lj, WAVE), jj = __shfl(j, lj, WAVE);
+            if (ci) {
+                if (gli == g && (ii == i || ji == i)) { pi = li; oi = ii == i ? 0 : 3; ci = 0ull; }
+                else ci &= ~(1ull << li);
+            }
+            if (cj) {
+                if (glj == g && (ij == j || jj == j)) { pj = lj; oj = ij == j ? 0 : 3; cj = 0ull; }
+                else cj &= ~(1ull << lj);
+            }
+        }
+        const uint64_t dep = (pi >= 0 ? 1ull << pi : 0ull) | (pj >= 0 ? 1ull << pj : 0ull);
+        double seen = 0.0;
+        int acc = 0;
+        bool far = false;
+        uint64_t done = ~__ballot(act);
+        while (done != ~0ull) {
+            const bool ready = !((done >> lane) & 1ull) && (dep & ~done) == 0ull;
+            if (ready) {
+                if (pi >= 0) { ui = fwd[wv][oi][pi]; vi = fwd[wv][oi + 1][pi]; wi = fwd[wv][oi + 2][pi]; }
+                if (pj >= 0) { uj = fwd[wv][oj][pj]; vj = fwd[wv][oj + 1][pj]; wj = fwd[wv][oj + 2][pj]; }
+                const T ui0 = ui, uj0 = uj;
+                if (collide_vals<T>(ui, vi, wi, uj, vj, wj, cm, aexp, u2, u3, u4, seen)) {
+                    acc = 1;
+                    pr[i] = P4<T>{xi, ui, vi, wi};
+                    pr[j] = P4<T>{xj, uj, vj, wj};
+                    // move the pair between destination bins of this step's histogram
+                    const DCase &c = cases[k];
+                    int32_t *hg = cl.hist + (int64_t)g * NBIN;
+                    bool f0 = false;
+                    const int a0 = flight_bin<T>(c, lc, xi, ui0, &f0), a1 = flight_bin<T>(c, lc, xi, ui, &far);
+                    const int b0 = flight_bin<T>(c, lc, xj, uj0, &f0), b1 = flight_bin<T>(c, lc, xj, uj, &far);
+                    if (a0 != a1) {
+                        if (a0 >= 0) atomicSub(&hg[a0], 1);
+                        if (a1 >= 0) atomicAdd(&hg[a1], 1);
+                    }
+                    if (b0 != b1) {
+                        if (b0 >= 0) atomicSub(&hg[b0], 1);
+                        if (b1 >= 0) atomicAdd(&hg[b1], 1);
+                    }
+                }
+                fwd[wv][0][lane] = ui; fwd[wv][1][lane] = vi; fwd[wv][2][lane] = wi;
+                fwd[wv][3][lane] = uj; fwd[wv][4][lane] = vj; fwd[wv][5][lane] = wj;
+            }
+            lds_fence();
+            done |= __ballot(ready);
+        }
+        // per-cell results: accepted collisions (segmented sum over the chunk's
+        // lanes of one cell), largest relative speed, out-of-window flag
+        int sacc = acc;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const int t = __shfl_up(sacc, o, WAVE);
+            const int gu = __shfl_up(g, o, WAVE);
+            if (lane >= o && gu == g) sacc += t;
+        }
+        const int gd = __shfl_down(g, 1, WAVE);
+        if (g >= 0 && (lane == WAVE - 1 || gd != g) && sacc > 0) atomicAdd(&cl.d_coll[g], sacc);
+        if (act && seen > cm)
+            atomicMax((unsigned long long *)&cl.cr_seen[g], (unsigned long long)__double_as_longlong(seen));
+        if (far) cl.fix[g] = 1;
+        // the next chunk of this work reads what this one stored
+        if (more) __threadfence_block();
+    };
+    if (by_cell) {
+        // a wave per cell, cells in visiting order (few cells with many candidates)
+        for (int gi = blockIdx.x * COLL_WPB + wv; gi < G; gi += gridDim.x * COLL_WPB) {
+            const int g = cl.order[gi];
+            const int32_t M = cl.ncand_w[g];
+            for (int32_t q0 = 0; q0 < M; q0 += WAVE) chunk(g, (uint32_t)(q0 + lane), q0 + lane < M, q0 + WAVE < M);
+        }
+        return;
+    }
+    // work items of whole cells from the scanned candidate list
+    const int64_t nitems = d_items[0];
     for (int64_t it = (int64_t)blockIdx.x * COLL_WPB + wv; it < nitems; it += (int64_t)gridDim.x * COLL_WPB) {
         const int ga = item_cell[it];
         const int gb = it + 1 < nitems ? item_cell[it + 1] : G;
@@ -471,119 +568,8 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
                 }
             }
             const int gnext = __builtin_amdgcn_readlane(g, WAVE - 1);
-            // the cell's particles, constants and pair
-            uint32_t i = 0, j = 0;
-            double u2 = 0.0, u3 = 0.0, u4 = 0.0, cm = 1.0, aexp = 0.0;
-            T xi = 0, ui = 0, vi = 0, wi = 0, xj = 0, uj = 0, vj = 0, wj = 0;
-            P4<T> *pr = nullptr;
-            int lc = 0, k = 0;
-            if (act) {
-                const int32_t N = cl.n_int[g];
-                const int64_t sb = cl.seg[g];
-                k = cl.cell_case[g];
-                const DCase &c = cases[k];
-                lc = g - c.cell_base;
-                if (sb + N > cap) {
-                    act = false;   // capacity overflow, already reported
-                } else {
-                    P4<T> *sg = cl.seg_stg[g] ? stg : src;
-                    cm = cl.cr_max[g];
-                    aexp = 1.0 - 2.0 * c.ups;
-                    const uint32_t q = (uint32_t)(Q - gstart);
-                    const U4 ra = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 0);
-                    const U4 rb = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 1);
-                    const uint64_t r0 = ((uint64_t)ra.a << 32) | ra.b;
-                    const uint64_t r1 = ((uint64_t)ra.c << 32) | ra.d;
-                    i = (uint32_t)mulhi64(r0, (uint64_t)N);
-                    j = (uint32_t)mulhi64(r1, (uint64_t)(N - 1));
-                    if (j >= i) j += 1;
-                    u2 = u01(rb.a); u3 = u01(rb.b); u4 = u01(rb.c);
-                    pr = sg + sb;
-                    const P4<T> a = pr[i], bq = pr[j];
-                    xi = a.x; ui = a.u; vi = a.v; wi = a.w;
-                    xj = bq.x; uj = bq.u; vj = bq.v; wj = bq.w;
-                }
-            }
-            if (!act) g = -1;
-            // last earlier lane touching each of this lane's particles
-            const uint32_t si = coll_slot(g, i), sj = coll_slot(g, j);
-            if (act) {
-                atomicOr(&hmask[wv][si], 1ull << lane);
-                atomicOr(&hmask[wv][sj], 1ull << lane);
-            }
-            lds_fence();
-            uint64_t ci = act ? (hmask[wv][si] & lt) : 0ull, cj = act ? (hmask[wv][sj] & lt) : 0ull;
-            lds_fence();
-            if (act) { hmask[wv][si] = 0ull; hmask[wv][sj] = 0ull; }
-            int pi = -1, pj = -1, oi = 0, oj = 0;
-            while (__ballot(ci != 0ull || cj != 0ull)) {
-                const int li = ci ? 63 - __clzll((long long)ci) : lane;
-                const int lj = cj ? 63 - __clzll((long long)cj) : lane;
-                const int gli = __shfl(g, li, WAVE), glj = __shfl(g, lj, WAVE);
-                const uint32_t ii = __shfl(i, li, WAVE), ji = __shfl(j, li, WAVE);
-                const uint32_t ij = __shfl(i, lj, WAVE), jj = __shfl(j, lj, WAVE);
-                if (ci) {
-                    if (gli == g && (ii == i || ji == i)) { pi = li; oi = ii == i ? 0 : 3; ci = 0ull; }
-                    else ci &= ~(1ull << li);
-                }
-                if (cj) {
-                    if (glj == g && (ij == j || jj == j)) { pj = lj; oj = ij == j ? 0 : 3; cj = 0ull; }
-                    else cj &= ~(1ull << lj);
-                }
-            }
-            const uint64_t dep = (pi >= 0 ? 1ull << pi : 0ull) | (pj >= 0 ? 1ull << pj : 0ull);
-            double seen = 0.0;
-            int acc = 0;
-            bool far = false;
-            uint64_t done = ~__ballot(act);
-            while (done != ~0ull) {
-                const bool ready = !((done >> lane) & 1ull) && (dep & ~done) == 0ull;
-                if (ready) {
-                    if (pi >= 0) { ui = fwd[wv][oi][pi]; vi = fwd[wv][oi + 1][pi]; wi = fwd[wv][oi + 2][pi]; }
-                    if (pj >= 0) { uj = fwd[wv][oj][pj]; vj = fwd[wv][oj + 1][pj]; wj = fwd[wv][oj + 2][pj]; }
-                    const T ui0 = ui, uj0 = uj;
-                    if (collide_vals<T>(ui, vi, wi, uj, vj, wj, cm, aexp, u2, u3, u4, seen)) {
-                        acc = 1;
-                        pr[i] = P4<T>{xi, ui, vi, wi};
-                        pr[j] = P4<T>{xj, uj, vj, wj};
-                        // move the pair between destination bins of this step's histogram
-                        const DCase &c = cases[k];
-                        int32_t *hg = cl.hist + (int64_t)g * NBIN;
-                        bool f0 = false;
-                        const int a0 = flight_bin<T>(c, lc, xi, ui0, &f0), a1 = flight_bin<T>(c, lc, xi, ui, &far);
-                        const int b0 = flight_bin<T>(c, lc, xj, uj0, &f0), b1 = flight_bin<T>(c, lc, xj, uj, &far);
-                        if (a0 != a1) {
-                            if (a0 >= 0) atomicSub(&hg[a0], 1);
-                            if (a1 >= 0) atomicAdd(&hg[a1], 1);
-                        }
-                        if (b0 != b1) {
-                            if (b0 >= 0) atomicSub(&hg[b0], 1);
-                            if (b1 >= 0) atomicAdd(&hg[b1], 1);
-                        }
-                    }
-                    fwd[wv][0][lane] = ui; fwd[wv][1][lane] = vi; fwd[wv][2][lane] = wi;
-                    fwd[wv][3][lane] = uj; fwd[wv][4][lane] = vj; fwd[wv][5][lane] = wj;
-                }
-                lds_fence();
-                done |= __ballot(ready);
-            }
-            // per-cell results: accepted collisions (segmented sum over the chunk's
-            // lanes of one cell), largest relative speed, out-of-window flag
-            int sacc = acc;
-#pragma unroll
-            for (int o = 1; o < WAVE; o <<= 1) {
-                const int t = __shfl_up(sacc, o, WAVE);
-                const int gu = __shfl_up(g, o, WAVE);
-                if (lane >= o && gu == g) sacc += t;
-            }
-            const int gd = __shfl_down(g, 1, WAVE);
-            if (g >= 0 && (lane == WAVE - 1 || gd != g) && sacc > 0) atomicAdd(&cl.d_coll[g], sacc);
-            if (act && seen > cm)
-                atomicMax((unsigned long long *)&cl.cr_seen[g], (unsigned long long)__double_as_longlong(seen));
-            if (far) cl.fix[g] = 1;
+            chunk(g, (uint32_t)(Q - gstart), act, Q0 + WAVE < qend);
             gcur = gnext;
-            // the next chunk of this item reads what this one stored
-            if (Q0 + WAVE < qend) __threadfence_block();
         }
     }
 }
@@ -960,7 +946,7 @@ __device__ __forceinline__ int block_stable_rank(int key, int *binbase, int (*wc
 // candidate chunk are visited: a prefix over the chunk counts maps the e-th
 // entrant of a side to its chunk.
 template <typename T>
-__global__ void __launch_bounds__(256) k_inject_rank(const DCase *__restrict__ cases, Cells cl, Inj<T> inj,
+__global__ void __launch_bounds__(1024) k_inject_rank(const DCase *__restrict__ cases, Cells cl, Inj<T> inj,
                                                      int64_t *d_ninj, int32_t *err)
 {
     constexpr int MAXCH = 2048;
@@ -1137,6 +1123,48 @@ __global__ void __launch_bounds__(256) k_bases(Cells cl, const int64_t *__restri
     if (ok) cl.hist[idx] = incl - h;
     const int run = __shfl(incl, WAVE - 1, WAVE);
     if (lane == 0) cl.inj_start[d] = off_new[d] + run;
+}
+
+// Entrants go after the cell-sourced particles of their destination cell; their
+// next-step destinations join the predicted histogram.  Part sub of nsub of the
+// entrants of case k.
+template <typename T>
+__device__ __forceinline__ void scatter_entrants(const DCase &c, const Cells &cl, const Inj<T> &inj, P4<T> *dst,
+                                              int64_t cap, int k, int sub, int nsub)
+{
+    const int32_t n = inj.count[k];
+    const int lane = lane_id();
+    for (int i0 = sub * blockDim.x; i0 < n; i0 += nsub * blockDim.x) {
+        const int i = i0 + threadIdx.x;
+        int key = -1;
+        if (i < n) {
+            const int64_t sl = c.inj_base + i;
+            const int d = inj.dest[sl];
+            const int64_t pos = cl.inj_start[d] + inj.rank[sl];
+            const T x = inj.x[sl], u = inj.u[sl];
+            if (pos < cap) dst[pos] = P4<T>{x, u, inj.v[sl], inj.w[sl]};
+            bool farp = false;
+            const int hb = flight_bin<T>(c, d - c.cell_base, x, u, &farp);
+            if (hb >= 0) key = d * NBIN + hb;
+            if (farp) cl.fix_nx[d] = 1;
+        }
+        uint64_t rem = __ballot(key >= 0);
+        while (rem) {
+            const int leader = __ffsll((unsigned long long)rem) - 1;
+            const int v0 = __builtin_amdgcn_readlane(key, leader);
+            const uint64_t mm = __ballot(key == v0);
+            if (lane == leader) atomicAdd(&cl.hist_nx[v0], __popcll(mm));
+            rem &= ~mm;
+        }
+    }
+}
+
+// 11. the entrants of case blockIdx.y, in gridDim.x parts
+template <typename T>
+__global__ void __launch_bounds__(256) k_scatter_inj(const DCase *__restrict__ cases, Cells cl, Inj<T> inj,
+                                                     P4<T> *dst, int64_t cap)
+{
+    scatter_entrants<T>(cases[blockIdx.y], cl, inj, dst, cap, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1422,63 +1450,11 @@ __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1
     }
 }
 
-// 11. entrants go after the cell-sourced particles of their destination cell;
-// their next-step destinations join the predicted histogram
-template <typename T>
-__global__ void __launch_bounds__(256) k_scatter_inj(const DCase *__restrict__ cases, Cells cl, Inj<T> inj,
-                                                     P4<T> *dst, int64_t cap)
-{
-    const int k = blockIdx.y;
-    const DCase &c = cases[k];
-    const int32_t n = inj.count[k];
-    const int lane = lane_id();
-    for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
-        const int i = i0 + threadIdx.x;
-        int key = -1;
-        if (i < n) {
-            const int64_t sl = c.inj_base + i;
-            const int d = inj.dest[sl];
-            const int64_t pos = cl.inj_start[d] + inj.rank[sl];
-            const T x = inj.x[sl], u = inj.u[sl];
-            if (pos < cap) dst[pos] = P4<T>{x, u, inj.v[sl], inj.w[sl]};
-            bool farp = false;
-            const int hb = flight_bin<T>(c, d - c.cell_base, x, u, &farp);
-            if (hb >= 0) key = d * NBIN + hb;
-            if (farp) cl.fix_nx[d] = 1;
-        }
-        uint64_t rem = __ballot(key >= 0);
-        while (rem) {
-            const int leader = __ffsll((unsigned long long)rem) - 1;
-            const int v0 = __builtin_amdgcn_readlane(key, leader);
-            const uint64_t mm = __ballot(key == v0);
-            if (lane == leader) atomicAdd(&cl.hist_nx[v0], __popcll(mm));
-            rem &= ~mm;
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
-// 12. Wave part update with the NS flux of the start-of-step total state
-// (Eq. r1).  One thread per cell computes both of its faces.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_wave(const DCase *__restrict__ cases, Cells cl, int G)
-{
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= G) return;
-    const DCase &c = cases[cl.cell_case[g]];
-    const int lc = g - c.cell_base;
-    double Fl[5], Fr[5];
-    case_face_flux(c, cl, lc, Fl);
-    case_face_flux(c, cl, lc + 1, Fr);
-    const double r = c.dt / c.dx;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) cl.psi_w[(int64_t)g * 5 + k] -= r * (Fr[k] - Fl[k]);
-}
-
-// ---------------------------------------------------------------------------
-// 13. Particle moments of the new state per cell (Eq. gkt_moment0): the sums of
-// the near source cells, of farther sources if any, then the entrants; running
-// average of Psi_t; largest relative speed of the collisions; finite-state check.
+// 12. Particle moments of the new state per cell (Eq. gkt_moment0): the sums of
+// the near source cells, of farther sources if any, then the entrants; the wave
+// part's flux update (Eq. r1); running average of Psi_t; largest relative speed
+// of the collisions; finite-state check.
 // One lane per destination cell; the entrants of a cell are summed by the whole wave.
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1495,6 +1471,7 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
         *d_psteps += off_old[G];
         *d_step += 1;
         *cl.nbig = 0;
+        *cl.ntouch = 0;
     }
     if ((d - lane) >= G) return;
     const bool in = d < G;
@@ -1541,6 +1518,22 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
     }
     if (!in) return;
     const DCase &c = cases[cl.cell_case[d]];
+    // wave part: the update with the NS flux of the start-of-step total state
+    // (Eq. r1; the states cl.wt are those of the step's start), after the
+    // absorbed and resampled moments
+    double pw[5];
+    {
+        const int lc = d - c.cell_base;
+        double Fl[5], Fr[5];
+        case_face_flux(c, cl, lc, Fl);
+        case_face_flux(c, cl, lc + 1, Fr);
+        const double r = c.dt / c.dx;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            pw[q] = cl.psi_w[(int64_t)d * 5 + q] - r * (Fr[q] - Fl[q]);
+            cl.psi_w[(int64_t)d * 5 + q] = pw[q];
+        }
+    }
     // largest relative speed seen by this cell's collision candidates
     const double seen = __longlong_as_double((long long)cl.cr_seen[d]);
     if (seen > cl.cr_max[d]) cl.cr_max[d] = seen;
@@ -1550,7 +1543,7 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
     for (int q = 0; q < 5; ++q) {
         const double p = c.fac * s[q];
         cl.psi_p[(int64_t)d * 5 + q] = p;
-        const double t = cl.psi_w[(int64_t)d * 5 + q] + p;
+        const double t = pw[q] + p;
         if (!isfinite(t)) bad = true;
         cl.avg[(int64_t)d * 5 + q] += t;
     }
@@ -1716,7 +1709,6 @@ static void step_impl(duwp_ctx *ctx)
     const Inj<T> inj{(T *)ctx->J[0], (T *)ctx->J[1], (T *)ctx->J[2], (T *)ctx->J[3], ctx->j_dest, ctx->j_rank,
                      ctx->j_count, (T *)ctx->K[0], (T *)ctx->K[1], (T *)ctx->K[2], (T *)ctx->K[3], ctx->k_dest,
                      ctx->k_n, ctx->k_chunk};
-    const int gthreads = (G + 255) / 256;
     Cells cl = ctx->cl;
     cl.hist = ctx->hist_buf[p];
     cl.hist_nx = ctx->hist_buf[p ^ 1];
@@ -1733,12 +1725,14 @@ static void step_impl(duwp_ctx *ctx)
     }
     {
         Mark m(ctx, "absorb_resample");
-        hipLaunchKernelGGL(k_absorb_resample<T>, dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src,
-                           ctx->off[p], stg, ctx->ibase, ctx->d_step, G, ctx->cap, ctx->d_err);
+        // the listed cells, by a grid of at most 16 blocks per compute unit
+        hipLaunchKernelGGL(k_absorb_resample<T>, dim3(std::min(G, 16 * ctx->big_blocks)), dim3(bc), 0, st,
+                           ctx->d_cases, cl, src, ctx->off[p], stg, ctx->ibase, ctx->d_step, G, ctx->cap,
+                           ctx->d_err);
     }
-    // Injection and the wave-part update do not depend on the collisions: they run
-    // on a second stream (a parallel branch of the captured graph) while the
-    // collide kernel runs.  Kernel timing keeps everything on one stream.
+    // Injection and the big-cell collide do not depend on the small-cell collide:
+    // they go on a second stream (a parallel branch of the captured graph).
+    // Kernel timing keeps everything on one stream.
     const bool fork = !ctx->timer.on && ctx->stream2 != nullptr;
     hipStream_t s2 = fork ? ctx->stream2 : st;
     if (fork) {
@@ -1750,12 +1744,9 @@ static void step_impl(duwp_ctx *ctx)
         if (ctx->inj_blocks > 0)
             hipLaunchKernelGGL(k_inject_gen<T>, dim3(ctx->inj_blocks, 2 * ctx->ncases), dim3(256), 0, s2,
                                ctx->d_cases, inj, ctx->d_step, ctx->d_err);
-        hipLaunchKernelGGL(k_inject_rank<T>, dim3(ctx->ncases), dim3(256), 0, s2, ctx->d_cases, cl, inj,
+        // 1024 threads: a side's entrants in few rounds (each round waits on loads)
+        hipLaunchKernelGGL(k_inject_rank<T>, dim3(ctx->ncases), dim3(1024), 0, s2, ctx->d_cases, cl, inj,
                            ctx->d_ninj, ctx->d_err);
-    }
-    {
-        Mark m(ctx, "wave");
-        hipLaunchKernelGGL(k_wave, dim3(gthreads), dim3(256), 0, s2, ctx->d_cases, cl, G);
     }
     {
         // cells with many particles and candidates (their own list): disjoint
@@ -1767,16 +1758,17 @@ static void step_impl(duwp_ctx *ctx)
     if (fork) (void)hipEventRecord(ctx->ev_join, s2);
     {
         Mark m(ctx, "collide");
-        if (G <= SCAN1_MAX)
-            hipLaunchKernelGGL(k_scan_items, dim3(1), dim3(1024), 0, st, ctx->cl.ncand_w, G, ctx->cl.cbase,
-                               ctx->d_total + 2, ctx->item_cell, ctx->d_items, ctx->items_cap);
-        else {
+        // few cells: a wave per cell; many (mostly small) cells: work items cut
+        // from the scanned candidate list
+        const int by_cell = G <= COLL_BY_CELL_MAX;
+        if (!by_cell) {
             enqueue_scan(ctx, ctx->cl.ncand_w, ctx->cl.cbase, ctx->d_total + 2, INT64_MAX);
             hipLaunchKernelGGL(k_items, dim3((G + 1 + 255) / 256), dim3(256), 0, st, ctx->cl.cbase, G,
                                ctx->item_cell, ctx->d_items, ctx->items_cap);
         }
         hipLaunchKernelGGL(k_collide<T>, dim3(ctx->coll_blocks), dim3(64 * COLL_WPB), 0, st, ctx->d_cases,
-                           cl, src, stg, ctx->d_step, G, ctx->cap, ctx->d_err, ctx->item_cell, ctx->d_items);
+                           cl, src, stg, ctx->d_step, G, ctx->cap, ctx->d_err, ctx->item_cell, ctx->d_items,
+                           by_cell);
     }
     if (fork) (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
     {
@@ -1802,8 +1794,8 @@ static void step_impl(duwp_ctx *ctx)
             hipLaunchKernelGGL((k_scatter<T, 1, SCAT_IT1>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
                                dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout);
         else
-            hipLaunchKernelGGL((k_scatter<T, 8, SCAT_ITN>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg, dst,
-                               ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout);
+            hipLaunchKernelGGL((k_scatter<T, 8, SCAT_ITN>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
+                               dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout);
     }
     {
         Mark m(ctx, "scatter_inj");
