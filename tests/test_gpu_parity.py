@@ -277,3 +277,106 @@ def test_stress_and_heat_flux_match_oracle(prec):
         assert not bad.any(), (n, np.argwhere(bad)[:5].tolist(), np.abs(a - b)[bad][:5], tol[bad][:5])
         assert np.any(b[:, 2] != 0.0)
     g.close()
+
+
+# --------------------------------------------------------------------------
+# Degenerate inputs
+# --------------------------------------------------------------------------
+
+def _step_both(g, o, nsteps, label):
+    for k in range(nsteps):
+        g.step(1)
+        o.step(1)
+        compare_diag(g.diag(), o.diag(), f"{label}:{k}")
+        compare_states(g.get_state(), o.get_state(), label=f"{label}:{k}", psi_t=o.cells()["psi_t"])
+
+
+@pytest.mark.parametrize("fo", [1, 2])
+def test_single_cell_case_matches_oracle(fo):
+    """One cell between two walls: every window, ghost and face is a boundary one."""
+    c = I.box(1, 1.0, 1.0, 300, 3.0)
+    c.flux_order = fo
+    _say("single cell, flux order", fo)
+    g = duwp.Sim(c, seed=2, precision=duwp.FP64)
+    o = O.Oracle(c, seed=2, case_id=0)
+    _step_both(g, o, 5, f"1cell{fo}")
+    g.close()
+
+
+def _without_cells(st, empty):
+    """The state with every particle of the listed cells removed and their wave part zeroed
+    (vacuum cells)."""
+    off = st["off"]
+    keep = np.ones(len(st["x"]), bool)
+    for cc in empty:
+        keep[off[cc]:off[cc + 1]] = False
+    cnt = np.diff(off).copy()
+    cnt[empty] = 0
+    psi = np.array(st["psi_w"], copy=True)
+    psi[empty] = 0.0
+    return dict(x=st["x"][keep], u=st["u"][keep], v=st["v"][keep], w=st["w"][keep],
+                off=np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64), psi_w=psi,
+                cr_max=st["cr_max"], step=st["step"])
+
+
+@pytest.mark.parametrize("fo", [1, 2])
+def test_vacuum_cells_inside_a_tube_match_oracle(fo):
+    """Vacuum cells (no particles, no wave part) between filled ones, at a wall and in
+    the middle: no sampling, no collisions, no wave flux through their faces."""
+    c = I.sod_paper(1e-4)
+    c.flux_order = fo
+    o = O.Oracle(c, seed=4, case_id=0)
+    o.step(6)
+    st = _without_cells(o.get_state(), [0, 10, 11, 40, 70, 99])
+    o.set_state(st)
+    g = duwp.Sim(c, seed=4, precision=duwp.FP64)
+    g.set_state(st)
+    _say("vacuum cells, flux order", fo)
+    _step_both(g, o, 3, f"vacuum{fo}")
+    g.close()
+
+
+def test_empty_case_beside_a_full_one():
+    """A case without any particle or wave mass in a batch: it stays empty, and the
+    other case matches its own oracle."""
+    ce = I.box(5, 1.0, 1.0, 100, 3.0, name="empty_box")
+    cf = CASES["mach3"]
+    g = duwp.Sim([ce, cf], seed=1, precision=duwp.FP64)
+    empty = dict(x=np.zeros(0), u=np.zeros(0), v=np.zeros(0), w=np.zeros(0), off=np.zeros(6, np.int64),
+                 psi_w=np.zeros((5, 5)), cr_max=np.ones(5), step=0)
+    g.set_state(empty, 0)
+    oe = O.Oracle(ce, seed=1, case_id=0)
+    oe.set_state(empty)
+    of = O.Oracle(cf, seed=1, case_id=1)
+    _say("empty case beside mach3")
+    for k in range(3):
+        g.step(1)
+        oe.step(1)
+        of.step(1)
+        se = g.get_state(0)
+        assert len(se["x"]) == 0 and not np.any(se["off"]) and not np.any(se["psi_w"]), k
+        compare_diag(g.diag(1), of.diag(), f"full:{k}")
+        compare_states(g.get_state(1), of.get_state(), label=f"full:{k}", psi_t=of.cells()["psi_t"])
+    g.close()
+
+
+def test_far_move_is_reported():
+    """A particle that would cross more than the sort window in one step is reported as
+    DUWP_ERANGE (the kernels leave it out; nothing is written out of place).  The gas
+    is collisionless (dt/tau = 1e-6), so no collision slows the particle first."""
+    c = I.box(60, 1.0, 1.0, 50, 1e-6)
+    o = O.Oracle(c, seed=1, case_id=0)
+    o.step(1)
+    st = o.get_state()
+    st["u"] = np.array(st["u"], copy=True)
+    st["x"] = np.array(st["x"], copy=True)
+    # the first particle of cell 5, sent 25 cells to the right in one step
+    i0 = int(st["off"][5])
+    st["u"][i0] = 25.0 * c.dx / c.dt
+    g = duwp.Sim(c, seed=1, precision=duwp.FP64)
+    g.set_state(st)
+    _say("far move")
+    with pytest.raises(duwp.DuwpError) as e:
+        g.step(1)
+    assert e.value.status == -6
+    g.close()
