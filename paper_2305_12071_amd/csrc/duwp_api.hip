@@ -394,12 +394,12 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
     ctx->chunk_total = std::max<int64_t>(chunks, 1);
     ctx->inj_blocks = (int)std::min<int64_t>((max_side + 255) / 256, 64);
     {
-        // collision work items are taken by a fixed grid of waves: 16 per compute unit
+        // collision work items are taken by a fixed grid of 16 blocks (64 waves) per compute unit
         int dev = 0, ncu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
             ncu = 256;
-        ctx->coll_blocks = 4 * ncu;
+        ctx->coll_blocks = 16 * ncu;   // work items: many waves in flight hide each chunk's load chain
         ctx->big_blocks = ncu;
     }
     duwp_status s = alloc_all(ctx);

@@ -1766,7 +1766,8 @@ static void step_impl(duwp_ctx *ctx)
             hipLaunchKernelGGL(k_items, dim3((G + 1 + 255) / 256), dim3(256), 0, st, ctx->cl.cbase, G,
                                ctx->item_cell, ctx->d_items, ctx->items_cap);
         }
-        hipLaunchKernelGGL(k_collide<T>, dim3(ctx->coll_blocks), dim3(64 * COLL_WPB), 0, st, ctx->d_cases,
+        const int cblocks = by_cell ? std::min(ctx->coll_blocks, (G + COLL_WPB - 1) / COLL_WPB) : ctx->coll_blocks;
+        hipLaunchKernelGGL(k_collide<T>, dim3(cblocks), dim3(64 * COLL_WPB), 0, st, ctx->d_cases,
                            cl, src, stg, ctx->d_step, G, ctx->cap, ctx->d_err, ctx->item_cell, ctx->d_items,
                            by_cell);
     }
