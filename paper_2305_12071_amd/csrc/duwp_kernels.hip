@@ -44,29 +44,34 @@ constexpr int NBI = 2 * (KWIN + 1);    // injection destination window (both end
 
 // ---------------------------------------------------------------------------
 // 1. Cell state at step start, absorbed and resampled counts, collision
-// candidate counts.  One lane per cell; the absorbed particles of a cell with
-// P > 0 are counted by the whole wave, one cell at a time.
+// candidate counts.  A block takes 64 cells, one lane of its first wave per
+// cell; the absorbed particles of its cells with P > 0 are counted by all of
+// its waves (cell l by wave l mod waves), so that cells with many particles
+// keep the whole GPU busy.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_cellstate(const DCase *__restrict__ cases, Cells cl,
-                                                    const int64_t *__restrict__ off,
-                                                    const uint32_t *__restrict__ d_step, int G,
-                                                    int32_t *err, int64_t *d_nout, int64_t *d_ninj)
+__global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ cases, Cells cl,
+                                                     const int64_t *__restrict__ off,
+                                                     const uint32_t *__restrict__ d_step, int G,
+                                                     int32_t *err, int64_t *d_nout, int64_t *d_ninj)
 {
+    __shared__ double sP[WAVE];
+    __shared__ int64_t sb[WAVE], se[WAVE], spb[WAVE];
+    __shared__ int sk[WAVE], scnt[WAVE];
     const uint32_t step = *d_step;
-    const int lane = lane_id();
-    const int g0 = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * WAVE;
+    const int lane = lane_id(), wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int g0 = blockIdx.x * WAVE;
     if (g0 >= G) return;
     const int nc = min(WAVE, G - g0);
-    for (int t = lane; t < nc * NBIN; t += WAVE) cl.hist_nx[(int64_t)g0 * NBIN + t] = 0;
+    for (int t = threadIdx.x; t < nc * NBIN; t += blockDim.x) cl.hist_nx[(int64_t)g0 * NBIN + t] = 0;
     const int g = g0 + lane;
     const bool in = lane < nc;
-    const int k = in ? cl.cell_case[g] : 0;
+    const int k = (in && wv == 0) ? cl.cell_case[g] : 0;
     const DCase &c = cases[k];
     double W[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     int ok = 0;
     double P = 0.0;
     int64_t b = 0, e = 0, pbase = 0;
-    if (in) {
+    if (in && wv == 0) {
         double t[5];
 #pragma unroll
         for (int i = 0; i < 5; ++i) t[i] = cl.psi_w[(int64_t)g * 5 + i] + cl.psi_p[(int64_t)g * 5 + i];
@@ -79,15 +84,19 @@ __global__ void __launch_bounds__(256) k_cellstate(const DCase *__restrict__ cas
         e = off[g + 1];
         pbase = off[c.cell_base];
     }
-    // classification (one Philox block decides four consecutive particles of a case)
-    int32_t nabs = 0;
-    uint64_t todo = __ballot(in && P > 0.0 && e > b);
-    while (todo) {
-        const int l = __ffsll((unsigned long long)todo) - 1;
-        todo &= todo - 1;
-        const int64_t bl = readlane64(b, l), el = readlane64(e, l), pl = readlane64(pbase, l);
-        const double Pl = readlane_d(P, l);
-        const DCase &cc = cases[__builtin_amdgcn_readlane(k, l)];
+    // classification (one Philox block decides four consecutive particles of a
+    // case): cell l of the block is counted by wave l mod nw
+    if (wv == 0) {
+        sP[lane] = (in && e > b) ? P : 0.0;
+        sb[lane] = b; se[lane] = e; spb[lane] = pbase; sk[lane] = k;
+        scnt[lane] = 0;
+    }
+    __syncthreads();
+    for (int l = wv; l < nc; l += nw) {
+        const double Pl = sP[l];
+        if (!(Pl > 0.0)) continue;
+        const int64_t bl = sb[l], el = se[l], pl = spb[l];
+        const DCase &cc = cases[sk[l]];
         const int64_t q0 = (bl - pl) >> 2, q1 = (el - 1 - pl) >> 2;
         int cnt = 0;
         for (int64_t q = q0 + lane; q <= q1; q += WAVE) {
@@ -99,8 +108,11 @@ __global__ void __launch_bounds__(256) k_cellstate(const DCase *__restrict__ cas
                 if (i0 + m >= bl && i0 + m < el && u01(wd[m]) < Pl) ++cnt;
         }
         cnt = wave_sum_i(cnt);
-        if (lane == l) nabs = cnt;
+        if (lane == 0) scnt[l] = cnt;
     }
+    __syncthreads();
+    if (wv != 0) return;
+    const int32_t nabs = in ? scnt[lane] : 0;
     const int lc = g - c.cell_base;
     int32_t nnew = 0, N = 0, M = 0, ns = 0;
     if (in) {
@@ -1716,7 +1728,11 @@ static void step_impl(duwp_ctx *ctx)
     cl.fix_nx = ctx->fix_buf[p ^ 1];
     {
         Mark m(ctx, "cellstate");
-        hipLaunchKernelGGL(k_cellstate, dim3((G + 255) / 256), dim3(256), 0, st, ctx->d_cases, cl, ctx->off[p],
+        // 64 cells per block; enough waves in all (>= 8192) to count absorbed
+        // particles of large cells at full occupancy, at most 16 per block
+        const int cblk = (G + WAVE - 1) / WAVE;
+        const int cw = std::max(1, std::min(16, (8192 + cblk - 1) / cblk));
+        hipLaunchKernelGGL(k_cellstate, dim3(cblk), dim3(WAVE * cw), 0, st, ctx->d_cases, cl, ctx->off[p],
                            ctx->d_step, G, ctx->d_err, ctx->d_nout, ctx->d_ninj);
     }
     {
