@@ -953,27 +953,45 @@ __device__ __forceinline__ int block_stable_rank(int key, int *binbase, int (*wc
     return r;
 }
 
-// 5b. One block per case: entrants in (side, slot) order, with their rank among
-// entrants of the same destination cell.  Only the compacted entrants of each
-// candidate chunk are visited: a prefix over the chunk counts maps the e-th
-// entrant of a side to its chunk.
+// 5b. Entrants in (side, slot) order, with their rank among entrants of the
+// same destination cell.  Only the compacted entrants of each candidate chunk
+// are visited: a prefix over the chunk counts maps the e-th entrant of a side to
+// its chunk.  A case of more than NBI cells has its sides ranked by two blocks:
+// each side's entrants then land in that side's own bins (one landing in the
+// other side's bins has crossed more than the sort window and is reported), and
+// side 1's entrants follow side 0's.  An entrant that is reported keeps its place
+// with destination -1 and is not scattered.
 template <typename T>
 __global__ void __launch_bounds__(1024) k_inject_rank(const DCase *__restrict__ cases, Cells cl, Inj<T> inj,
-                                                     int64_t *d_ninj, int32_t *err)
+                                                      int64_t *d_ninj, int32_t *err)
 {
     constexpr int MAXCH = 2048;
     __shared__ int binbase[NBI];
     __shared__ int wcnt[16][NBI];
     __shared__ int pref[MAXCH + 1];
+    __shared__ int red[16];
     const int k = blockIdx.x;
     const DCase &c = cases[k];
     const int C = c.ncells;
     const int lane = lane_id();
+    const bool split = C > NBI;
+    if (!split && blockIdx.y == 1) return;
+    const int s0 = split ? (int)blockIdx.y : 0, s1 = split ? s0 + 1 : 2;
     for (int t = threadIdx.x; t < NBI; t += blockDim.x) binbase[t] = 0;
     for (int t = threadIdx.x; t < 16 * NBI; t += blockDim.x) (&wcnt[0][0])[t] = 0;
-    __syncthreads();
     int64_t count = 0;
-    for (int side = 0; side < 2; ++side) {
+    if (s0 == 1) {
+        // side 1 follows the entrants of side 0: the sum of its chunk counts
+        const int64_t nch0 = (inj.ncand[2 * k] + 255) / 256;
+        int sum = 0;
+        for (int64_t i = threadIdx.x; i < nch0; i += blockDim.x) sum += inj.cchunk[c.chunk_base[0] + i];
+        sum = wave_sum_i(sum);
+        if (lane == 0) red[threadIdx.x >> 6] = sum;
+        __syncthreads();
+        for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) count += red[w2];
+    }
+    __syncthreads();
+    for (int side = s0; side < s1; ++side) {
         const int64_t n = inj.ncand[2 * k + side];
         const int64_t cb = c.cand_base[side];
         const int64_t nch = (n + 255) / 256;
@@ -1012,17 +1030,22 @@ __global__ void __launch_bounds__(1024) k_inject_rank(const DCase *__restrict__ 
                     slc = cb + (ch0 + lo) * 256 + (e - pref[lo]);
                     d = inj.cdest[slc];
                     slot = inj_slot(d, C);
+                    if (slot >= 0 && split && (slot <= KWIN ? 0 : 1) != side) slot = -1;
                     if (slot < 0) atomicOr(err, ERR_RANGE);
                 }
                 const int r = block_stable_rank<NBI>(slot, binbase, wcnt);
-                if (slot >= 0) {
+                if (e < E) {
                     const int64_t pos = count + e;
                     if (pos < c.inj_cap) {
                         const int64_t sl = c.inj_base + pos;
-                        inj.x[sl] = inj.cx[slc]; inj.u[sl] = inj.cu[slc];
-                        inj.v[sl] = inj.cv[slc]; inj.w[sl] = inj.cw[slc];
-                        inj.dest[sl] = c.cell_base + d;
-                        inj.rank[sl] = r;
+                        if (slot >= 0) {
+                            inj.x[sl] = inj.cx[slc]; inj.u[sl] = inj.cu[slc];
+                            inj.v[sl] = inj.cv[slc]; inj.w[sl] = inj.cw[slc];
+                            inj.dest[sl] = c.cell_base + d;
+                            inj.rank[sl] = r;
+                        } else {
+                            inj.dest[sl] = -1;
+                        }
                     } else {
                         atomicOr(err, ERR_CAPACITY);
                     }
@@ -1034,11 +1057,12 @@ __global__ void __launch_bounds__(1024) k_inject_rank(const DCase *__restrict__ 
         }
         if (threadIdx.x == 0) d_ninj[2 * k + side] = nside;
     }
+    // entrant counts of the bins of the sides ranked here
     for (int t = threadIdx.x; t < NBI; t += blockDim.x) {
         const int d = inj_cell(t, C);
-        if (d >= 0) cl.inj_cnt[c.cell_base + d] = binbase[t];
+        if (d >= 0 && (!split || (t <= KWIN ? 0 : 1) == s0)) cl.inj_cnt[c.cell_base + d] = binbase[t];
     }
-    if (threadIdx.x == 0) inj.count[k] = (int32_t)min(count, c.inj_cap);
+    if (threadIdx.x == 0 && s1 == 2) inj.count[k] = (int32_t)min(count, c.inj_cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -1152,13 +1176,15 @@ __device__ __forceinline__ void scatter_entrants(const DCase &c, const Cells &cl
         if (i < n) {
             const int64_t sl = c.inj_base + i;
             const int d = inj.dest[sl];
-            const int64_t pos = cl.inj_start[d] + inj.rank[sl];
-            const T x = inj.x[sl], u = inj.u[sl];
-            if (pos < cap) dst[pos] = P4<T>{x, u, inj.v[sl], inj.w[sl]};
-            bool farp = false;
-            const int hb = flight_bin<T>(c, d - c.cell_base, x, u, &farp);
-            if (hb >= 0) key = d * NBIN + hb;
-            if (farp) cl.fix_nx[d] = 1;
+            if (d >= 0) {      // -1: an entrant reported out of range
+                const int64_t pos = cl.inj_start[d] + inj.rank[sl];
+                const T x = inj.x[sl], u = inj.u[sl];
+                if (pos < cap) dst[pos] = P4<T>{x, u, inj.v[sl], inj.w[sl]};
+                bool farp = false;
+                const int hb = flight_bin<T>(c, d - c.cell_base, x, u, &farp);
+                if (hb >= 0) key = d * NBIN + hb;
+                if (farp) cl.fix_nx[d] = 1;
+            }
         }
         uint64_t rem = __ballot(key >= 0);
         while (rem) {
@@ -1761,7 +1787,7 @@ static void step_impl(duwp_ctx *ctx)
             hipLaunchKernelGGL(k_inject_gen<T>, dim3(ctx->inj_blocks, 2 * ctx->ncases), dim3(256), 0, s2,
                                ctx->d_cases, inj, ctx->d_step, ctx->d_err);
         // 1024 threads: a side's entrants in few rounds (each round waits on loads)
-        hipLaunchKernelGGL(k_inject_rank<T>, dim3(ctx->ncases), dim3(1024), 0, s2, ctx->d_cases, cl, inj,
+        hipLaunchKernelGGL(k_inject_rank<T>, dim3(ctx->ncases, 2), dim3(1024), 0, s2, ctx->d_cases, cl, inj,
                            ctx->d_ninj, ctx->d_err);
     }
     {

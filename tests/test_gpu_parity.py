@@ -380,3 +380,17 @@ def test_far_move_is_reported():
         g.step(1)
     assert e.value.status == -6
     g.close()
+
+
+def test_entrants_beyond_the_window_are_reported():
+    """A reservoir whose entrants cross some 30 cells in one step: every such entrant
+    is reported as DUWP_ERANGE and left out (its slot is marked, nothing is placed
+    from it), as are the interior particles that move as far."""
+    c = I.argon_shock(3.0, 60, 60 * 20.0, 2e4, name="fast_reservoir")
+    c.u_L = 30.0 * c.dx / c.dt
+    g = duwp.Sim(c, seed=1, precision=duwp.FP64)
+    _say("fast reservoir")
+    with pytest.raises(duwp.DuwpError) as e:
+        g.step(2)
+    assert e.value.status == -6
+    g.close()
