@@ -38,8 +38,8 @@ typedef enum {
     DUWP_EINVAL = -1,     /* bad argument or case description */
     DUWP_ENOMEM = -2,     /* device allocation failed */
     DUWP_EDEVICE = -3,    /* a HIP call failed */
-    DUWP_ECAPACITY = -4,  /* particle, staging or injection capacity exceeded during a step, or 2^30
-                             (FP32; 2^29 FP64) particles or more in one cell or 33 consecutive cells */
+    DUWP_ECAPACITY = -4,  /* particle, staging or injection capacity exceeded during a step, or 2^28
+                             (FP32; 2^27 FP64) particles or more in one cell or 33 consecutive cells */
     DUWP_ESTATE = -5,     /* non-finite cell state detected */
     DUWP_ERANGE = -6      /* a particle moved more than DUWP_SORT_WINDOW cells in one step */
 } duwp_status;
