@@ -701,8 +701,9 @@ __global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__res
     __shared__ int ovf[2];           // by chunk parity
     __shared__ int rflag[NW];        // per-wave "still waiting" flags of a round
     const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
-    const uint32_t step = *d_step;
     const int nbig = *cl.nbig;
+    if ((int)blockIdx.x >= nbig) return;   // no cell for this block (often none at all)
+    const uint32_t step = *d_step;
     for (int s = t; s < SLOTS; s += B) { hkey[s] = 0xffffffffu; hcnt[s] = 0; }
     // barrier over LDS only (the rounds exchange nothing else through memory),
     // true when any thread of the block passes v
@@ -1075,50 +1076,65 @@ __global__ void __launch_bounds__(512) k_hist_build(const DCase *__restrict__ ca
 {
     // Recount of the destination histogram of a cell from its particles: every
     // cell of a loaded canonical state (all = 1), or the intermediate segments
-    // of the cells flagged during the step (all = 0).
+    // of the cells flagged during the step (all = 0, usually none).  A block
+    // takes groups of 64 consecutive cells: one wave reads their flags, and the
+    // block recounts the flagged ones.
     constexpr int IT = 4;
     __shared__ int h[NBIN];
-    for (int gi = blockIdx.x; gi < G; gi += gridDim.x) {
-        const int g = cl.order[gi];
-        if (!all && !cl.fix[g]) continue;
-        const DCase &c = cases[cl.cell_case[g]];
-        const int lc = g - c.cell_base;
-        for (int t = threadIdx.x; t < NBIN; t += blockDim.x) h[t] = 0;
-        __syncthreads();
-        int64_t b;
-        P4<T> *sg;
-        int32_t n;
-        if (all) {
-            sg = src;
-            b = off[g];
-            n = (int32_t)(off[g + 1] - b);
-        } else {
-            sg = segment(cl, g, src, stg, b);
-            n = (int32_t)min((int64_t)cl.n_int[g], cap - b);
+    __shared__ int flagged[WAVE];
+    __shared__ int nfl;
+    for (int g0 = blockIdx.x * WAVE; g0 < G; g0 += gridDim.x * WAVE) {
+        if (threadIdx.x < WAVE) {
+            const int gg = g0 + (int)threadIdx.x;
+            const bool f = gg < G && (all || cl.fix[gg]);
+            const uint64_t m = __ballot(f);
+            if (f) flagged[lane_rank_lt(m)] = gg;
+            if (threadIdx.x == 0) nfl = __popcll(m);
         }
-        bool far = false;
-        for (int i0 = 0; i0 < n; i0 += IT * blockDim.x) {
-            T x[IT], u[IT];
+        __syncthreads();
+        const int nf = nfl;
+        for (int qf = 0; qf < nf; ++qf) {
+            const int g = flagged[qf];
+            const DCase &c = cases[cl.cell_case[g]];
+            const int lc = g - c.cell_base;
+            for (int t = threadIdx.x; t < NBIN; t += blockDim.x) h[t] = 0;
+            __syncthreads();
+            int64_t b;
+            P4<T> *sg;
+            int32_t n;
+            if (all) {
+                sg = src;
+                b = off[g];
+                n = (int32_t)(off[g + 1] - b);
+            } else {
+                sg = segment(cl, g, src, stg, b);
+                n = (int32_t)min((int64_t)cl.n_int[g], cap - b);
+            }
+            bool far = false;
+            for (int i0 = 0; i0 < n; i0 += IT * blockDim.x) {
+                T x[IT], u[IT];
 #pragma unroll
-            for (int j = 0; j < IT; ++j) {
-                const int i = i0 + j * blockDim.x + threadIdx.x;
-                x[j] = 0; u[j] = 0;
-                if (i < n) {
-                    const P4<T> r = sg[b + i];
-                    x[j] = r.x; u[j] = r.u;
+                for (int j = 0; j < IT; ++j) {
+                    const int i = i0 + j * blockDim.x + threadIdx.x;
+                    x[j] = 0; u[j] = 0;
+                    if (i < n) {
+                        const P4<T> r = sg[b + i];
+                        x[j] = r.x; u[j] = r.u;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < IT; ++j) {
+                    const int i = i0 + j * blockDim.x + threadIdx.x;
+                    if (i >= n) continue;
+                    const int hb = flight_bin<T>(c, lc, x[j], u[j], &far);
+                    if (hb >= 0) atomicAdd(&h[hb], 1);
                 }
             }
-#pragma unroll
-            for (int j = 0; j < IT; ++j) {
-                const int i = i0 + j * blockDim.x + threadIdx.x;
-                if (i >= n) continue;
-                const int hb = flight_bin<T>(c, lc, x[j], u[j], &far);
-                if (hb >= 0) atomicAdd(&h[hb], 1);
-            }
+            __syncthreads();
+            for (int t = threadIdx.x; t < NBIN; t += blockDim.x) cl.hist[(int64_t)g * NBIN + t] = h[t];
+            if (threadIdx.x == 0) cl.fix[g] = 0;
+            __syncthreads();
         }
-        __syncthreads();
-        for (int t = threadIdx.x; t < NBIN; t += blockDim.x) cl.hist[(int64_t)g * NBIN + t] = h[t];
-        if (threadIdx.x == 0) cl.fix[g] = 0;
         __syncthreads();
     }
 }
@@ -1816,8 +1832,8 @@ static void step_impl(duwp_ctx *ctx)
     if (fork) (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
     {
         Mark m(ctx, "hist_fix");
-        hipLaunchKernelGGL(k_hist_build<T>, dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg, ctx->off[p], G,
-                           ctx->cap, 0);
+        hipLaunchKernelGGL(k_hist_build<T>, dim3((G + WAVE - 1) / WAVE), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
+                           ctx->off[p], G, ctx->cap, 0);
     }
     {
         Mark m(ctx, "count_new");
@@ -1875,8 +1891,8 @@ static void reload_impl(duwp_ctx *ctx)
     P4<T> *const a = recs<T>(ctx->A[p]);
     hipLaunchKernelGGL(k_moments<T>, dim3(G), dim3(ctx->block_cells), 0, ctx->stream, ctx->d_cases, cl, a,
                        ctx->off[p], G, ctx->d_err);
-    hipLaunchKernelGGL(k_hist_build<T>, dim3(G), dim3(ctx->block_cells), 0, ctx->stream, ctx->d_cases, cl, a, a,
-                       ctx->off[p], G, ctx->cap, 1);
+    hipLaunchKernelGGL(k_hist_build<T>, dim3((G + WAVE - 1) / WAVE), dim3(ctx->block_cells), 0, ctx->stream,
+                       ctx->d_cases, cl, a, a, ctx->off[p], G, ctx->cap, 1);
 }
 
 // Particle moments and destination histogram of a loaded canonical state.
