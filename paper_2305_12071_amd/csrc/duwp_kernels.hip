@@ -1139,42 +1139,87 @@ __global__ void __launch_bounds__(512) k_hist_build(const DCase *__restrict__ ca
     }
 }
 
-// 7. particles arriving in each destination cell (one wave per cell, lane = source offset)
-__global__ void __launch_bounds__(256) k_count_new(Cells cl, int G)
+// Destination cells d of a block: [d0, d0 + nd), nd <= CN_D (fewer when the
+// grid would otherwise be small); the histogram rows of their sources,
+// [d0 - KWIN, d0 + nd + KWIN), are contiguous in memory and are read into LDS
+// once (a destination's 33 sources are 33 different rows).
+constexpr int CN_D = 64;
+constexpr int CN_ROWS = CN_D + 2 * KWIN;
+
+__device__ __forceinline__ void load_hist_tile(const Cells &cl, int d0, int nd, int G, int *tile)
 {
-    const int lane = lane_id();
-    const int d = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (d >= G) return;
-    int v = 0;
-    if (lane < NBIN) {
-        const int src = d + lane - KWIN;                 // bin of src pointing at d: d - src + KWIN
-        if (src >= 0 && src < G) v = cl.hist[(int64_t)src * NBIN + (2 * KWIN - lane)];
+    const int s0 = d0 - KWIN;
+    for (int t = threadIdx.x; t < (nd + 2 * KWIN) * NBIN; t += blockDim.x) {
+        const int src = s0 + t / NBIN;
+        tile[t] = (src >= 0 && src < G) ? cl.hist[(int64_t)s0 * NBIN + t] : 0;
     }
-    v = wave_sum_i(v);
-    if (lane == 0) cl.cnt_new[d] = v + cl.inj_cnt[d];
+}
+
+// 7. particles arriving in each destination cell (a wave per destination, lane =
+// source offset; the bin of source d + l - KWIN pointing at d is 2 KWIN - l)
+__global__ void __launch_bounds__(256) k_count_new(Cells cl, int G, int nd)
+{
+    // nd > 4: the rows through LDS; nd = 4 (small grids): read in place
+    __shared__ int tile[CN_ROWS * NBIN];
+    const int d0 = blockIdx.x * nd;
+    const bool tiled = nd > 4;
+    if (tiled) load_hist_tile(cl, d0, nd, G, tile);
+    __syncthreads();
+    const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int dd = w; dd < nd && d0 + dd < G; dd += nw) {
+        const int d = d0 + dd;
+        const int src = d + lane - KWIN;
+        int v = 0;
+        if (lane < NBIN && src >= 0 && src < G)
+            v = tiled ? tile[(dd + lane) * NBIN + (2 * KWIN - lane)]
+                      : cl.hist[(int64_t)src * NBIN + (2 * KWIN - lane)];
+        v = wave_sum_i(v);
+        if (lane == 0) cl.cnt_new[d] = v + cl.inj_cnt[d];
+    }
 }
 
 // 9. start of each (source cell, destination) group inside its destination segment,
-// in source-cell order; entrants follow the cell-sourced particles.  One wave per
-// destination cell: lane l is source d + l - KWIN, an exclusive prefix gives the bases.
-__global__ void __launch_bounds__(256) k_bases(Cells cl, const int64_t *__restrict__ off_new, int G)
+// in source-cell order; entrants follow the cell-sourced particles.  A wave per
+// destination cell: lane l is source d + l - KWIN, an exclusive prefix gives the
+// bases, which replace the counts (the block writes back the entries of its
+// destinations).
+__global__ void __launch_bounds__(256) k_bases(Cells cl, const int64_t *__restrict__ off_new, int G, int nd)
 {
-    const int lane = lane_id();
-    const int d = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (d >= G) return;
-    const int src = d + lane - KWIN;
-    const bool ok = lane < NBIN && src >= 0 && src < G;
-    const int64_t idx = (int64_t)src * NBIN + (2 * KWIN - lane);
-    const int h = ok ? cl.hist[idx] : 0;
-    int incl = h;
+    // nd > 4: the rows through LDS; nd = 4 (small grids): read and written in place
+    __shared__ int tile[CN_ROWS * NBIN];
+    const int d0 = blockIdx.x * nd;
+    const bool tiled = nd > 4;
+    if (tiled) load_hist_tile(cl, d0, nd, G, tile);
+    __syncthreads();
+    const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int dd = w; dd < nd && d0 + dd < G; dd += nw) {
+        const int d = d0 + dd;
+        const int src = d + lane - KWIN;
+        const bool ok = lane < NBIN && src >= 0 && src < G;
+        const int ti = (dd + lane) * NBIN + (2 * KWIN - lane);
+        const int64_t gi = (int64_t)src * NBIN + (2 * KWIN - lane);
+        const int h = ok ? (tiled ? tile[ti] : cl.hist[gi]) : 0;
+        int incl = h;
 #pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        const int t = __shfl_up(incl, o, WAVE);
-        if (lane >= o) incl += t;
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const int t = __shfl_up(incl, o, WAVE);
+            if (lane >= o) incl += t;
+        }
+        if (ok) {
+            if (tiled) tile[ti] = incl - h;
+            else cl.hist[gi] = incl - h;
+        }
+        const int run = __shfl(incl, WAVE - 1, WAVE);
+        if (lane == 0) cl.inj_start[d] = off_new[d] + run;
     }
-    if (ok) cl.hist[idx] = incl - h;
-    const int run = __shfl(incl, WAVE - 1, WAVE);
-    if (lane == 0) cl.inj_start[d] = off_new[d] + run;
+    if (!tiled) return;
+    __syncthreads();
+    const int s0 = d0 - KWIN, dend = min(d0 + nd, G);
+    for (int t = threadIdx.x; t < (nd + 2 * KWIN) * NBIN; t += blockDim.x) {
+        const int src = s0 + t / NBIN;
+        const int d = src + t % NBIN - KWIN;
+        if (src >= 0 && src < G && d >= d0 && d < dend) cl.hist[(int64_t)s0 * NBIN + t] = tile[t];
+    }
 }
 
 // Entrants go after the cell-sourced particles of their destination cell; their
@@ -1830,6 +1875,9 @@ static void step_impl(duwp_ctx *ctx)
                            by_cell);
     }
     if (fork) (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
+    // destinations per block of the two histogram passes: 4 to 64, so that their
+    // grids keep about 1000 blocks or more
+    const int nd = std::max(4, std::min(CN_D, G / 1024 / 4 * 4));
     {
         Mark m(ctx, "hist_fix");
         hipLaunchKernelGGL(k_hist_build<T>, dim3((G + WAVE - 1) / WAVE), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
@@ -1837,7 +1885,7 @@ static void step_impl(duwp_ctx *ctx)
     }
     {
         Mark m(ctx, "count_new");
-        hipLaunchKernelGGL(k_count_new, dim3((G + 3) / 4), dim3(256), 0, st, cl, G);
+        hipLaunchKernelGGL(k_count_new, dim3((G + nd - 1) / nd), dim3(256), 0, st, cl, G, nd);
     }
     {
         Mark m(ctx, "scan_offsets");
@@ -1845,7 +1893,7 @@ static void step_impl(duwp_ctx *ctx)
     }
     {
         Mark m(ctx, "bases");
-        hipLaunchKernelGGL(k_bases, dim3((G + 3) / 4), dim3(256), 0, st, cl, ctx->off[p ^ 1], G);
+        hipLaunchKernelGGL(k_bases, dim3((G + nd - 1) / nd), dim3(256), 0, st, cl, ctx->off[p ^ 1], G, nd);
     }
     {
         Mark m(ctx, "scatter");

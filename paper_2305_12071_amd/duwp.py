@@ -180,7 +180,10 @@ class Sim:
             self.ptr = C.c_void_p()
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:       # interpreter shutdown: the library may be gone already
+            pass
 
     def step(self, n: int = 1) -> None:
         _check(lib().duwp_step(self.ptr, n), "duwp_step")
