@@ -401,6 +401,11 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
             ncu = 256;
         ctx->coll_blocks = 16 * ncu;   // work items: many waves in flight hide each chunk's load chain
         ctx->big_blocks = ncu;
+        // the scatter visits cells largest first only when its grid runs in
+        // few rounds of resident blocks (the tail then matters); with many
+        // rounds the order lookup would only lengthen each block's load chain
+        const int64_t resident = (int64_t)duwp::scatter_blocks_per_cu(ctx->precision, ctx->block_cells) * ncu;
+        ctx->scat_by_order = G < 16 * resident ? 1 : 0;
     }
     duwp_status s = alloc_all(ctx);
     if (s == DUWP_OK) s = upload_initial(ctx);

@@ -68,6 +68,7 @@ struct duwp_ctx {
     int64_t items_cap = 0;
     int coll_blocks = 0;
     int big_blocks = 0;            // grid of the block-per-cell collision kernel
+    int scat_by_order = 1;         // scatter blocks take cells largest first (few rounds of blocks)
     double *diag = nullptr;        // [G*5] on-demand cell diagnostics
     int64_t *d_psteps = nullptr;   // particle-steps since init or the last reset
 
@@ -80,6 +81,8 @@ struct duwp_ctx {
 namespace duwp {
 // Launch the kernels of one step on ctx->stream (defined with the kernels).
 void enqueue_step(duwp_ctx *ctx);
+// Scatter blocks that fit on one compute unit at once (for this precision and block size).
+int scatter_blocks_per_cu(int precision, int bc);
 // Recompute the particle moments of the current canonical state (no averaging).
 void enqueue_moments(duwp_ctx *ctx);
 // Normal stress and heat flux of cells [g0, g1) of the current state into out[G*5].

@@ -1287,9 +1287,13 @@ constexpr int SCAT_ITN = 4, SCAT_WN = 1;
 template <typename T, int MAXW, int IT>
 __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1 : SCAT_WN)) k_scatter(const DCase *__restrict__ cases, Cells cl, P4<T> *src,
                                                  P4<T> *stg, P4<T> *dst, const int64_t *__restrict__ off_new,
-                                                 int G, int64_t cap, int32_t *err, int64_t *d_nout)
+                                                 int G, int64_t cap, int32_t *err, int64_t *d_nout,
+                                                 int by_order)
 {
-    // One block per cell (grid = G, visiting order cl.order).  Besides placing
+    // One block per cell (grid = G), in visiting order cl.order when by_order
+    // is set (largest cells first: worth it when the grid runs in few rounds
+    // of resident blocks), else in index order, which spares the first load
+    // of the chain before a block's particle loads.  Besides placing
     // each particle, the scatter predicts where it goes next step (free flight
     // from its new place with its current velocity) and counts the next step's
     // destination histogram of its new cell in hn[] (new cell relative to this
@@ -1318,7 +1322,7 @@ __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1
     for (int t = threadIdx.x; t < (NBIN * NBIN + 3) / 4; t += blockDim.x)
         reinterpret_cast<int4 *>(hn)[t] = int4{0, 0, 0, 0};
     if (threadIdx.x == 0) nout = 0;
-    const int g = cl.order[blockIdx.x];
+    const int g = by_order ? cl.order[blockIdx.x] : (int)blockIdx.x;
     const int k = cl.cell_case[g];
     const DCase &c = cases[k];
     const int lc = g - c.cell_base;
@@ -1899,10 +1903,10 @@ static void step_impl(duwp_ctx *ctx)
         Mark m(ctx, "scatter");
         if (bc == WAVE)
             hipLaunchKernelGGL((k_scatter<T, 1, SCAT_IT1>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
-                               dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout);
+                               dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout, ctx->scat_by_order);
         else
             hipLaunchKernelGGL((k_scatter<T, 8, SCAT_ITN>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
-                               dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout);
+                               dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout, ctx->scat_by_order);
     }
     {
         Mark m(ctx, "scatter_inj");
@@ -1914,6 +1918,19 @@ static void step_impl(duwp_ctx *ctx)
         hipLaunchKernelGGL(k_gather_moments<T>, dim3((G + 255) / 256), dim3(256), 0, st, ctx->d_cases, cl, dst,
                            ctx->off[p ^ 1], G, ctx->d_err, ctx->d_step, ctx->off[p], ctx->d_psteps);
     }
+}
+
+// Scatter blocks that fit on one compute unit at once, for this precision and block size.
+int scatter_blocks_per_cu(int precision, int bc)
+{
+    const void *f;
+    if (precision == DUWP_MIXED)
+        f = bc == WAVE ? (const void *)&k_scatter<float, 1, SCAT_IT1> : (const void *)&k_scatter<float, 8, SCAT_ITN>;
+    else
+        f = bc == WAVE ? (const void *)&k_scatter<double, 1, SCAT_IT1> : (const void *)&k_scatter<double, 8, SCAT_ITN>;
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, bc, 0) != hipSuccess || per <= 0) per = 1;
+    return per;
 }
 
 void enqueue_step(duwp_ctx *ctx)
