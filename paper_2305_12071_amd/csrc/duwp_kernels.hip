@@ -1558,7 +1558,10 @@ __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1
 // the near source cells, of farther sources if any, then the entrants; the wave
 // part's flux update (Eq. r1); running average of Psi_t; largest relative speed
 // of the collisions; finite-state check.
-// One lane per destination cell; the entrants of a cell are summed by the whole wave.
+// Two lanes per destination cell: the even one owns the cell, each computes
+// one of its two face fluxes (the odd lane's goes to the even one), so the
+// transcendental chains of a cell's two faces run side by side.  The entrants
+// of a cell are summed by the whole wave.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict__ cases, Cells cl, const P4<T> *dst,
@@ -1567,7 +1570,9 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
                                                         int64_t *d_psteps)
 {
     const int lane = lane_id();
-    const int d = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * WAVE + lane;
+    constexpr int CPW = WAVE / 2;    // cells per wave
+    const int d0 = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * CPW;
+    const int d = d0 + (lane >> 1), h = lane & 1;
     // the step's close: particle-steps (particles alive at its start), step
     // index, and the big-cell list emptied for the next step
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1576,8 +1581,8 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
         *cl.nbig = 0;
         *cl.ntouch = 0;
     }
-    if ((d - lane) >= G) return;
-    const bool in = d < G;
+    if (d0 >= G) return;
+    const bool in = d < G && h == 0;
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     int64_t ib = 0, ie = 0;
     if (in) {
@@ -1619,21 +1624,22 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
             if (lane == l) s[q] += a[q];
         }
     }
-    if (!in) return;
-    const DCase &c = cases[cl.cell_case[d]];
     // wave part: the update with the NS flux of the start-of-step total state
     // (Eq. r1; the states cl.wt are those of the step's start), after the
-    // absorbed and resampled moments
+    // absorbed and resampled moments.  Lane h of a cell takes its face lc + h.
+    const DCase &c = cases[cl.cell_case[min(d, G - 1)]];
+    double F[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (d < G) case_face_flux(c, cl, d - c.cell_base + h, F);
+    double Fr[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Fr[q] = __shfl_down(F[q], 1, WAVE);
+    if (!in) return;
     double pw[5];
     {
-        const int lc = d - c.cell_base;
-        double Fl[5], Fr[5];
-        case_face_flux(c, cl, lc, Fl);
-        case_face_flux(c, cl, lc + 1, Fr);
         const double r = c.dt / c.dx;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            pw[q] = cl.psi_w[(int64_t)d * 5 + q] - r * (Fr[q] - Fl[q]);
+            pw[q] = cl.psi_w[(int64_t)d * 5 + q] - r * (Fr[q] - F[q]);
             cl.psi_w[(int64_t)d * 5 + q] = pw[q];
         }
     }
@@ -1915,7 +1921,7 @@ static void step_impl(duwp_ctx *ctx)
     }
     {
         Mark m(ctx, "gather_moments");
-        hipLaunchKernelGGL(k_gather_moments<T>, dim3((G + 255) / 256), dim3(256), 0, st, ctx->d_cases, cl, dst,
+        hipLaunchKernelGGL(k_gather_moments<T>, dim3((G + 127) / 128), dim3(256), 0, st, ctx->d_cases, cl, dst,
                            ctx->off[p ^ 1], G, ctx->d_err, ctx->d_step, ctx->off[p], ctx->d_psteps);
     }
 }
