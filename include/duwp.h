@@ -156,7 +156,10 @@ duwp_status duwp_get_state(duwp_ctx *ctx, int32_t case_id, duwp_state *st);
 
 /* Replace one case's state (and the context's step index) from host buffers.  The
  * particle moments are recomputed; the case keeps its place among the others.
- * DUWP_EINVAL if offsets are not monotone, DUWP_ECAPACITY if it does not fit. */
+ * With the case's particle count unchanged only its records move (host work in
+ * proportion to the case); otherwise the whole canonical array makes a round trip
+ * through the host.  DUWP_EINVAL if offsets are not monotone, DUWP_ECAPACITY if it
+ * does not fit. */
 duwp_status duwp_set_state(duwp_ctx *ctx, int32_t case_id, const duwp_state *st);
 
 /* Average device duration in ms of each kernel of the step over nsteps eager steps

@@ -607,50 +607,68 @@ duwp_status duwp_set_state(duwp_ctx *ctx, int32_t case_id, const duwp_state *st)
     const int64_t b = off[d.cell_base], nold = off[d.cell_base + d.ncells] - b;
     const int64_t total = off[G] - nold + st->n_particles;
     if (total > ctx->cap) return DUWP_ECAPACITY;
-    // rebuild the whole canonical array on the host: earlier cases, this case, later cases
     const bool mixed = ctx->precision == DUWP_MIXED;
     const size_t es = mixed ? 4 : 8, rs = 4 * es;   // element and record sizes
-    std::vector<char> hh(rs * (size_t)total);
-    {
-        std::vector<char> old(rs * (size_t)off[G]);
-        if (off[G]) HIP_OK(hipMemcpyAsync(old.data(), ctx->A[p], old.size(), hipMemcpyDeviceToHost, ctx->stream));
-        HIP_OK(hipStreamSynchronize(ctx->stream));
-        std::memcpy(hh.data(), old.data(), rs * (size_t)b);
-        std::memcpy(hh.data() + rs * (size_t)(b + st->n_particles), old.data() + rs * (size_t)(b + nold),
-                    rs * (size_t)(off[G] - b - nold));
-    }
-    const double *srcv[4] = {st->x, st->u, st->v, st->w};
-    for (int i = 0; i < d.ncells; ++i)
-        for (int64_t q = st->off[i]; q < st->off[i + 1]; ++q)
-            for (int a = 0; a < 4; ++a) {
-                double val = srcv[a][q];
-                char *slot = hh.data() + rs * (size_t)(b + q) + es * (size_t)a;
-                if (mixed) {
-                    float f;
-                    if (a == 0) {
-                        double s = (val - d.x_lo) / d.dx - (double)i;
-                        f = (float)s;
-                        if (f < 0.0f) f = 0.0f;
-                        if (f >= 1.0f) f = 0.99999994f;
+    // the case's records in device layout, record q at out + rs q
+    auto fill = [&](char *out) {
+        const double *srcv[4] = {st->x, st->u, st->v, st->w};
+        for (int i = 0; i < d.ncells; ++i)
+            for (int64_t q = st->off[i]; q < st->off[i + 1]; ++q)
+                for (int a = 0; a < 4; ++a) {
+                    double val = srcv[a][q];
+                    char *slot = out + rs * (size_t)q + es * (size_t)a;
+                    if (mixed) {
+                        float f;
+                        if (a == 0) {
+                            double sv = (val - d.x_lo) / d.dx - (double)i;
+                            f = (float)sv;
+                            if (f < 0.0f) f = 0.0f;
+                            if (f >= 1.0f) f = 0.99999994f;
+                        } else {
+                            f = (float)val;
+                        }
+                        std::memcpy(slot, &f, 4);
                     } else {
-                        f = (float)val;
+                        std::memcpy(slot, &val, 8);
                     }
-                    std::memcpy(slot, &f, 4);
-                } else {
-                    std::memcpy(slot, &val, 8);
                 }
-            }
-    if (total) HIP_OK(hipMemcpyAsync(ctx->A[p], hh.data(), hh.size(), hipMemcpyHostToDevice, ctx->stream));
-    HIP_OK(hipStreamSynchronize(ctx->stream));
-    std::vector<int64_t> noff((size_t)G + 1);
-    const int64_t delta = st->n_particles - nold;
-    for (int g = 0; g <= G; ++g) {
-        if (g < d.cell_base) noff[g] = off[g];
-        else if (g <= d.cell_base + d.ncells) noff[g] = b + st->off[g - d.cell_base];
-        else noff[g] = off[g] + delta;
-    }
+    };
     hipStream_t s = ctx->stream;
-    HIP_OK(hipMemcpyAsync(ctx->off[p], noff.data(), 8 * noff.size(), hipMemcpyHostToDevice, s));
+    if (st->n_particles == nold) {
+        // same particle count: the case's records and cell offsets are replaced
+        // in place; the other cases are not touched
+        std::vector<char> hh(rs * (size_t)nold);
+        fill(hh.data());
+        if (nold)
+            HIP_OK(hipMemcpyAsync((char *)ctx->A[p] + rs * (size_t)b, hh.data(), hh.size(), hipMemcpyHostToDevice, s));
+        std::vector<int64_t> coff((size_t)d.ncells + 1);
+        for (int i = 0; i <= d.ncells; ++i) coff[i] = b + st->off[i];
+        HIP_OK(hipMemcpyAsync(ctx->off[p] + d.cell_base, coff.data(), 8 * coff.size(), hipMemcpyHostToDevice, s));
+        HIP_OK(hipStreamSynchronize(s));
+    } else {
+        // rebuild the whole canonical array on the host: earlier cases, this case, later cases
+        std::vector<char> hh(rs * (size_t)total);
+        {
+            std::vector<char> old(rs * (size_t)off[G]);
+            if (off[G]) HIP_OK(hipMemcpyAsync(old.data(), ctx->A[p], old.size(), hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+            std::memcpy(hh.data(), old.data(), rs * (size_t)b);
+            std::memcpy(hh.data() + rs * (size_t)(b + st->n_particles), old.data() + rs * (size_t)(b + nold),
+                        rs * (size_t)(off[G] - b - nold));
+        }
+        fill(hh.data() + rs * (size_t)b);
+        if (total) HIP_OK(hipMemcpyAsync(ctx->A[p], hh.data(), hh.size(), hipMemcpyHostToDevice, s));
+        HIP_OK(hipStreamSynchronize(s));
+        std::vector<int64_t> noff((size_t)G + 1);
+        const int64_t delta = st->n_particles - nold;
+        for (int g = 0; g <= G; ++g) {
+            if (g < d.cell_base) noff[g] = off[g];
+            else if (g <= d.cell_base + d.ncells) noff[g] = b + st->off[g - d.cell_base];
+            else noff[g] = off[g] + delta;
+        }
+        HIP_OK(hipMemcpyAsync(ctx->off[p], noff.data(), 8 * noff.size(), hipMemcpyHostToDevice, s));
+        HIP_OK(hipStreamSynchronize(s));
+    }
     HIP_OK(hipMemcpyAsync(ctx->cl.psi_w + 5 * (size_t)d.cell_base, st->psi_w, 8 * 5 * (size_t)d.ncells,
                           hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(ctx->cl.cr_max + d.cell_base, st->cr_max, 8 * (size_t)d.ncells, hipMemcpyHostToDevice, s));

@@ -201,6 +201,36 @@ def test_resume_from_checkpoint_is_bitwise_identical():
         assert np.array_equal(sa[key], sb[key]), key
 
 
+@pytest.mark.parametrize("prec", [duwp.FP64, duwp.MIXED])
+def test_restore_in_place_equals_full_rebuild(prec):
+    # a restore that keeps a case's particle count replaces its records in
+    # place; one that changes counts rebuilds the whole array: both must leave
+    # the same state behind
+    cases = [CASES["mach3"], CASES["sod_kn1e-4"], CASES["box_ragged"]]
+    _say("restore", prec)
+    a = duwp.Sim(cases, seed=6, precision=prec)
+    a.step(6)
+    states = [a.get_state(k) for k in range(3)]
+    changed = dict(states[1])
+    changed["u"] = -states[1]["u"]
+    changed["v"], changed["w"] = states[1]["w"].copy(), states[1]["v"].copy()
+    mine = [states[0], changed, states[2]]
+    b = duwp.Sim(cases, seed=6, precision=prec)
+    b.step(3)
+    assert any(b.counts(k)[0] != len(states[k]["x"]) for k in range(3))
+    for k in range(3):
+        a.set_state(mine[k], k)     # same counts: in place
+        b.set_state(mine[k], k)     # other counts: whole array
+    a.step(4)
+    b.step(4)
+    for k in range(3):
+        sa, sb = a.get_state(k), b.get_state(k)
+        for key in ("x", "u", "v", "w", "off", "psi_w", "cr_max"):
+            assert np.array_equal(sa[key], sb[key]), (k, key)
+    a.close()
+    b.close()
+
+
 def test_capacity_overflow_is_reported():
     c = I.sod_paper(1e-2)
     c.capacity = 1000      # far below the ~1.1e5 particles of the first step
