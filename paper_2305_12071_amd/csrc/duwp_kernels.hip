@@ -1143,7 +1143,7 @@ __global__ void __launch_bounds__(512) k_hist_build(const DCase *__restrict__ ca
 // grid would otherwise be small); the histogram rows of their sources,
 // [d0 - KWIN, d0 + nd + KWIN), are contiguous in memory and are read into LDS
 // once (a destination's 33 sources are 33 different rows).
-constexpr int CN_D = 64;
+constexpr int CN_D = 256;   // destinations of a block on large grids: one per thread
 constexpr int CN_ROWS = CN_D + 2 * KWIN;
 
 __device__ __forceinline__ void load_hist_tile(const Cells &cl, int d0, int nd, int G, int *tile)
@@ -1155,64 +1155,85 @@ __device__ __forceinline__ void load_hist_tile(const Cells &cl, int d0, int nd, 
     }
 }
 
-// 7. particles arriving in each destination cell (a wave per destination, lane =
-// source offset; the bin of source d + l - KWIN pointing at d is 2 KWIN - l)
+// 7. particles arriving in each destination cell: the bin of source d + l - KWIN
+// pointing at d is 2 KWIN - l.  Large grids (nd > 4): the block's rows through
+// LDS, a thread per destination summing its 33 entries; small grids (nd = 4): a
+// wave per destination, lane = source offset, rows read in place.
 __global__ void __launch_bounds__(256) k_count_new(Cells cl, int G, int nd)
 {
-    // nd > 4: the rows through LDS; nd = 4 (small grids): read in place
     __shared__ int tile[CN_ROWS * NBIN];
     const int d0 = blockIdx.x * nd;
-    const bool tiled = nd > 4;
-    if (tiled) load_hist_tile(cl, d0, nd, G, tile);
-    __syncthreads();
+    if (nd > 4) {
+        load_hist_tile(cl, d0, nd, G, tile);
+        __syncthreads();
+        const int dd = threadIdx.x, d = d0 + dd;
+        if (dd < nd && d < G) {
+            int v = 0;
+#pragma unroll
+            for (int l = 0; l < NBIN; ++l) v += tile[(dd + l) * NBIN + (2 * KWIN - l)];
+            cl.cnt_new[d] = v + cl.inj_cnt[d];
+        }
+        return;
+    }
     const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int dd = w; dd < nd && d0 + dd < G; dd += nw) {
         const int d = d0 + dd;
         const int src = d + lane - KWIN;
         int v = 0;
-        if (lane < NBIN && src >= 0 && src < G)
-            v = tiled ? tile[(dd + lane) * NBIN + (2 * KWIN - lane)]
-                      : cl.hist[(int64_t)src * NBIN + (2 * KWIN - lane)];
+        if (lane < NBIN && src >= 0 && src < G) v = cl.hist[(int64_t)src * NBIN + (2 * KWIN - lane)];
         v = wave_sum_i(v);
         if (lane == 0) cl.cnt_new[d] = v + cl.inj_cnt[d];
     }
 }
 
 // 9. start of each (source cell, destination) group inside its destination segment,
-// in source-cell order; entrants follow the cell-sourced particles.  A wave per
-// destination cell: lane l is source d + l - KWIN, an exclusive prefix gives the
-// bases, which replace the counts (the block writes back the entries of its
-// destinations).
+// in source-cell order; entrants follow the cell-sourced particles.  The
+// exclusive prefix over the sources d + l - KWIN (l = 0..32) of a destination
+// gives the bases, which replace the counts.  Large grids: a thread per
+// destination over the block's rows in LDS (the block writes back the entries
+// of its destinations); small grids: a wave per destination, lane l = source
+// d + l - KWIN, in place.
 __global__ void __launch_bounds__(256) k_bases(Cells cl, const int64_t *__restrict__ off_new, int G, int nd)
 {
-    // nd > 4: the rows through LDS; nd = 4 (small grids): read and written in place
     __shared__ int tile[CN_ROWS * NBIN];
     const int d0 = blockIdx.x * nd;
-    const bool tiled = nd > 4;
-    if (tiled) load_hist_tile(cl, d0, nd, G, tile);
-    __syncthreads();
-    const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int dd = w; dd < nd && d0 + dd < G; dd += nw) {
-        const int d = d0 + dd;
-        const int src = d + lane - KWIN;
-        const bool ok = lane < NBIN && src >= 0 && src < G;
-        const int ti = (dd + lane) * NBIN + (2 * KWIN - lane);
-        const int64_t gi = (int64_t)src * NBIN + (2 * KWIN - lane);
-        const int h = ok ? (tiled ? tile[ti] : cl.hist[gi]) : 0;
-        int incl = h;
+    if (nd <= 4) {
+        const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        for (int dd = w; dd < nd && d0 + dd < G; dd += nw) {
+            const int d = d0 + dd;
+            const int src = d + lane - KWIN;
+            const bool ok = lane < NBIN && src >= 0 && src < G;
+            const int64_t gi = (int64_t)src * NBIN + (2 * KWIN - lane);
+            const int h = ok ? cl.hist[gi] : 0;
+            int incl = h;
 #pragma unroll
-        for (int o = 1; o < WAVE; o <<= 1) {
-            const int t = __shfl_up(incl, o, WAVE);
-            if (lane >= o) incl += t;
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const int t = __shfl_up(incl, o, WAVE);
+                if (lane >= o) incl += t;
+            }
+            if (ok) cl.hist[gi] = incl - h;
+            const int run = __shfl(incl, WAVE - 1, WAVE);
+            if (lane == 0) cl.inj_start[d] = off_new[d] + run;
         }
-        if (ok) {
-            if (tiled) tile[ti] = incl - h;
-            else cl.hist[gi] = incl - h;
-        }
-        const int run = __shfl(incl, WAVE - 1, WAVE);
-        if (lane == 0) cl.inj_start[d] = off_new[d] + run;
+        return;
     }
-    if (!tiled) return;
+    load_hist_tile(cl, d0, nd, G, tile);
+    __syncthreads();
+    {
+        const int dd = threadIdx.x, d = d0 + dd;
+        if (dd < nd && d < G) {
+            // (entries of sources outside the grid are zero in the tile and stay so)
+            int run = 0;
+#pragma unroll
+            for (int l = 0; l < NBIN; ++l) {
+                const int ti = (dd + l) * NBIN + (2 * KWIN - l);
+                const int h = tile[ti];
+                tile[ti] = run;
+                run += h;
+            }
+            cl.inj_start[d] = off_new[d] + run;
+        }
+    }
     __syncthreads();
     const int s0 = d0 - KWIN, dend = min(d0 + nd, G);
     for (int t = threadIdx.x; t < (nd + 2 * KWIN) * NBIN; t += blockDim.x) {
@@ -1885,8 +1906,9 @@ static void step_impl(duwp_ctx *ctx)
                            by_cell);
     }
     if (fork) (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
-    // destinations per block of the two histogram passes: 4 to 64, so that their
-    // grids keep about 1000 blocks or more
+    // destinations per block of the two histogram passes: 4 (a wave each, small
+    // grids) or up to 256 (a thread each), so that their grids keep about 1000
+    // blocks or more
     const int nd = std::max(4, std::min(CN_D, G / 1024 / 4 * 4));
     {
         Mark m(ctx, "hist_fix");
