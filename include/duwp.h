@@ -72,6 +72,13 @@ typedef struct {
     int32_t dsmc_full_dt;         /* 0: collide over (1-P) dt (default); 1: over dt */
     int32_t flux_order;           /* 2: the wave flux's inviscid part takes MUSCL face states
                                      (minmod slopes of (rho,U,V,W,T)); else first order */
+    int32_t absorb_stream;        /* 1: an absorbed particle first streams for its sampled free
+                                     time t_f < dt (tau/(1-u), or -tau ln(1-u) under the
+                                     exponential law) and joins the wave part of the cell it
+                                     reaches (leaving through a reservoir, it leaves the domain);
+                                     0 (default): it joins the wave part of its own cell at
+                                     step start, as the paper's Step 2 states */
+    int32_t reserved_case;        /* 0 */
     int64_t capacity;             /* particle capacity of this case; 0 = derived from the mass */
 } duwp_case;
 

@@ -566,7 +566,15 @@ int orc_step_masked(orc_state *s, int32_t mask)
     double *Pc = malloc((size_t)C * sizeof(double));
     int *ok = malloc((size_t)C * sizeof(int));
     double *psi_w0 = malloc((size_t)C * sizeof(double));   /* start-of-step rho_w */
-    if (!Wt || !Pc || !ok || !psi_w0) { free(Wt); free(Pc); free(ok); free(psi_w0); return -1; }
+    double *tauc = calloc((size_t)C, sizeof(double));       /* tau = mu/p of the total state */
+    /* absorb_stream: moments of absorbed particles that reached another cell,
+     * by the cell reached (sources in ascending order), and whether any did */
+    double *wab = calloc((size_t)C * 5, sizeof(double));
+    int *wabin = calloc((size_t)C, sizeof(int));
+    if (!Wt || !Pc || !ok || !psi_w0 || !tauc || !wab || !wabin) {
+        free(Wt); free(Pc); free(ok); free(psi_w0); free(tauc); free(wab); free(wabin);
+        return -1;
+    }
     for (int c = 0; c < C; ++c) {
         double t[5];
         for (int k = 0; k < 5; ++k) t[k] = s->psi_w[c * 5 + k] + s->psi_p[c * 5 + k];
@@ -576,6 +584,7 @@ int orc_step_masked(orc_state *s, int32_t mask)
             double T = Wt[c * 5 + 4];
             double tau = viscosity(s, T) / (Wt[c * 5 + 0] * R * T);   /* tau = mu/p */
             Pc[c] = absorb_fraction(cs->classify_law, dt, tau);
+            tauc[c] = tau;
         } else {
             Pc[c] = 0.0;
         }
@@ -589,7 +598,10 @@ int orc_step_masked(orc_state *s, int32_t mask)
     int64_t icap = s->n + 1024, ni = 0;
     ipart *ib = malloc((size_t)icap * sizeof(ipart));
     int64_t *ioff = malloc(((size_t)C + 1) * sizeof(int64_t));
-    if (!ib || !ioff) { free(ib); free(ioff); free(Wt); free(Pc); free(ok); free(psi_w0); return -1; }
+    if (!ib || !ioff) {
+        free(ib); free(ioff); free(Wt); free(Pc); free(ok); free(psi_w0); free(tauc); free(wab); free(wabin); free(tauc); free(wab); free(wabin);
+        return -1;
+    }
 
     for (int c = 0; c < C; ++c) {
         ioff[c] = ni;
@@ -597,7 +609,10 @@ int orc_step_masked(orc_state *s, int32_t mask)
         /* ---- O2/O3: classify and absorb (Step 2, Eq. p).  A particle whose
          * sampled free-transport time tau/(1-u) is shorter than dt, i.e.
          * u < P, is absorbed: its moments join the wave part and it is
-         * removed.  Absorbed particles do not stream. ---- */
+         * removed.  Absorbed particles do not stream; with absorb_stream they
+         * first stream for that free time (-tau ln(1-u) under the exponential
+         * law) and join the wave part of the cell they reach, or leave the
+         * domain through a reservoir. ---- */
         double sa[5] = { 0, 0, 0, 0, 0 };
         int32_t nabs = 0;
         for (int64_t k = s->off[c]; k < s->off[c + 1]; ++k) {
@@ -610,9 +625,27 @@ int orc_step_masked(orc_state *s, int32_t mask)
             }
             if (absorbed) {
                 double u = s->u[k], v = s->v[k], w = s->w[k];
-                sa[0] += 1.0; sa[1] += u; sa[2] += v; sa[3] += w;
-                sa[4] += 0.5 * (u * u + v * v + w * w);
+                int64_t cland = c;
+                if (cs->absorb_stream) {
+                    uint32_t r[4];
+                    draw(s, (uint32_t)(k >> 2), 0, T_CLS, 0, r);
+                    double uc = u01(r[k & 3]);
+                    double tf = cs->classify_law == 1 ? -tauc[c] * log(1.0 - uc) : tauc[c] / (1.0 - uc);
+                    double x = s->x[k] + u * tf;
+                    cland = apply_bc(cs, &x, &u) ? cell_of(s, x) : -1;
+                }
                 ++nabs;
+                if (cland < 0) {
+                    s->d_out++;
+                } else if (cland == c) {
+                    sa[0] += 1.0; sa[1] += u; sa[2] += v; sa[3] += w;
+                    sa[4] += 0.5 * (u * u + v * v + w * w);
+                } else {
+                    double *a = wab + cland * 5;
+                    a[0] += 1.0; a[1] += u; a[2] += v; a[3] += w;
+                    a[4] += 0.5 * (u * u + v * v + w * w);
+                    wabin[cland] = 1;
+                }
             } else {
                 if (ni >= icap) { icap *= 2; ib = realloc(ib, (size_t)icap * sizeof(ipart)); if (!ib) return -1; }
                 ipart p = { s->x[k], s->u[k], s->v[k], s->w[k], c };
@@ -705,6 +738,10 @@ int orc_step_masked(orc_state *s, int32_t mask)
         }
     }
     ioff[C] = ni;
+    /* absorbed moments that reached other cells join their wave parts */
+    for (int c = 0; c < C; ++c)
+        if (wabin[c])
+            for (int k = 0; k < 5; ++k) s->psi_w[c * 5 + k] += fac * wab[c * 5 + k];
 
     /* ---- O6: free transport x <- x + xi dt (Step 3), boundaries, and
      * reservoir injection from ghost slabs beyond each reservoir side. ---- */

@@ -37,6 +37,7 @@ typedef struct {
     int32_t eps_law;            /* 0 eps_1, 1 eps_12, 2 eps_0, 3 eps of Eq. vp */
     int32_t dsmc_full_dt;       /* 1: collide over dt instead of (1-P) dt */
     int32_t flux_order;         /* 2: MUSCL-minmod inviscid face states; else first order */
+    int32_t absorb_stream;      /* 1: an absorbed particle streams for its free time first */
 } orc_case;
 
 typedef struct orc_state orc_state;

@@ -42,7 +42,7 @@ class _Case(C.Structure):
         ("m_particle", C.c_double), ("dt", C.c_double),
         ("bc_lo", C.c_int32), ("bc_hi", C.c_int32),
         ("classify_law", C.c_int32), ("eps_law", C.c_int32), ("dsmc_full_dt", C.c_int32),
-        ("flux_order", C.c_int32),
+        ("flux_order", C.c_int32), ("absorb_stream", C.c_int32),
     ]
 
 

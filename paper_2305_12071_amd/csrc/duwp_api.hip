@@ -49,6 +49,7 @@ DCase derive(const duwp_case &c, int cell_base, uint64_t seed, int case_id)
     d.eps_law = c.eps_law;
     d.full_dt = c.dsmc_full_dt;
     d.flux2 = c.flux_order == 2;
+    d.abs_stream = c.absorb_stream != 0;
     d.key0 = (uint32_t)seed;
     d.key1 = (uint32_t)(seed >> 32) + (uint32_t)case_id;
     d.x_lo = c.x_lo;
@@ -122,6 +123,7 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &c.psi_p, 8 * 5 * (size_t)G));
     TRY(dalloc(ctx, &c.wt, 8 * 5 * (size_t)G));
     TRY(dalloc(ctx, &c.pc, 8 * (size_t)G));
+    TRY(dalloc(ctx, &c.tau, 8 * (size_t)G));
     TRY(dalloc(ctx, &c.okc, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.cr_max, 8 * (size_t)G));
     TRY(dalloc(ctx, &c.n_surv, 4 * (size_t)G));
@@ -133,6 +135,14 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &c.mpart, 8 * 5 * (size_t)G * duwp::NBIN));
     TRY(dalloc(ctx, &c.mnear, 8 * 15 * (size_t)G));
     TRY(dalloc(ctx, &c.far_in, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.wabs_in, 4 * (size_t)G));
+    {
+        // the table of absorbed moments that stream across cells, only when a case asks for it
+        bool any = false;
+        for (const DCase &d : ctx->hcases) any = any || d.abs_stream;
+        ctx->abs_stream = any ? 1 : 0;
+        if (any) TRY(dalloc(ctx, &c.wabs, 8 * 5 * (size_t)G * duwp::NBIN));
+    }
     TRY(dalloc(ctx, &c.d_abs, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.d_new, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.d_cand, 4 * (size_t)G));
@@ -213,6 +223,8 @@ duwp_status upload_initial(duwp_ctx *ctx)
     HIP_OK(hipMemsetAsync(ctx->cl.cr_seen, 0, 8 * (size_t)G, s));
     HIP_OK(hipMemsetAsync(ctx->cl.mpart, 0, 8 * 5 * (size_t)G * duwp::NBIN, s));
     HIP_OK(hipMemsetAsync(ctx->cl.far_in, 0, 4 * (size_t)G, s));
+    HIP_OK(hipMemsetAsync(ctx->cl.wabs_in, 0, 4 * (size_t)G, s));
+    if (ctx->cl.wabs) HIP_OK(hipMemsetAsync(ctx->cl.wabs, 0, 8 * 5 * (size_t)G * duwp::NBIN, s));
     HIP_OK(hipMemsetAsync(ctx->cl.nbig, 0, 4, s));
     HIP_OK(hipMemsetAsync(ctx->cl.ntouch, 0, 4, s));
     for (int p = 0; p < 2; ++p) HIP_OK(hipMemsetAsync(ctx->off[p], 0, 8 * (size_t)(G + 1), s));

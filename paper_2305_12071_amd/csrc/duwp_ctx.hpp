@@ -69,6 +69,7 @@ struct duwp_ctx {
     int coll_blocks = 0;
     int big_blocks = 0;            // grid of the block-per-cell collision kernel
     int scat_by_order = 1;         // scatter blocks take cells largest first (few rounds of blocks)
+    int abs_stream = 0;            // some case lets absorbed particles stream for their free time
     double *diag = nullptr;        // [G*5] on-demand cell diagnostics
     int64_t *d_psteps = nullptr;   // particle-steps since init or the last reset
 

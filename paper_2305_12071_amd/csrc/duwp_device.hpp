@@ -23,6 +23,7 @@ enum : int32_t { ERR_CAPACITY = 1, ERR_RANGE = 2, ERR_STATE = 4 };
 struct DCase {
     int32_t ncells, cell_base;
     int32_t bc_lo, bc_hi, law, eps_law, full_dt, flux2;   // flux2: MUSCL inviscid face states
+    int32_t abs_stream;                                   // absorbed particles stream for t_f first
     uint32_t key0, key1;
     int64_t inj_base, inj_cap;       // slot range of this case's entrants in the injection buffer
     int64_t cand_base[2], cand_cap[2];  // injection candidate slots per side
@@ -58,6 +59,7 @@ struct Cells {
     double *psi_p;      // [G*5] particle part of the canonical array
     double *wt;         // [G*5] (rho, U, V, W, T) of the total at step start
     double *pc;         // [G] absorbed fraction P
+    double *tau;        // [G] mean collision time mu/p of the total state at step start
     int32_t *okc;       // [G] 1 unless vacuum
     double *cr_max;     // [G]
     int32_t *n_surv, *n_new, *n_int;   // [G] survivors, resampled, survivors+resampled
@@ -85,6 +87,9 @@ struct Cells {
     double *mnear;      // [G*15] particle moment sums of a source cell per destination g-1, g, g+1
     double *mpart;      // [G*NBIN*5] sums from farther sources, by destination (zero unless far_in)
     int32_t *far_in;    // [G] 1: a farther source left sums in the cell's mpart row this step
+    double *wabs;       // [G*NBIN*5] absorbed moments that streamed in from other cells, by
+                        // source (absorb_stream cases only; zero unless wabs_in)
+    int32_t *wabs_in;   // [G] 1: another cell's absorbed particles reached this one this step
 };
 
 // Injection buffers: candidates of every (case, side), then the entrants of

@@ -27,6 +27,7 @@
 //   wave             NS wave flux and update of Psi_w
 //   gather_moments   Psi_p of the new state, running average of Psi_t
 #include <hip/hip_runtime.h>
+#include <climits>
 #include <math.h>
 
 #include <type_traits>
@@ -69,7 +70,7 @@ __global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ ca
     const DCase &c = cases[k];
     double W[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     int ok = 0;
-    double P = 0.0;
+    double P = 0.0, tau = 0.0;
     int64_t b = 0, e = 0, pbase = 0;
     if (in && wv == 0) {
         double t[5];
@@ -77,7 +78,7 @@ __global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ ca
         for (int i = 0; i < 5; ++i) t[i] = cl.psi_w[(int64_t)g * 5 + i] + cl.psi_p[(int64_t)g * 5 + i];
         ok = primitive(t, c.R, W);
         if (ok) {
-            const double tau = viscosity(c, W[4]) / (W[0] * c.R * W[4]);
+            tau = viscosity(c, W[4]) / (W[0] * c.R * W[4]);
             P = absorb_fraction(c.law, c.dt, tau);
         }
         b = off[g];
@@ -169,6 +170,7 @@ __global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ ca
 #pragma unroll
     for (int i = 0; i < 5; ++i) cl.wt[(int64_t)g * 5 + i] = W[i];
     cl.pc[g] = P;
+    cl.tau[g] = tau;
     cl.okc[g] = ok;
     cl.n_surv[g] = ns;
     cl.n_new[g] = nnew;
@@ -227,17 +229,18 @@ __device__ __forceinline__ P4<T> *segment(const Cells &cl, int g, P4<T> *src, P4
 // 3. Classify + absorb + compact survivors + resample (Step 2), for the cells
 // that absorb or resample anything; every cell records where its segment is.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool STRM>
 __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict__ cases, Cells cl,
                                                           const P4<T> *__restrict__ src,
                                                           const int64_t *__restrict__ off, P4<T> *__restrict__ stg,
                                                           const int64_t *__restrict__ sbase,
                                                           const uint32_t *__restrict__ d_step, int G,
-                                                          int64_t cap, int32_t *err)
+                                                          int64_t cap, int32_t *err, int64_t *d_nout)
 {
     __shared__ double red[5 * 16];
     __shared__ int scr[16];
     __shared__ int dh[NBIN];
+    __shared__ unsigned long long farland;   // landing bins |dd| >= 2 of absorbed particles
     const uint32_t step = *d_step;
     const int ntouch = *cl.ntouch;
     for (int e0 = blockIdx.x; e0 < ntouch; e0 += gridDim.x) {
@@ -253,9 +256,18 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
         const int64_t ob = sbase[g];
         const int32_t nsurv = cl.n_surv[g];
         double sa[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        // absorb_stream: moments of the absorbed particles landing in g-1 and g+1
+        // (sa: in g), particles that leave through a reservoir
+        // (STRM: the context has such a case; the other instantiation carries none of this)
+        const bool strm = STRM && c.abs_stream != 0;
+        const double tau = strm ? cl.tau[g] : 0.0;
+        double sl[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, sr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        bool hasl = false, hasr = false;
+        int nleave = 0;
         int64_t written = 0;
         // the cell's destination histogram loses the absorbed and gains the resampled particles
         for (int t = threadIdx.x; t < NBIN; t += blockDim.x) dh[t] = 0;
+        if (threadIdx.x == 0) farland = 0ull;
         bool far = false;
         __syncthreads();
         if (P > 0.0) {
@@ -276,10 +288,34 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
                         if (kk < b || kk >= e) continue;
                         const P4<T> r = src[kk];
                         xs[m] = r.x; us[m] = r.u; vs[m] = r.v; ws[m] = r.w;
-                        if (u01(wd[m]) < P) {
-                            const double du = us[m], dv = vs[m], dw = ws[m];
-                            sa[0] += 1.0; sa[1] += du; sa[2] += dv; sa[3] += dw;
-                            sa[4] += 0.5 * (du * du + dv * dv + dw * dw);
+                        const double uu = u01(wd[m]);
+                        if (uu < P) {
+                            double du = us[m];
+                            const double dv = vs[m], dw = ws[m];
+                            int dd = 0;
+                            if (strm) {
+                                T uf = us[m];
+                                const int dest = PartialFlight<T>::go(ck, lc, xs[m], uf,
+                                                                      free_time(c.law, tau, uu));
+                                dd = dest < 0 ? INT_MIN : dest - lc;
+                                du = uf;
+                            }
+                            const double e2 = 0.5 * (du * du + dv * dv + dw * dw);
+                            if (dd == 0) {
+                                sa[0] += 1.0; sa[1] += du; sa[2] += dv; sa[3] += dw; sa[4] += e2;
+                            } else if (dd == -1) {
+                                sl[0] += 1.0; sl[1] += du; sl[2] += dv; sl[3] += dw; sl[4] += e2;
+                                hasl = true;
+                            } else if (dd == 1) {
+                                sr[0] += 1.0; sr[1] += du; sr[2] += dv; sr[3] += dw; sr[4] += e2;
+                                hasr = true;
+                            } else if (dd == INT_MIN) {
+                                ++nleave;
+                            } else if (dd >= -KWIN && dd <= KWIN) {
+                                atomicOr(&farland, 1ull << (dd + KWIN));
+                            } else {
+                                atomicOr(err, ERR_RANGE);
+                            }
                             bool f2 = false;
                             const int hb = flight_bin<T>(ck, lc, xs[m], us[m], &f2);
                             if (hb >= 0) atomicSub(&dh[hb], 1);
@@ -301,6 +337,43 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
                 written += tot;
             }
             block_sum<5>(sa, red);
+            if (strm) {
+                // absorbed moments that landed in other cells go to those cells'
+                // rows (slot KWIN - dd); the gather adds them to the wave part
+                auto land = [&](int dd, const double (&v)[5]) {
+                    if (threadIdx.x < 5) cl.wabs[((int64_t)(g + dd) * NBIN + (KWIN - dd)) * 5 + threadIdx.x] = v[threadIdx.x];
+                    if (threadIdx.x == 0) cl.wabs_in[g + dd] = 1;
+                };
+                if (__syncthreads_or(hasl)) { block_sum<5>(sl, red); land(-1, sl); }
+                if (__syncthreads_or(hasr)) { block_sum<5>(sr, red); land(1, sr); }
+                int tot;
+                (void)block_count_prefix(nleave, scr, &tot);
+                if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&d_nout[k], (unsigned long long)tot);
+                // farther landings (rare): a pass over the cell per landing bin
+                const unsigned long long fl = farland;
+                for (int bin = 0; bin < NBIN; ++bin) {
+                    if (!((fl >> bin) & 1ull)) continue;
+                    const int dd = bin - KWIN;
+                    double a2[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+                    for (int64_t kk = b + threadIdx.x; kk < e; kk += blockDim.x) {
+                        const int64_t li = kk - pbase;
+                        const U4 r = draw(ck, step, (uint32_t)(li >> 2), 0, TAG_CLS, 0);
+                        const int m = (int)(li & 3);
+                        const uint32_t wdm = m == 0 ? r.a : (m == 1 ? r.b : (m == 2 ? r.c : r.d));
+                        const double uu = u01(wdm);
+                        if (!(uu < P)) continue;
+                        const P4<T> rr = src[kk];
+                        T uf = rr.u;
+                        const int dest = PartialFlight<T>::go(ck, lc, rr.x, uf, free_time(c.law, tau, uu));
+                        if (dest < 0 || dest - lc != dd) continue;
+                        const double du = uf, dv = rr.v, dw = rr.w;
+                        a2[0] += 1.0; a2[1] += du; a2[2] += dv; a2[3] += dw;
+                        a2[4] += 0.5 * (du * du + dv * dv + dw * dw);
+                    }
+                    block_sum<5>(a2, red);
+                    land(dd, a2);
+                }
+            }
         } else {
             for (int64_t kk = b + threadIdx.x; kk < e; kk += blockDim.x) {
                 int64_t d = ob + (kk - b);
@@ -1657,10 +1730,25 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
     if (!in) return;
     double pw[5];
     {
+        // absorbed moments that streamed in from other cells (absorb_stream),
+        // their sources in order, join the wave part before its flux update
+        double wa[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        const bool win = c.abs_stream && cl.wabs_in[d];
+        if (win) {
+            double *row = cl.wabs + (int64_t)d * NBIN * 5;
+            for (int t = 0; t < NBIN; ++t)
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    wa[q] += row[t * 5 + q];
+                    row[t * 5 + q] = 0.0;
+                }
+            cl.wabs_in[d] = 0;
+        }
         const double r = c.dt / c.dx;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            pw[q] = cl.psi_w[(int64_t)d * 5 + q] - r * (Fr[q] - F[q]);
+            const double w0 = win ? cl.psi_w[(int64_t)d * 5 + q] + c.fac * wa[q] : cl.psi_w[(int64_t)d * 5 + q];
+            pw[q] = w0 - r * (Fr[q] - F[q]);
             cl.psi_w[(int64_t)d * 5 + q] = pw[q];
         }
     }
@@ -1860,9 +1948,14 @@ static void step_impl(duwp_ctx *ctx)
     {
         Mark m(ctx, "absorb_resample");
         // the listed cells, by a grid of at most 16 blocks per compute unit
-        hipLaunchKernelGGL(k_absorb_resample<T>, dim3(std::min(G, 16 * ctx->big_blocks)), dim3(bc), 0, st,
-                           ctx->d_cases, cl, src, ctx->off[p], stg, ctx->ibase, ctx->d_step, G, ctx->cap,
-                           ctx->d_err);
+        if (ctx->abs_stream)
+            hipLaunchKernelGGL((k_absorb_resample<T, true>), dim3(std::min(G, 16 * ctx->big_blocks)), dim3(bc), 0,
+                               st, ctx->d_cases, cl, src, ctx->off[p], stg, ctx->ibase, ctx->d_step, G, ctx->cap,
+                               ctx->d_err, ctx->d_nout);
+        else
+            hipLaunchKernelGGL((k_absorb_resample<T, false>), dim3(std::min(G, 16 * ctx->big_blocks)), dim3(bc), 0,
+                               st, ctx->d_cases, cl, src, ctx->off[p], stg, ctx->ibase, ctx->d_step, G, ctx->cap,
+                               ctx->d_err, ctx->d_nout);
     }
     // Injection and the big-cell collide do not depend on the small-cell collide:
     // they go on a second stream (a parallel branch of the captured graph).

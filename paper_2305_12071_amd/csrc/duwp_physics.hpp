@@ -193,6 +193,41 @@ struct Flight<float> {
     }
 };
 
+// Free time of an absorbed particle (absorb_stream): the u of its classification
+// draw gives t_f < dt with u < P: tau/(1-u) under Eq. p, -tau ln(1-u) under
+// the exponential law.
+__device__ __forceinline__ double free_time(int law, double tau, double u)
+{
+    return law == 1 ? -tau * log(1.0 - u) : tau / (1.0 - u);
+}
+
+// Flight of an absorbed particle over its free time tf < dt: its landing cell
+// (local), or -1 when it leaves through a reservoir; u follows wall reflections.
+template <typename T>
+struct PartialFlight;
+
+template <>
+struct PartialFlight<double> {
+    template <typename K>
+    __device__ static int go(const K &c, int /*lc*/, double x, double &u, double tf)
+    {
+        x = x + u * tf;
+        return bc_cell_abs(c, x, u);
+    }
+};
+
+template <>
+struct PartialFlight<float> {
+    template <typename K>
+    __device__ static int go(const K &c, int lc, float s, float &u, double tf)
+    {
+        const float X = s + u * (float)(tf / c.dx);
+        if (!(fabsf(X) < 1.0e9f)) return -1;
+        const float fl = floorf(X);
+        return bc_cell_rel(c, lc + (int)fl, X - fl, u, s);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Wave part: NS flux (KFVS inviscid + central viscous, eps-scaled viscosity,
 // weighted by the interface absorption fraction).

@@ -38,7 +38,8 @@ class _Case(C.Structure):
         ("m_particle", C.c_double), ("dt", C.c_double),
         ("bc_lo", C.c_int32), ("bc_hi", C.c_int32),
         ("classify_law", C.c_int32), ("eps_law", C.c_int32), ("dsmc_full_dt", C.c_int32),
-        ("flux_order", C.c_int32), ("capacity", C.c_int64),
+        ("flux_order", C.c_int32), ("absorb_stream", C.c_int32), ("reserved_case", C.c_int32),
+        ("capacity", C.c_int64),
     ]
 
 

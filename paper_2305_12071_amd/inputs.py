@@ -73,6 +73,7 @@ class Case:
     eps_law: int = EPS1
     dsmc_full_dt: int = 0    # 1: DSMC collides over the full dt instead of (1-P) dt
     flux_order: int = 1      # 2: MUSCL-minmod inviscid face states in the wave flux
+    absorb_stream: int = 0   # 1: absorbed particles stream for their free time first
     capacity: int = 0        # particle capacity hint (0 = derive)
     name: str = ""
 

@@ -44,4 +44,4 @@ def test_case_struct_layout_matches_header():
     body = src[src.index("typedef struct {\n    int32_t kind;"):src.index("} duwp_case;")]
     names = re.findall(r"\b([a-zA-Z_]+)\s*[,;]", re.sub(r"/\*.*?\*/", "", body, flags=re.S))
     assert names == [f for f, _ in duwp._Case._fields_]
-    assert ctypes.sizeof(duwp._Case) == 4 * 2 + 8 * 18 + 4 * 6 + 8
+    assert ctypes.sizeof(duwp._Case) == 4 * 2 + 8 * 18 + 4 * 8 + 8

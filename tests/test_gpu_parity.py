@@ -51,6 +51,18 @@ def _cases():
     c = I.box(7, 0.8, 2.0, 150, 3.0, u=0.3)
     c.flux_order = 2
     out["box_ragged_muscl"] = c
+    # absorbed particles stream for their free time first: walls, the
+    # exponential law, reservoirs (absorbed particles can leave through them)
+    c = I.box(7, 0.8, 2.0, 150, 3.0, u=0.3, cfl=0.8)
+    c.absorb_stream = 1
+    out["box_stream"] = c
+    c = I.sod_paper(3e-4)
+    c.classify_law = I.CLASSIFY_EXP
+    c.absorb_stream = 1
+    out["sod_exp_stream"] = c
+    c = I.argon_shock(3.0, 60, 60 * 20.0, 3e4, name="shock_dx20_stream")
+    c.absorb_stream = 1
+    out["shock_dx20_stream"] = c
     return out
 
 
@@ -125,7 +137,7 @@ def test_block_sizes_match_oracle(bc):
         g.close()
 
 
-@pytest.mark.parametrize("name", ["mach3", "sod_kn1e-4", "box_p97"])
+@pytest.mark.parametrize("name", ["mach3", "sod_kn1e-4", "box_p97", "box_stream", "shock_dx20_stream"])
 def test_twenty_steps_from_initial_state(name):
     c = CASES[name]
     _say("case", name, "fp64 20 steps")
@@ -242,11 +254,13 @@ def test_capacity_overflow_is_reported():
     g.close()
 
 
-def test_mixed_precision_profiles_match_fp64():
-    """FP32 particles + FP64 cells against FP64: time-averaged profiles of the Mach-3
-    shock agree to the seed-to-seed noise of the FP64 path."""
-    c = CASES["mach3"]
-    _say("mixed vs fp64")
+@pytest.mark.parametrize("name", ["mach3", "shock_dx20_stream"])
+def test_mixed_precision_profiles_match_fp64(name):
+    """FP32 particles + FP64 cells against FP64: time-averaged profiles of a shock
+    (pure DSMC; and one whose absorbed particles stream first) agree to the
+    seed-to-seed noise of the FP64 path."""
+    c = CASES[name]
+    _say("mixed vs fp64", name)
     res = {}
     for prec in (duwp.FP64, duwp.MIXED):
         for seed in (1, 2):

@@ -685,3 +685,96 @@ def test_second_order_sod_conserves_and_beats_first_order():
             errs[order, n] = np.abs(o.cells()["prim"][:, 0] - ex[:, 0]).mean()
     assert errs[2, 100] < 0.5 * errs[1, 100], errs
     assert errs[2, 200] < 0.7 * errs[2, 100], errs
+
+
+# --------------------------------------------------------------------------
+# Absorbed particles that stream for their free time first (absorb_stream)
+# --------------------------------------------------------------------------
+
+def _stream_box(law, dt_over_tau=3.0):
+    c = I.box(6, 1.0, 1.0, 600, dt_over_tau, u=0.4, cfl=0.8)
+    c.classify_law = law
+    c.absorb_stream = 1
+    return c
+
+
+@pytest.mark.parametrize("law,r", [(I.CLASSIFY_RATIONAL, 3.0), (I.CLASSIFY_EXP, 1.2)])
+def test_streamed_absorption_matches_a_direct_recount(law, r):
+    # The classify stage alone, recomputed here from its definition: a particle
+    # whose draw u is below P streams for its free time (tau/(1-u), or
+    # -tau ln(1-u) under the exponential law), is reflected at the walls, and its
+    # moments join the wave part of the cell it reaches.
+    c = _stream_box(law, r)
+    seed = 3
+    o = O.Oracle(c, seed=seed)
+    _to_particles(o)
+    st = o.get_state()
+    step = o.step_index
+    prim = o.cells()["prim"]
+    k = o.constants()
+    mu = k["mu_ref"] * (prim[:, 4] / c.T_ref) ** c.omega
+    tau = mu / (prim[:, 0] * c.R * prim[:, 4])
+    if law == I.CLASSIFY_RATIONAL:
+        P = np.maximum(1.0 - tau / c.dt, 0.0)
+    else:
+        P = 1.0 - np.exp(-c.dt / tau)
+    dx = k["dx"]
+    fac = c.m_particle / dx
+    off, x, u, v, w = st["off"], st["x"], st["u"], st["v"], st["w"]
+    dpsi = np.zeros((c.ncells, 5))
+    nabs = np.zeros(c.ncells, np.int64)
+    moved = reflected = 0
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for cell in range(c.ncells):
+        for q in range(off[cell], off[cell + 1]):
+            uu = float(O.philox([step, q >> 2, 0, 1 << 16], key)[q & 3]) / 4294967296.0
+            if not uu < P[cell]:
+                continue
+            nabs[cell] += 1
+            tf = tau[cell] / (1.0 - uu) if law == I.CLASSIFY_RATIONAL else -tau[cell] * math.log(1.0 - uu)
+            xp, up = x[q] + u[q] * tf, u[q]
+            while xp < c.x_lo or xp > c.x_hi:
+                xp, up = (2 * c.x_lo - xp, -up) if xp < c.x_lo else (2 * c.x_hi - xp, -up)
+                reflected += 1
+            land = min(int(math.floor((xp - c.x_lo) / dx)), c.ncells - 1)
+            moved += land != cell
+            dpsi[land] += fac * np.array([1.0, up, v[q], w[q], 0.5 * (up * up + v[q] ** 2 + w[q] ** 2)])
+    assert moved > 20 and reflected > 0
+    psi0 = st["psi_w"].copy()
+    o.step_masked(O.CLASSIFY)
+    st1 = o.get_state()
+    assert np.array_equal(o.diag()["n_abs"], nabs)
+    assert np.array_equal(np.diff(st1["off"]), np.diff(off) - nabs)
+    np.testing.assert_allclose(st1["psi_w"], psi0 + dpsi, rtol=1e-12, atol=1e-12 * np.abs(psi0).max())
+
+
+def _totals(o, c):
+    st = o.get_state()
+    dx = o.constants()["dx"]
+    mass = st["psi_w"][:, 0].sum() * dx + len(st["x"]) * c.m_particle
+    e_p = 0.5 * c.m_particle * (st["u"] ** 2 + st["v"] ** 2 + st["w"] ** 2).sum()
+    return mass, st["psi_w"][:, 4].sum() * dx + e_p
+
+
+@pytest.mark.parametrize("law", [I.CLASSIFY_RATIONAL, I.CLASSIFY_EXP])
+def test_streamed_absorption_conserves_mass_and_energy_between_walls(law):
+    c = _stream_box(law)
+    o = O.Oracle(c, seed=8)
+    _to_particles(o)
+    m0, e0 = _totals(o, c)
+    o.step(4)
+    m1, e1 = _totals(o, c)
+    assert abs(m1 - m0) <= 1e-12 * m0
+    assert abs(e1 - e0) <= 1e-12 * e0
+
+
+def test_streamed_absorption_changes_nothing_when_nothing_is_absorbed():
+    a_case = _stream_box(I.CLASSIFY_RATIONAL, dt_over_tau=0.5)      # P = 0
+    b_case = _stream_box(I.CLASSIFY_RATIONAL, dt_over_tau=0.5)
+    b_case.absorb_stream = 0
+    a, b = O.Oracle(a_case, seed=9), O.Oracle(b_case, seed=9)
+    a.step(3)
+    b.step(3)
+    sa, sb = a.get_state(), b.get_state()
+    for key in ("x", "u", "v", "w", "off", "psi_w", "cr_max"):
+        assert np.array_equal(sa[key], sb[key]), key
