@@ -53,7 +53,8 @@ constexpr int NBI = 2 * (KWIN + 1);    // injection destination window (both end
 __global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ cases, Cells cl,
                                                      const int64_t *__restrict__ off,
                                                      const uint32_t *__restrict__ d_step, int G,
-                                                     int32_t *err, int64_t *d_nout, int64_t *d_ninj)
+                                                     int32_t *err, int64_t *d_nout, int64_t *d_ninj,
+                                                     int abs_stream)
 {
     __shared__ double sP[WAVE];
     __shared__ int64_t sb[WAVE], se[WAVE], spb[WAVE];
@@ -170,7 +171,7 @@ __global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ ca
 #pragma unroll
     for (int i = 0; i < 5; ++i) cl.wt[(int64_t)g * 5 + i] = W[i];
     cl.pc[g] = P;
-    cl.tau[g] = tau;
+    if (abs_stream) cl.tau[g] = tau;    // read only by streamed absorption
     cl.okc[g] = ok;
     cl.n_surv[g] = ns;
     cl.n_new[g] = nnew;
@@ -1661,7 +1662,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict__ cases, Cells cl, const P4<T> *dst,
                                                         const int64_t *__restrict__ off_new, int G, int32_t *err,
                                                         uint32_t *d_step, const int64_t *__restrict__ off_old,
-                                                        int64_t *d_psteps)
+                                                        int64_t *d_psteps, int abs_stream)
 {
     const int lane = lane_id();
     constexpr int CPW = WAVE / 2;    // cells per wave
@@ -1733,7 +1734,8 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
         // absorbed moments that streamed in from other cells (absorb_stream),
         // their sources in order, join the wave part before its flux update
         double wa[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        const bool win = c.abs_stream && cl.wabs_in[d];
+        // (abs_stream: some case of the context streams absorbed particles)
+        const bool win = abs_stream && c.abs_stream && cl.wabs_in[d];
         if (win) {
             double *row = cl.wabs + (int64_t)d * NBIN * 5;
             for (int t = 0; t < NBIN; ++t)
@@ -1939,7 +1941,7 @@ static void step_impl(duwp_ctx *ctx)
         const int cblk = (G + WAVE - 1) / WAVE;
         const int cw = std::max(1, std::min(16, (8192 + cblk - 1) / cblk));
         hipLaunchKernelGGL(k_cellstate, dim3(cblk), dim3(WAVE * cw), 0, st, ctx->d_cases, cl, ctx->off[p],
-                           ctx->d_step, G, ctx->d_err, ctx->d_nout, ctx->d_ninj);
+                           ctx->d_step, G, ctx->d_err, ctx->d_nout, ctx->d_ninj, ctx->abs_stream);
     }
     {
         Mark m(ctx, "scan_staging");
@@ -2037,7 +2039,7 @@ static void step_impl(duwp_ctx *ctx)
     {
         Mark m(ctx, "gather_moments");
         hipLaunchKernelGGL(k_gather_moments<T>, dim3((G + 127) / 128), dim3(256), 0, st, ctx->d_cases, cl, dst,
-                           ctx->off[p ^ 1], G, ctx->d_err, ctx->d_step, ctx->off[p], ctx->d_psteps);
+                           ctx->off[p ^ 1], G, ctx->d_err, ctx->d_step, ctx->off[p], ctx->d_psteps, ctx->abs_stream);
     }
 }
 
