@@ -247,8 +247,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the pipeline would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs each context on one GPU "
+              "and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     legs = [x for x in args.legs.split(",") if x]
     for flag, leg in ((args.no_fp64, "fp64"), (args.no_batched, "batched"), (args.no_large, "large"),
