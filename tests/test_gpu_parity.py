@@ -122,7 +122,7 @@ def test_step_from_identical_developed_state(name):
 def test_block_sizes_match_oracle(bc):
     """The per-cell kernels at other block sizes (64: one-wave blocks, the scatter's
     register-only variant) from a developed state, against the oracle."""
-    for name in ("mach3", "sod_kn1e-4", "box_ragged", "sod_kn1e-5_muscl"):
+    for name in ("mach3", "sod_kn1e-4", "box_ragged", "sod_kn1e-5_muscl", "box_stream"):
         c = CASES[name]
         _say("case", name, "block size", bc)
         o = O.Oracle(c, seed=5, case_id=0)
@@ -152,8 +152,12 @@ def test_twenty_steps_from_initial_state(name):
     g.close()
 
 
-def test_batched_uneven_cases_match_per_case_oracles():
-    names = ["mach3", "sod_kn1e-4", "box_ragged", "sod_kn1e-2", "sod_exp_epsfull"]
+@pytest.mark.parametrize("names", [
+    ["mach3", "sod_kn1e-4", "box_ragged", "sod_kn1e-2", "sod_exp_epsfull"],
+    # cases that stream absorbed particles beside cases that do not
+    ["box_stream", "sod_kn1e-4", "shock_dx20_stream", "mach3", "sod_exp_stream"],
+])
+def test_batched_uneven_cases_match_per_case_oracles(names):
     cases = [CASES[n] for n in names]
     _say("batched", names)
     g = duwp.Sim(cases, seed=5, precision=duwp.FP64)
