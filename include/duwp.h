@@ -127,7 +127,9 @@ enum {
 
 /* Create a context holding ncases independent cases; all cases step together.
  * Fails with DUWP_EINVAL on an invalid case (ncells <= 0, x_hi <= x_lo, m_particle
- * or dt <= 0, no gas constants), DUWP_ENOMEM when buffers do not fit.  The initial
+ * or dt <= 0, no gas constants, a mode field out of its range, reserved_case not 0)
+ * or options (precision, block_cells not a multiple of 64 up to 512), checked before
+ * any device call; DUWP_ENOMEM when buffers do not fit.  The initial
  * state puts all mass in the wave part (no particles), the first step samples them. */
 duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, const duwp_opts *opts);
 

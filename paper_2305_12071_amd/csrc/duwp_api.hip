@@ -30,6 +30,8 @@ bool case_valid(const duwp_case &c)
     if (!(c.lambda_ref > 0.0 && c.rho_ref > 0.0) && !(c.m_mol > 0.0 && c.d_ref > 0.0)) return false;
     if (c.bc_lo < 0 || c.bc_lo > 1 || c.bc_hi < 0 || c.bc_hi > 1) return false;
     if (c.classify_law < 0 || c.classify_law > 1 || c.eps_law < 0 || c.eps_law > 3) return false;
+    if (c.dsmc_full_dt < 0 || c.dsmc_full_dt > 1 || c.absorb_stream < 0 || c.absorb_stream > 1) return false;
+    if (c.reserved_case != 0) return false;
     return true;
 }
 
@@ -344,7 +346,17 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
 {
     if (!out || !cases || ncases <= 0 || !opts) return DUWP_EINVAL;
     *out = nullptr;
+    // every check on the arguments comes before the first device call
     if (opts->precision != DUWP_FP64 && opts->precision != DUWP_MIXED) return DUWP_EINVAL;
+    if (opts->block_cells > 0 && (opts->block_cells % 64 || opts->block_cells > 512)) return DUWP_EINVAL;
+    {
+        int64_t cells = 0;
+        for (int k = 0; k < ncases; ++k) {
+            if (!case_valid(cases[k])) return DUWP_EINVAL;
+            cells += cases[k].ncells;
+        }
+        if (cells > (int64_t)1 << 30) return DUWP_EINVAL;
+    }
     duwp_ctx *ctx = new (std::nothrow) duwp_ctx();
     if (!ctx) return DUWP_ENOMEM;
     ctx->ncases = ncases;
@@ -361,7 +373,6 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
     }
     ctx->seed = opts->seed;
     ctx->block_cells = opts->block_cells > 0 ? opts->block_cells : 256;
-    if (ctx->block_cells % 64 || ctx->block_cells > 512) { delete ctx; return DUWP_EINVAL; }
     if (hipStreamCreateWithFlags(&ctx->stream2, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
@@ -372,7 +383,6 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
     int64_t G = 0, cap = 0, inj = 0, cand = 0, max_side = 0, chunks = 0;
     for (int k = 0; k < ncases; ++k) {
         const duwp_case &c = cases[k];
-        if (!case_valid(c)) { delete ctx; return DUWP_EINVAL; }
         ctx->cases.push_back(c);
         ctx->hcases.push_back(derive(c, (int)G, opts->seed, k));
         G += c.ncells;
@@ -398,7 +408,7 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
         d.inj_cap = ib;
         inj += ib;
     }
-    if (G > (int64_t)1 << 30 || cap > ((int64_t)1 << 40)) { delete ctx; return DUWP_EINVAL; }
+    if (cap > ((int64_t)1 << 40)) { duwp_destroy(ctx); return DUWP_EINVAL; }
     ctx->G = (int)G;
     ctx->cap = cap;
     ctx->inj_total = std::max<int64_t>(inj, 1);

@@ -45,3 +45,39 @@ def test_case_struct_layout_matches_header():
     names = re.findall(r"\b([a-zA-Z_]+)\s*[,;]", re.sub(r"/\*.*?\*/", "", body, flags=re.S))
     assert names == [f for f, _ in duwp._Case._fields_]
     assert ctypes.sizeof(duwp._Case) == 4 * 2 + 8 * 18 + 4 * 8 + 8
+
+
+def _init_status(cases, precision=duwp.FP64, block_cells=0):
+    arr = (duwp._Case * len(cases))(*[c if isinstance(c, duwp._Case) else duwp.make_case(c) for c in cases])
+    o = duwp._Opts()
+    o.seed = 1
+    o.precision = precision
+    o.use_graph = 0
+    o.stream = None
+    o.headroom = 0.0
+    o.block_cells = block_cells
+    ptr = ctypes.c_void_p()
+    s = duwp.lib().duwp_init(ctypes.byref(ptr), arr, len(cases), ctypes.byref(o))
+    assert not ptr.value
+    return s
+
+
+def test_init_rejects_bad_descriptors_before_any_device_call():
+    # every argument is checked before the first device call, so these run
+    # on a host without a GPU and leave nothing behind
+    from dataclasses import replace
+    from paper_2305_12071_amd import inputs as I
+    EINVAL = -1
+    good = I.box(4, 1.0, 1.0, 10, 0.5)
+    for bad in (dict(ncells=0), dict(dt=0.0), dict(m_particle=-1.0), dict(x_hi=good.x_lo),
+                dict(x_split=2.0), dict(rho_L=0.0), dict(T_R=-1.0), dict(lambda_ref=0.0),
+                dict(bc_lo=2), dict(classify_law=2), dict(eps_law=4), dict(dsmc_full_dt=2),
+                dict(absorb_stream=2)):
+        assert _init_status([replace(good, **bad)]) == EINVAL, bad
+    reserved = duwp.make_case(good)
+    reserved.reserved_case = 1
+    assert _init_status([reserved]) == EINVAL
+    assert _init_status([good, replace(good, rho_R=-1.0)]) == EINVAL     # a bad second case
+    assert _init_status([good], precision=7) == EINVAL
+    for bc in (100, 1024, 96):
+        assert _init_status([good], block_cells=bc) == EINVAL, bc

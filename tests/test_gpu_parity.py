@@ -247,6 +247,24 @@ def test_restore_in_place_equals_full_rebuild(prec):
     b.close()
 
 
+def test_non_finite_state_is_reported():
+    # a NaN put into one cell's wave energy through set_state: the cell counts as
+    # vacuum (no sampling, no collisions, no flux), and the step reports the
+    # non-finite total as DUWP_ESTATE
+    c = CASES["sod_kn1e-4"]
+    _say("non-finite state")
+    g = duwp.Sim(c, seed=3)
+    g.step(3)
+    st = g.get_state()
+    st["psi_w"] = st["psi_w"].copy()
+    st["psi_w"][5, 4] = np.nan
+    g.set_state(st)
+    with pytest.raises(duwp.DuwpError) as e:
+        g.step(1)
+    assert e.value.status == -5
+    g.close()
+
+
 def test_capacity_overflow_is_reported():
     c = I.sod_paper(1e-2)
     c.capacity = 1000      # far below the ~1.1e5 particles of the first step
