@@ -778,3 +778,23 @@ def test_streamed_absorption_changes_nothing_when_nothing_is_absorbed():
     sa, sb = a.get_state(), b.get_state()
     for key in ("x", "u", "v", "w", "off", "psi_w", "cr_max"):
         assert np.array_equal(sa[key], sb[key]), key
+
+
+def test_reservoir_entrants_follow_the_one_sided_maxwellian_flux():
+    # Particles entering through a reservoir side per step: (1 - P_s) rho dt /
+    # m_p times the mean inward speed of a Maxwellian, E[max(U_n, 0)] =
+    # sqrt(RT / 2 pi) exp(-s^2) + (U_n / 2)(1 + erf(s)), s = U_n / sqrt(2 R T),
+    # with U_n the reservoir velocity along the inward normal (P_s = 0 here).
+    c = I.mach3_small()
+    o = O.Oracle(c, seed=12)
+    steps = 200
+    got = np.zeros(2)
+    for _ in range(steps):
+        o.step(1)
+        got += o.diag()["n_inj"]
+    for side, (rho, U, T) in enumerate(((c.rho_L, c.u_L, c.T_L), (c.rho_R, -c.u_R, c.T_R))):
+        s = U / math.sqrt(2 * c.R * T)
+        mean_in = math.sqrt(c.R * T / (2 * math.pi)) * math.exp(-s * s) + 0.5 * U * (1 + math.erf(s))
+        expect = steps * rho * c.dt / c.m_particle * mean_in
+        assert expect > 500
+        assert abs(got[side] - expect) < 4 * math.sqrt(expect), (side, got[side], expect)
