@@ -798,3 +798,27 @@ def test_reservoir_entrants_follow_the_one_sided_maxwellian_flux():
         expect = steps * rho * c.dt / c.m_particle * mean_in
         assert expect > 500
         assert abs(got[side] - expect) < 4 * math.sqrt(expect), (side, got[side], expect)
+
+
+def test_time_average_is_the_sum_of_each_steps_total_state():
+    # the running sum holds Psi_t of the state each step ends with, rebuilt here
+    # from the raw state: the wave part plus m_p/dx times the per-cell sums of
+    # (1, u, v, w, |c|^2/2) of the particles
+    c = I.sod_paper(1e-4)
+    o = O.Oracle(c, seed=13)
+    o.step(3)
+    o.reset_average()
+    fac = c.m_particle / o.constants()["dx"]
+    acc = np.zeros((c.ncells, 5))
+    for _ in range(5):
+        o.step(1)
+        st = o.get_state()
+        cell = np.repeat(np.arange(c.ncells), np.diff(st["off"]))
+        u, v, w = st["u"], st["v"], st["w"]
+        psi = st["psi_w"].copy()
+        for q, val in enumerate((np.ones_like(u), u, v, w, 0.5 * (u * u + v * v + w * w))):
+            psi[:, q] += fac * np.bincount(cell, weights=val, minlength=c.ncells)
+        acc += psi
+    s, cnt = o.average()
+    assert cnt == 5
+    np.testing.assert_allclose(s, acc, rtol=1e-11, atol=1e-11 * np.abs(acc).max())
