@@ -822,3 +822,16 @@ def test_time_average_is_the_sum_of_each_steps_total_state():
     s, cnt = o.average()
     assert cnt == 5
     np.testing.assert_allclose(s, acc, rtol=1e-11, atol=1e-11 * np.abs(acc).max())
+
+
+def test_resample_count_is_the_unabsorbed_share_of_the_wave_mass():
+    # Step 2: 1 - P of each cell's wave mass becomes particles, the count rounded
+    # stochastically (so within one of the exact value); the box fixes
+    # dt/tau = 3, so P = 2/3 under Eq. p
+    c = I.box(8, 1.0, 1.0, 3001, 3.0)     # 1000.33 per cell: clear of an integer
+    o = O.Oracle(c, seed=14)
+    mw = o.get_state()["psi_w"][:, 0] * o.constants()["dx"]
+    o.step_masked(O.RESAMPLE)
+    n = np.diff(o.get_state()["off"])
+    exact = (1.0 - 2.0 / 3.0) * mw / c.m_particle
+    assert np.all(n >= np.floor(exact)) and np.all(n <= np.floor(exact) + 1), (n, exact)
