@@ -96,7 +96,11 @@ typedef struct duwp_ctx duwp_ctx;
 
 /* Host copy of one case's state (FP64 whatever the precision; x absolute).
  * x,u,v,w: [n_particles]; off: [ncells+1]; psi_w: [ncells*5] = (rho, rho U, rho V,
- * rho W, rho E) of the wave part; cr_max: [ncells]. */
+ * rho W, rho E) of the wave part; cr_max: [ncells].  psi_p: [ncells*5], the
+ * particle part (Eq. gkt_moment0 over the cell's particles, per unit area), or
+ * NULL.  The step sums it in its own order while it sorts; a restore that
+ * brings it back resumes bit for bit, one without it sums it afresh from the
+ * particles (equal up to rounding order). */
 typedef struct {
     int64_t n_particles;
     int32_t ncells;
@@ -105,6 +109,7 @@ typedef struct {
     int64_t *off;
     double *psi_w;
     double *cr_max;
+    double *psi_p;
 } duwp_state;
 
 /* What duwp_moments returns, each [ncells*5] doubles */
@@ -160,11 +165,15 @@ duwp_status duwp_counts(duwp_ctx *ctx, int32_t case_id, int64_t *n_particles, in
 duwp_status duwp_diag(duwp_ctx *ctx, int32_t case_id, int32_t *n_abs, int32_t *n_new,
                       int32_t *n_cand, int32_t *n_coll, int64_t *n_inj, int64_t *n_out);
 
-/* Copy one case's state to host buffers sized from duwp_counts (checkpoint, parity). */
+/* Copy one case's state to host buffers sized from duwp_counts (checkpoint, parity).
+ * A NULL array is skipped. */
 duwp_status duwp_get_state(duwp_ctx *ctx, int32_t case_id, duwp_state *st);
 
 /* Replace one case's state (and the context's step index) from host buffers.  The
- * particle moments are recomputed; the case keeps its place among the others.
+ * particle moments of the case's cells are loaded from psi_p, or recomputed from
+ * the particles when psi_p is NULL (a state whose particles were changed must not
+ * bring the old psi_p); other cases keep theirs.  The case keeps its place among
+ * the others.
  * With the case's particle count unchanged only its records move (host work in
  * proportion to the case); otherwise the whole canonical array makes a round trip
  * through the host.  DUWP_EINVAL if offsets are not monotone, DUWP_ECAPACITY if it

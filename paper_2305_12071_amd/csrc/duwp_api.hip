@@ -610,6 +610,9 @@ duwp_status duwp_get_state(duwp_ctx *ctx, int32_t case_id, duwp_state *st)
                               hipMemcpyDeviceToHost, s));
     if (st->cr_max)
         HIP_OK(hipMemcpyAsync(st->cr_max, ctx->cl.cr_max + d.cell_base, 8 * (size_t)d.ncells, hipMemcpyDeviceToHost, s));
+    if (st->psi_p)
+        HIP_OK(hipMemcpyAsync(st->psi_p, ctx->cl.psi_p + 5 * (size_t)d.cell_base, 8 * 5 * (size_t)d.ncells,
+                              hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     return DUWP_OK;
 }
@@ -694,6 +697,9 @@ duwp_status duwp_set_state(duwp_ctx *ctx, int32_t case_id, const duwp_state *st)
     HIP_OK(hipMemcpyAsync(ctx->cl.psi_w + 5 * (size_t)d.cell_base, st->psi_w, 8 * 5 * (size_t)d.ncells,
                           hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(ctx->cl.cr_max + d.cell_base, st->cr_max, 8 * (size_t)d.ncells, hipMemcpyHostToDevice, s));
+    if (st->psi_p)
+        HIP_OK(hipMemcpyAsync(ctx->cl.psi_p + 5 * (size_t)d.cell_base, st->psi_p, 8 * 5 * (size_t)d.ncells,
+                              hipMemcpyHostToDevice, s));
     // the step index is shared by all cases; the parity of the buffers follows it
     if ((st->step & 1u) != (ctx->step & 1u)) {
         if (total) HIP_OK(hipMemcpyAsync(ctx->A[p ^ 1], ctx->A[p], rs * (size_t)total, hipMemcpyDeviceToDevice, s));
@@ -704,7 +710,7 @@ duwp_status duwp_set_state(duwp_ctx *ctx, int32_t case_id, const duwp_state *st)
     HIP_OK(hipMemcpyAsync(ctx->d_step, &dstep, 4, hipMemcpyHostToDevice, s));
     HIP_OK(hipStreamSynchronize(s));
     (void)hipGetLastError();
-    duwp::enqueue_moments(ctx);
+    duwp::enqueue_moments(ctx, d.cell_base, d.cell_base + d.ncells, st->psi_p == nullptr);
     if (hipGetLastError() != hipSuccess) return DUWP_EDEVICE;
     HIP_OK(hipStreamSynchronize(s));
     return DUWP_OK;

@@ -84,8 +84,10 @@ namespace duwp {
 void enqueue_step(duwp_ctx *ctx);
 // Scatter blocks that fit on one compute unit at once (for this precision and block size).
 int scatter_blocks_per_cu(int precision, int bc);
-// Recompute the particle moments of the current canonical state (no averaging).
-void enqueue_moments(duwp_ctx *ctx);
+// Particle moments of cells [g0, g1) of the current canonical state: recomputed
+// from the particles, or (recompute false) kept as loaded and checked for finite
+// totals; then the destination histogram of every cell (no averaging).
+void enqueue_moments(duwp_ctx *ctx, int g0, int g1, bool recompute);
 // Normal stress and heat flux of cells [g0, g1) of the current state into out[G*5].
 void enqueue_stress_heat(duwp_ctx *ctx, int g0, int g1, double *out);
 }  // namespace duwp

@@ -1863,25 +1863,34 @@ __global__ void __launch_bounds__(256) k_stress_heat(const DCase *__restrict__ c
 // Particle moments recomputed from a canonical array (after a state is loaded).
 template <typename T>
 __global__ void __launch_bounds__(512) k_moments(const DCase *__restrict__ cases, Cells cl, const P4<T> *a,
-                                                  const int64_t *__restrict__ off, int G, int32_t *err)
+                                                  const int64_t *__restrict__ off, int G, int g0, int g1,
+                                                  int recompute, int32_t *err)
 {
     __shared__ double red[5 * 16];
     for (int gi = blockIdx.x; gi < G; gi += gridDim.x) {
         const int g = cl.order[gi];
+        if (g < g0 || g >= g1) continue;   // uniform over the block
         const DCase &c = cases[cl.cell_case[g]];
-        const int64_t b = off[g], e = off[g + 1];
         double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int64_t kk = b + threadIdx.x; kk < e; kk += blockDim.x) {
-            const P4<T> r = a[kk];
-            add_phi(s, (double)r.u, (double)r.v, (double)r.w);
+        if (recompute) {
+            const int64_t b = off[g], e = off[g + 1];
+            for (int64_t kk = b + threadIdx.x; kk < e; kk += blockDim.x) {
+                const P4<T> r = a[kk];
+                add_phi(s, (double)r.u, (double)r.v, (double)r.w);
+            }
+            block_sum<5>(s, red);
         }
-        block_sum<5>(s, red);
         if (threadIdx.x == 0) {
             bool bad = false;
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
-                double p = c.fac * s[k];
-                cl.psi_p[(int64_t)g * 5 + k] = p;
+                double p;
+                if (recompute) {
+                    p = c.fac * s[k];
+                    cl.psi_p[(int64_t)g * 5 + k] = p;
+                } else {
+                    p = cl.psi_p[(int64_t)g * 5 + k];
+                }
                 if (!isfinite(cl.psi_w[(int64_t)g * 5 + k] + p)) bad = true;
             }
             if (bad) atomicOr(err, ERR_STATE);
@@ -2070,7 +2079,7 @@ __global__ void k_zero_i32(int32_t *a, int n)
 }
 
 template <typename T>
-static void reload_impl(duwp_ctx *ctx)
+static void reload_impl(duwp_ctx *ctx, int g0, int g1, bool recompute)
 {
     const int p = ctx->step & 1, G = ctx->G;
     Cells cl = ctx->cl;
@@ -2078,16 +2087,18 @@ static void reload_impl(duwp_ctx *ctx)
     cl.fix = ctx->fix_buf[p];
     P4<T> *const a = recs<T>(ctx->A[p]);
     hipLaunchKernelGGL(k_moments<T>, dim3(G), dim3(ctx->block_cells), 0, ctx->stream, ctx->d_cases, cl, a,
-                       ctx->off[p], G, ctx->d_err);
+                       ctx->off[p], G, g0, g1, recompute ? 1 : 0, ctx->d_err);
     hipLaunchKernelGGL(k_hist_build<T>, dim3((G + WAVE - 1) / WAVE), dim3(ctx->block_cells), 0, ctx->stream,
                        ctx->d_cases, cl, a, a, ctx->off[p], G, ctx->cap, 1);
 }
 
-// Particle moments and destination histogram of a loaded canonical state.
-void enqueue_moments(duwp_ctx *ctx)
+// Particle moments of cells [g0, g1) of a loaded canonical state (recomputed from
+// the particles, or kept as loaded and only checked), and the destination
+// histogram of all cells.
+void enqueue_moments(duwp_ctx *ctx, int g0, int g1, bool recompute)
 {
-    if (ctx->precision == DUWP_MIXED) reload_impl<float>(ctx);
-    else reload_impl<double>(ctx);
+    if (ctx->precision == DUWP_MIXED) reload_impl<float>(ctx, g0, g1, recompute);
+    else reload_impl<double>(ctx, g0, g1, recompute);
 }
 
 // Normal stress and heat flux of cells [g0, g1) into out (device, [G*5] by global cell).

@@ -54,7 +54,7 @@ class _State(C.Structure):
                 ("x", C.POINTER(C.c_double)), ("u", C.POINTER(C.c_double)),
                 ("v", C.POINTER(C.c_double)), ("w", C.POINTER(C.c_double)),
                 ("off", C.POINTER(C.c_int64)), ("psi_w", C.POINTER(C.c_double)),
-                ("cr_max", C.POINTER(C.c_double))]
+                ("cr_max", C.POINTER(C.c_double)), ("psi_p", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -236,9 +236,11 @@ class Sim:
         off = np.zeros(nc + 1, np.int64)
         psi = np.zeros(nc * 5)
         cr = np.zeros(nc)
-        s = _State(n, nc, step, _p(x), _p(u), _p(v), _p(w), _p(off, C.c_int64), _p(psi), _p(cr))
+        pp = np.zeros(nc * 5)
+        s = _State(n, nc, step, _p(x), _p(u), _p(v), _p(w), _p(off, C.c_int64), _p(psi), _p(cr), _p(pp))
         _check(lib().duwp_get_state(self.ptr, case_id, C.byref(s)), "duwp_get_state")
-        return dict(x=x, u=u, v=v, w=w, off=off, psi_w=psi.reshape(nc, 5), cr_max=cr, step=s.step)
+        return dict(x=x, u=u, v=v, w=w, off=off, psi_w=psi.reshape(nc, 5), cr_max=cr, step=s.step,
+                    psi_p=pp.reshape(nc, 5))
 
     def set_state(self, st: dict, case_id: int = 0) -> None:
         x = np.ascontiguousarray(st["x"], np.float64)
@@ -248,8 +250,12 @@ class Sim:
         off = np.ascontiguousarray(st["off"], np.int64)
         psi = np.ascontiguousarray(st["psi_w"], np.float64).reshape(-1)
         cr = np.ascontiguousarray(st["cr_max"], np.float64)
+        # particle moments travel with the state when it has them (a resume bit for
+        # bit); without them the library sums them from the particles
+        pp = st.get("psi_p")
+        pp = None if pp is None else np.ascontiguousarray(pp, np.float64).reshape(-1)
         s = _State(len(x), len(off) - 1, int(st["step"]), _p(x), _p(u), _p(v), _p(w),
-                   _p(off, C.c_int64), _p(psi), _p(cr))
+                   _p(off, C.c_int64), _p(psi), _p(cr), None if pp is None else _p(pp))
         _check(lib().duwp_set_state(self.ptr, case_id, C.byref(s)), "duwp_set_state")
 
     def profile(self, nsteps: int = 3) -> dict:

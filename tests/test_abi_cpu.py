@@ -47,6 +47,15 @@ def test_case_struct_layout_matches_header():
     assert ctypes.sizeof(duwp._Case) == 4 * 2 + 8 * 18 + 4 * 8 + 8
 
 
+def test_state_struct_layout_matches_header():
+    src = open(os.path.join(ROOT, "include", "duwp.h")).read()
+    body = src[src.index("typedef struct {\n    int64_t n_particles;"):src.index("} duwp_state;")]
+    names = re.findall(r"\b([a-zA-Z_]+)\s*[,;]", re.sub(r"/\*.*?\*/", "", body, flags=re.S))
+    assert names == [f for f, _ in duwp._State._fields_]
+    assert duwp._State.psi_p.offset == 8 + 4 + 4 + 8 * 7
+    assert ctypes.sizeof(duwp._State) == 8 + 4 + 4 + 8 * 8
+
+
 def _init_status(cases, precision=duwp.FP64, block_cells=0):
     arr = (duwp._Case * len(cases))(*[c if isinstance(c, duwp._Case) else duwp.make_case(c) for c in cases])
     o = duwp._Opts()

@@ -228,6 +228,7 @@ def test_restore_in_place_equals_full_rebuild(prec):
     a.step(6)
     states = [a.get_state(k) for k in range(3)]
     changed = dict(states[1])
+    del changed["psi_p"]        # its particles change: the moments are summed afresh
     changed["u"] = -states[1]["u"]
     changed["v"], changed["w"] = states[1]["w"].copy(), states[1]["v"].copy()
     mine = [states[0], changed, states[2]]
@@ -250,16 +251,17 @@ def test_restore_in_place_equals_full_rebuild(prec):
 @pytest.mark.parametrize("prec", [duwp.FP64, duwp.MIXED])
 def test_restore_under_graph_replay_matches_eager(prec):
     # replayed graphs keep working after a restore that changes the step parity:
-    # a context that ran on, rewound to a saved state and replayed its graphs
-    # for three steps ends bit for bit where a fresh eager context restored to
-    # the same state ends (a restore recomputes the particle moments, which a
-    # continuing run sums in another order, so both sides restore)
+    # a context that ran on, rewound to a saved state (particle moments included)
+    # and replayed its graphs for three steps ends bit for bit where it was
+    # before the rewind, and where a fresh eager context restored to the same
+    # state ends
     cases = [CASES["mach3"], CASES["sod_kn1e-4"]]
     _say("graph restore", prec)
     g = duwp.Sim(cases, seed=11, precision=prec, use_graph=True)
     g.step(5)
     saved = [g.get_state(k) for k in range(2)]
     g.step(3)
+    before = [g.get_state(k) for k in range(2)]
     for k in range(2):
         g.set_state(saved[k], k)
     g.step(3)
@@ -269,10 +271,43 @@ def test_restore_under_graph_replay_matches_eager(prec):
     h.step(3)
     for k in range(2):
         a, b = g.get_state(k), h.get_state(k)
-        for key in ("x", "u", "v", "w", "off", "psi_w", "cr_max"):
+        for key in ("x", "u", "v", "w", "off", "psi_w", "cr_max", "psi_p"):
             assert np.array_equal(a[key], b[key]), (k, key)
+            assert np.array_equal(a[key], before[k][key]), (k, key)
     g.close()
     h.close()
+
+
+@pytest.mark.parametrize("prec", [duwp.FP64, duwp.MIXED])
+def test_resume_with_particle_moments_is_bit_for_bit(prec):
+    # the Sod case at Kn 1e-4 absorbs particles (P > 0), so its next step depends
+    # on the particle moments, which the step sums in its own order while it
+    # sorts: a checkpoint that carries them resumes bit for bit, and restoring
+    # one case, with or without them, leaves the other cases' moments alone
+    cases = [CASES["mach3"], CASES["sod_kn1e-4"]]
+    _say("resume with moments", prec)
+    a = duwp.Sim(cases, seed=21, precision=prec)
+    b = duwp.Sim(cases, seed=21, precision=prec)
+    c = duwp.Sim(cases, seed=21, precision=prec)
+    for s in (a, b, c):
+        s.step(6)
+    assert a.diag(1)["n_abs"].sum() > 0
+    b.set_state(b.get_state(1), 1)
+    st = c.get_state(1)
+    del st["psi_p"]
+    c.set_state(st, 1)
+    for s in (a, b, c):
+        s.step(4)
+    keys = ("x", "u", "v", "w", "off", "psi_w", "cr_max", "psi_p")
+    for k in range(2):
+        sa, sb = a.get_state(k), b.get_state(k)
+        for key in keys:
+            assert np.array_equal(sa[key], sb[key]), (k, key)
+    sa, sc = a.get_state(0), c.get_state(0)
+    for key in keys:
+        assert np.array_equal(sa[key], sc[key]), key
+    for s in (a, b, c):
+        s.close()
 
 
 def test_non_finite_state_is_reported():
@@ -336,8 +371,11 @@ def test_fused_moments_equal_recomputed_moments(prec):
     g.step(8)
     for k in range(len(cases)):
         h = duwp.Sim(cases, seed=6, precision=prec)
-        h.set_state(g.get_state(k), k)
+        st = g.get_state(k)
+        del st["psi_p"]             # make the restore sum them from the particles
+        h.set_state(st, k)
         a, b = g.moments(k, duwp.M_PSI_P), h.moments(k, duwp.M_PSI_P)
+        assert np.array_equal(a, g.get_state(k)["psi_p"]), k
         scale = np.abs(b).max(axis=0)[None, :]
         assert np.all(np.abs(a - b) <= 1e-12 * scale), k
         h.close()
