@@ -171,8 +171,9 @@ duwp_status duwp_get_state(duwp_ctx *ctx, int32_t case_id, duwp_state *st);
 
 /* Replace one case's state (and the context's step index) from host buffers.  The
  * particle moments of the case's cells are loaded from psi_p, or recomputed from
- * the particles when psi_p is NULL (a state whose particles were changed must not
- * bring the old psi_p); other cases keep theirs.  The case keeps its place among
+ * the particles when psi_p is NULL (a state whose particles were changed, or one
+ * saved by a context of the other precision, whose particles the load rounds, must
+ * not bring the old psi_p); other cases keep theirs.  The case keeps its place among
  * the others.
  * With the case's particle count unchanged only its records move (host work in
  * proportion to the case); otherwise the whole canonical array makes a round trip

@@ -251,7 +251,9 @@ class Sim:
         psi = np.ascontiguousarray(st["psi_w"], np.float64).reshape(-1)
         cr = np.ascontiguousarray(st["cr_max"], np.float64)
         # particle moments travel with the state when it has them (a resume bit for
-        # bit); without them the library sums them from the particles
+        # bit); without them the library sums them from the particles.  Drop
+        # "psi_p" from a state whose particles were edited or that another
+        # precision saved.
         pp = st.get("psi_p")
         pp = None if pp is None else np.ascontiguousarray(pp, np.float64).reshape(-1)
         s = _State(len(x), len(off) - 1, int(st["step"]), _p(x), _p(u), _p(v), _p(w),
