@@ -240,7 +240,7 @@ class Sim:
         s = _State(n, nc, step, _p(x), _p(u), _p(v), _p(w), _p(off, C.c_int64), _p(psi), _p(cr), _p(pp))
         _check(lib().duwp_get_state(self.ptr, case_id, C.byref(s)), "duwp_get_state")
         return dict(x=x, u=u, v=v, w=w, off=off, psi_w=psi.reshape(nc, 5), cr_max=cr, step=s.step,
-                    psi_p=pp.reshape(nc, 5))
+                    psi_p=pp.reshape(nc, 5), precision=self.precision)
 
     def set_state(self, st: dict, case_id: int = 0) -> None:
         x = np.ascontiguousarray(st["x"], np.float64)
@@ -251,10 +251,12 @@ class Sim:
         psi = np.ascontiguousarray(st["psi_w"], np.float64).reshape(-1)
         cr = np.ascontiguousarray(st["cr_max"], np.float64)
         # particle moments travel with the state when it has them (a resume bit for
-        # bit); without them the library sums them from the particles.  Drop
-        # "psi_p" from a state whose particles were edited or that another
-        # precision saved.
+        # bit); without them the library sums them from the particles.  A state
+        # that the other precision saved leaves them behind (the load rounds its
+        # particles); drop "psi_p" from one whose particles were edited.
         pp = st.get("psi_p")
+        if st.get("precision", self.precision) != self.precision:
+            pp = None
         pp = None if pp is None else np.ascontiguousarray(pp, np.float64).reshape(-1)
         s = _State(len(x), len(off) - 1, int(st["step"]), _p(x), _p(u), _p(v), _p(w),
                    _p(off, C.c_int64), _p(psi), _p(cr), None if pp is None else _p(pp))
