@@ -12,8 +12,10 @@ the start of each step, summed over the timed steps, over the wall time).
 Also reported (legs): the batched form (256 independent uneven shock and Sod
 cases in one context, against the plain FP64 path), the large near-continuum
 Mach-10 case (20000 cells, 1e9 particles, most mass in the wave part), the
-roofline of the dominant kernel, the step's effective bandwidth and the CPU
-oracle on the same state.  Prints one JSON line.
+roofline of the dominant kernel, the step's effective bandwidth, the mixed
+path's profile error (its time-averaged rho, U, T against the FP64 path's,
+beside the gap between two FP64 seeds) and the CPU oracle on the same state.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -22,6 +24,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -119,6 +123,7 @@ def run_path(cases, precision, steps, warmup, graph, seed=1, block_cells=0):
     t = time.perf_counter()
     sim.step(warmup)
     log(f"  warmup {warmup} steps in {time.perf_counter() - t:.2f}s, N={sim.total_particles()}")
+    sim.reset_average()      # the timed steps' time average (summed inside the step anyway)
     sim.particle_steps(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -127,6 +132,15 @@ def run_path(cases, precision, steps, warmup, graph, seed=1, block_cells=0):
     t1 = time.perf_counter()
     ps = sim.particle_steps(reset=True)
     return sim, ps, t1 - t0
+
+
+def profile_gap(a, b):
+    """Largest difference of two time-averaged (rho, U, T) profiles over the cells,
+    relative to the largest magnitude of the second."""
+    out = {}
+    for name, k in (("rho", 0), ("U", 1), ("T", 4)):
+        out[name] = float(np.abs(a[:, k] - b[:, k]).max() / np.abs(b[:, k]).max())
+    return out
 
 
 def block_size(cases, precision, args):
@@ -276,6 +290,7 @@ def main():
     value = dt = None
     n_now = None
     roofline = kernels = cpu = fp64 = None
+    avg_mixed = prof_err = None
     bc = bc64 = None
     if "main" in legs:
         bc, bc_src = block_size([case], duwp.MIXED, args)
@@ -283,6 +298,7 @@ def main():
         sim, ps, dt = run_path([case], duwp.MIXED, args.steps, args.warmup, graph, block_cells=bc)
         value = ps / dt
         n_now = sim.total_particles()
+        avg_mixed = sim.moments(0, duwp.M_AVG_PRIM)
         log(f"  {args.steps} steps in {dt:.3f}s -> {value:.4e} particle-steps/s")
         # per-kernel device time (HIP events on the library's stream, eager launches)
         roofline, kernels = roofline_of(sim, args.profile_steps, case.name, bc)
@@ -317,7 +333,22 @@ def main():
         s64, ps64, dt64 = run_path([case], duwp.FP64, args.steps, args.warmup, graph, block_cells=bc64)
         fp64 = ps64 / dt64
         log(f"  {args.steps} steps in {dt64:.3f}s -> {fp64:.4e} particle-steps/s")
+        avg64 = s64.moments(0, duwp.M_AVG_PRIM)
         s64.close()
+        # the profile error of the mixed path: its time-averaged profiles against
+        # the FP64 path's over the same steps, beside two FP64 runs that differ
+        # only in the seed.  Both paths draw from the same seed, so their samples
+        # stay correlated for a while; a gap within the seed-to-seed one says the
+        # FP32 particles add nothing that this sample size can resolve
+        s64b, _, _ = run_path([case], duwp.FP64, args.steps, args.warmup, graph, seed=2, block_cells=bc64)
+        avg64b = s64b.moments(0, duwp.M_AVG_PRIM)
+        s64b.close()
+        if avg_mixed is not None:
+            prof_err = {"quantity": f"rho, U, T averaged over the {args.steps} timed steps",
+                        "norm": "max over cells of |a - b| / max over cells of |b|",
+                        "mixed_vs_fp64": profile_gap(avg_mixed, avg64),
+                        "fp64_seed_to_seed": profile_gap(avg64b, avg64)}
+            log("  profile error:", json.dumps(prof_err))
 
     extra = {}
     for leg, fn in (("batched", lambda: leg_batched(args, graph, legs)), ("large", lambda: leg_large(args, graph))):
@@ -361,6 +392,7 @@ def main():
         "fp64_value": fp64,
         "mixed_over_fp64": (value / fp64) if (fp64 and value) else None,
         "fp64_block_cells": bc64,
+        "profile_error": prof_err,
         "kernels_ms": kernels,
         "batched": extra["batched"],
         "large": extra["large"],
