@@ -268,18 +268,21 @@ static void maxwell_sample(double U, double V, double W, double T, double R,
 }
 
 /* ------------------------------------------------------------------------ */
-static void *xrealloc(void *p, size_t n) { void *q = realloc(p, n ? n : 1); return q; }
+/* Grow *p to n doubles; on failure *p is left as it was (still owned by the caller). */
+static int regrow(double **p, int64_t n)
+{
+    double *q = realloc(*p, (size_t)(n ? n : 1) * sizeof(double));
+    if (!q) return -1;
+    *p = q;
+    return 0;
+}
 
 static int reserve(orc_state *s, int64_t need)
 {
     if (need <= s->cap) return 0;
     int64_t nc = s->cap ? s->cap : 1024;
     while (nc < need) nc *= 2;
-    s->x = xrealloc(s->x, (size_t)nc * sizeof(double));
-    s->u = xrealloc(s->u, (size_t)nc * sizeof(double));
-    s->v = xrealloc(s->v, (size_t)nc * sizeof(double));
-    s->w = xrealloc(s->w, (size_t)nc * sizeof(double));
-    if (!s->x || !s->u || !s->v || !s->w) return -1;
+    if (regrow(&s->x, nc) || regrow(&s->u, nc) || regrow(&s->v, nc) || regrow(&s->w, nc)) return -1;
     s->cap = nc;
     return 0;
 }
@@ -552,6 +555,16 @@ static int64_t cell_of(const orc_state *s, double x)
 
 typedef struct { double x, u, v, w; int64_t cell; } ipart;
 
+/* Double the intermediate array; on failure it is left as it was. */
+static int grow(ipart **ib, int64_t *icap)
+{
+    ipart *q = realloc(*ib, (size_t)(*icap * 2) * sizeof(ipart));
+    if (!q) return -1;
+    *ib = q;
+    *icap *= 2;
+    return 0;
+}
+
 /* One DUWP step (Sec. 3.4, Steps 2-3) over the stages in mask. */
 int orc_step_masked(orc_state *s, int32_t mask)
 {
@@ -571,10 +584,11 @@ int orc_step_masked(orc_state *s, int32_t mask)
      * by the cell reached (sources in ascending order), and whether any did */
     double *wab = calloc((size_t)C * 5, sizeof(double));
     int *wabin = calloc((size_t)C, sizeof(int));
-    if (!Wt || !Pc || !ok || !psi_w0 || !tauc || !wab || !wabin) {
-        free(Wt); free(Pc); free(ok); free(psi_w0); free(tauc); free(wab); free(wabin);
-        return -1;
-    }
+    /* intermediate array and the wave-update and sort buffers (below) */
+    ipart *ib = NULL;
+    int64_t *ioff = NULL, *cnt = NULL;
+    double *F = NULL, *D = NULL;
+    if (!Wt || !Pc || !ok || !psi_w0 || !tauc || !wab || !wabin) { err = -1; goto done; }
     for (int c = 0; c < C; ++c) {
         double t[5];
         for (int k = 0; k < 5; ++k) t[k] = s->psi_w[c * 5 + k] + s->psi_p[c * 5 + k];
@@ -596,12 +610,9 @@ int orc_step_masked(orc_state *s, int32_t mask)
     /* Intermediate array: per cell [survivors in canonical order][new by slot],
      * then injected entrants.  Sized generously and grown as needed. */
     int64_t icap = s->n + 1024, ni = 0;
-    ipart *ib = malloc((size_t)icap * sizeof(ipart));
-    int64_t *ioff = malloc(((size_t)C + 1) * sizeof(int64_t));
-    if (!ib || !ioff) {
-        free(ib); free(ioff); free(Wt); free(Pc); free(ok); free(psi_w0); free(tauc); free(wab); free(wabin); free(tauc); free(wab); free(wabin);
-        return -1;
-    }
+    ib = malloc((size_t)icap * sizeof(ipart));
+    ioff = malloc(((size_t)C + 1) * sizeof(int64_t));
+    if (!ib || !ioff) { err = -1; goto done; }
 
     for (int c = 0; c < C; ++c) {
         ioff[c] = ni;
@@ -647,7 +658,7 @@ int orc_step_masked(orc_state *s, int32_t mask)
                     wabin[cland] = 1;
                 }
             } else {
-                if (ni >= icap) { icap *= 2; ib = realloc(ib, (size_t)icap * sizeof(ipart)); if (!ib) return -1; }
+                if (ni >= icap && grow(&ib, &icap)) { err = -1; goto done; }
                 ipart p = { s->x[k], s->u[k], s->v[k], s->w[k], c };
                 ib[ni++] = p;
             }
@@ -680,7 +691,7 @@ int orc_step_masked(orc_state *s, int32_t mask)
                 double xi[3];
                 maxwell_sample(Wc[1], Wc[2], Wc[3], Wc[4], R, uu, xi);
                 ipart p = { cs->x_lo + ((double)c + u01(a[0])) * dx, xi[0], xi[1], xi[2], c };
-                if (ni >= icap) { icap *= 2; ib = realloc(ib, (size_t)icap * sizeof(ipart)); if (!ib) return -1; }
+                if (ni >= icap && grow(&ib, &icap)) { err = -1; goto done; }
                 ib[ni++] = p;
                 ss[0] += 1.0; ss[1] += xi[0]; ss[2] += xi[1]; ss[3] += xi[2];
                 ss[4] += 0.5 * (xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
@@ -783,7 +794,7 @@ int orc_step_masked(orc_state *s, int32_t mask)
                 p.x = p.x + p.u * dt;
                 if (!apply_bc(cs, &p.x, &p.u)) continue;
                 p.cell = cell_of(s, p.x);
-                if (ni >= icap) { icap *= 2; ib = realloc(ib, (size_t)icap * sizeof(ipart)); if (!ib) return -1; }
+                if (ni >= icap && grow(&ib, &icap)) { err = -1; goto done; }
                 ib[ni++] = p;
                 s->d_inj[side]++;
             }
@@ -794,9 +805,9 @@ int orc_step_masked(orc_state *s, int32_t mask)
      * state (Eq. r1, wave term).  Ghost states: the reservoir state, or the
      * mirror image of the boundary cell at a wall. ---- */
     if (mask & ORC_WAVE) {
-        double *F = calloc(((size_t)C + 1) * 5, sizeof(double));
-        double *D = calloc((size_t)C * 5, sizeof(double));
-        if (!F || !D) { free(F); free(D); return -1; }
+        F = calloc(((size_t)C + 1) * 5, sizeof(double));
+        D = calloc((size_t)C * 5, sizeof(double));
+        if (!F || !D) { err = -1; goto done; }
         double G0[5], G1[5];
         ghost_state(cs, 0, Wt, G0);
         ghost_state(cs, 1, Wt + (C - 1) * 5, G1);
@@ -832,19 +843,17 @@ int orc_step_masked(orc_state *s, int32_t mask)
             int okr = (f == C) ? okg1 : ok[f];
             if (okl && okr) orc_wave_flux2(s, Wl, Wr, ql, qr, F + f * 5);
         }
-        free(D);
         double r = dt / dx;
         for (int c = 0; c < C; ++c)
             for (int k = 0; k < 5; ++k)
                 s->psi_w[c * 5 + k] -= r * (F[(c + 1) * 5 + k] - F[c * 5 + k]);
-        free(F);
     }
 
     /* ---- O7: stable counting sort of the intermediate array by cell; the
      * result is the next canonical array. ---- */
-    if (reserve(s, ni)) return -1;
-    int64_t *cnt = calloc((size_t)C + 1, sizeof(int64_t));
-    if (!cnt) return -1;
+    if (reserve(s, ni)) { err = -1; goto done; }
+    cnt = calloc((size_t)C + 1, sizeof(int64_t));
+    if (!cnt) { err = -1; goto done; }
     for (int64_t k = 0; k < ni; ++k) cnt[ib[k].cell + 1]++;
     for (int c = 0; c < C; ++c) cnt[c + 1] += cnt[c];
     memcpy(s->off, cnt, ((size_t)C + 1) * sizeof(int64_t));
@@ -853,13 +862,14 @@ int orc_step_masked(orc_state *s, int32_t mask)
         s->x[d] = ib[k].x; s->u[d] = ib[k].u; s->v[d] = ib[k].v; s->w[d] = ib[k].w;
     }
     s->n = ni;
-    free(cnt);
-    free(ib); free(ioff); free(Wt); free(Pc); free(ok); free(psi_w0);
 
     /* ---- O9: moments of the new state and the running average of Psi_t. ---- */
     particle_moments(s);
     accumulate_average(s);
     s->step += 1;
+done:
+    free(cnt); free(F); free(D); free(ib); free(ioff);
+    free(Wt); free(Pc); free(ok); free(psi_w0); free(tauc); free(wab); free(wabin);
     return err;
 }
 

@@ -835,3 +835,163 @@ def test_resample_count_is_the_unabsorbed_share_of_the_wave_mass():
     n = np.diff(o.get_state()["off"])
     exact = (1.0 - 2.0 / 3.0) * mw / c.m_particle
     assert np.all(n >= np.floor(exact)) and np.all(n <= np.floor(exact) + 1), (n, exact)
+
+
+# --------------------------------------------------------------------------
+# Viscous part of the wave flux (Sec. 3.3, Eq. ce2 with eps of Eq. vp1)
+# --------------------------------------------------------------------------
+
+def _bird_mu(c, T):
+    """Bird's VHS viscosity 15 sqrt(pi m k T_ref) / (2 pi d^2 (5-2w)(7-2w)) (T/T_ref)^w."""
+    w, m, d = c.omega, c.m_mol, c.d_ref
+    return 15.0 * math.sqrt(math.pi * m * I.KB * c.T_ref) / (2.0 * math.pi * d * d * (5 - 2 * w) * (7 - 2 * w)) \
+        * (T / c.T_ref) ** w
+
+
+@pytest.mark.parametrize("which", ["U", "V", "T"])
+def test_wave_flux_viscous_terms_are_navier_stokes_with_eps(which):
+    """Two argon states that differ only in U, only in V or only in T, with dt about twice
+    the interface's mean collision time (P_m ~ 1/2, eps_1 ~ 0.7): the flux minus P_m times
+    the split Maxwellian flux (pinned by quadrature above) is -P_m times the NS closure,
+    sigma_xx = (4/3) eps mu dU/dx, sigma_xy = eps mu dV/dx, q = -(15/4) R eps mu dT/dx and
+    the work term U sigma_xx + V sigma_xy, with Bird's viscosity at the mean state and
+    central gradients.  Momentum flows against dU/dx and heat down dT/dx."""
+    c = I.argon_shock(3.0, 100, 50.0, 2e4)
+    rho, T0, U0, V0 = c.rho_L, 300.0, 400.0, 30.0
+    Wl = np.array([rho, U0, V0, 0.0, T0])
+    Wr = Wl.copy()
+    jump = {"U": (1, 40.0), "V": (2, 25.0), "T": (4, 45.0)}[which]
+    Wr[jump[0]] += jump[1]
+    Wm = 0.5 * (Wl + Wr)
+    mu = _bird_mu(c, Wm[4])
+    tau = mu / (Wm[0] * c.R * Wm[4])
+    c.dt = 2.0 * tau
+    o = O.Oracle(c)
+    F = o.wave_flux(Wl, Wr)
+    x = c.dt / tau
+    Pm = 1.0 - tau / c.dt
+    eps = 1.0 - x / math.expm1(x)
+    Finv = Wl[0] * O.kfvs_half(Wl, c.R, +1) + Wr[0] * O.kfvs_half(Wr, c.R, -1)
+    visc = -(F - Pm * Finv) / Pm
+    g = (Wr - Wl) / c.dx
+    mue = eps * mu
+    sxx, sxy, q = (4.0 / 3.0) * mue * g[1], mue * g[2], -(15.0 / 4.0) * c.R * mue * g[4]
+    want = np.array([0.0, sxx, sxy, 0.0, Wm[1] * sxx + Wm[2] * sxy - q])
+    scale = np.abs(want).max()
+    assert scale > 1e-3 * np.abs(Finv).max()          # the viscous part is resolved
+    assert np.allclose(visc, want, rtol=1e-9, atol=1e-12 * scale), (which, visc, want)
+    # directions fixed by physics: x-momentum flux lowered where U rises, y-momentum
+    # against dV/dx, energy flux lowered where T rises
+    dF = F - Pm * Finv
+    tiny = 1e-12 * scale
+    if which == "U":
+        assert dF[1] < 0 and abs(dF[2]) < tiny
+    elif which == "V":
+        assert dF[2] < 0 and abs(dF[1]) < tiny
+    else:
+        assert dF[4] < 0 and abs(dF[1]) < tiny and abs(dF[2]) < tiny
+
+
+# --------------------------------------------------------------------------
+# (sigma c_r)_max of NTC: frozen during a step, then the largest c_r sampled (App. A)
+# --------------------------------------------------------------------------
+
+def _philox_words(o, seed, case_id, a, b, tag, j):
+    key = [seed & 0xFFFFFFFF, ((seed >> 32) + case_id) & 0xFFFFFFFF]
+    return [int(v) for v in O.philox([o.step_index, a, b, (tag << 16) | j], key)]
+
+
+def _replay_collisions(o, c, st, cr0, seed):
+    """The collide stage of one step replayed candidate by candidate from its definition
+    (Appendix A, NTC with the frozen c_m of each cell): returns the velocities after it,
+    the accepted collisions and the largest c_r sampled per cell."""
+    k = o.constants()
+    u = np.stack([st["u"], st["v"], st["w"]], axis=1).copy()
+    off = st["off"]
+    prim = o.cells()["prim"]
+    acc = np.zeros(c.ncells, np.int64)
+    seen = np.zeros(c.ncells)
+    ncand = np.zeros(c.ncells, np.int64)
+    for cell in range(c.ncells):
+        N = int(off[cell + 1] - off[cell])
+        if N < 2:
+            continue
+        cm = cr0[cell]
+        Mr = 0.5 * (N - 1) * k["coll_k"] * prim[cell, 0] * (k["c_ref"] / cm) ** (2 * k["upsilon"]) * cm * c.dt
+        M = int(math.floor(Mr + _philox_words(o, seed, 0, cell, 0, 4, 0)[0] / 2.0 ** 32))
+        ncand[cell] = M
+        seg = u[off[cell]:off[cell + 1]]
+        for q in range(M):
+            a = _philox_words(o, seed, 0, cell, q, 5, 0)
+            b = _philox_words(o, seed, 0, cell, q, 5, 1)
+            i = (((a[0] << 32) | a[1]) * N) >> 64
+            j = (((a[2] << 32) | a[3]) * (N - 1)) >> 64
+            j += j >= i
+            d = seg[i] - seg[j]
+            cr = math.sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])
+            seen[cell] = max(seen[cell], cr)
+            if b[0] / 2.0 ** 32 < (cr / cm) ** (1.0 - 2.0 * k["upsilon"]):
+                seg[i], seg[j] = O.scatter_pair(seg[i], seg[j], b[1] / 2.0 ** 32, b[2] / 2.0 ** 32)
+                acc[cell] += 1
+    return u, acc, ncand, seen
+
+
+@pytest.mark.parametrize("scale", [1e-3, 100.0])
+def test_cr_max_is_frozen_in_a_step_and_ends_as_the_largest_sampled_speed(scale):
+    """A box at P = 0 whose (sigma c_r)_max starts far below (1e-3 of) or far above (100x)
+    the thermal speed.  Frozen below every c_r, every candidate is accepted (an estimate
+    raised during the step would reject some); the step ends with c_max = max c_r of its
+    candidates.  Frozen far above, it stays unchanged.  The replay draws the pairs from
+    the Philox words and scatters them with the pinned pair collision."""
+    c = _box(0.9, ppc=400, ncells=6)
+    seed = 9
+    o = O.Oracle(c, seed=seed)
+    _to_particles(o)
+    st = o.get_state()
+    cr0 = np.full(c.ncells, scale * math.sqrt(c.R * c.T_L))
+    st["cr_max"] = cr0.copy()
+    o.set_state(st)
+    u_want, acc, ncand, seen = _replay_collisions(o, c, st, cr0, seed)
+    o.step_masked(O.COLLIDE)
+    d = o.diag()
+    s1 = o.get_state()
+    assert np.array_equal(d["n_cand"], ncand) and ncand.sum() > 20
+    assert np.array_equal(d["n_coll"], acc)
+    assert np.array_equal(np.stack([s1["u"], s1["v"], s1["w"]], axis=1), u_want)
+    if scale < 1:
+        assert np.array_equal(acc, ncand)                   # all accepted: c_m frozen
+        assert np.array_equal(s1["cr_max"], np.maximum(cr0, seen))
+        assert np.all(s1["cr_max"] > cr0)
+    else:
+        assert acc.sum() < ncand.sum()
+        assert np.array_equal(s1["cr_max"], cr0)
+
+
+# --------------------------------------------------------------------------
+# Stable counting sort (O7): order inside a destination cell
+# --------------------------------------------------------------------------
+
+def test_sort_keeps_the_intermediate_order_inside_each_cell():
+    """A stream-only step of a developed Sod state between walls: the new canonical array
+    is the intermediate array (here the old canonical array, streamed with its wall
+    reflections) reordered by a stable argsort of the destination cell.  Particles of
+    several source cells share destinations, so any reordering inside a cell shows."""
+    c = I.sod_paper(1e-2)
+    o = O.Oracle(c, seed=4)
+    o.step(3)
+    st = o.get_state()
+    x = st["x"] + st["u"] * c.dt
+    u = st["u"].copy()
+    for _ in range(4):
+        lo, hi = x < c.x_lo, x > c.x_hi
+        x = np.where(lo, 2 * c.x_lo - x, np.where(hi, 2 * c.x_hi - x, x))
+        u = np.where(lo | hi, -u, u)
+    cell = np.clip(np.floor((x - c.x_lo) / c.dx).astype(np.int64), 0, c.ncells - 1)
+    src = np.repeat(np.arange(c.ncells), np.diff(st["off"]))
+    assert (cell != src).sum() > 100
+    perm = np.argsort(cell, kind="stable")
+    o.step_masked(O.STREAM)
+    s1 = o.get_state()
+    assert np.array_equal(s1["off"], np.r_[0, np.cumsum(np.bincount(cell, minlength=c.ncells))])
+    assert np.array_equal(s1["x"], x[perm]) and np.array_equal(s1["u"], u[perm])
+    assert np.array_equal(s1["v"], st["v"][perm]) and np.array_equal(s1["w"], st["w"][perm])
