@@ -13,9 +13,12 @@
  *
  * Conventions
  *  - Every call returns a duwp_status (0 = OK).  No exception crosses the ABI.
- *  - The context owns all device memory; it allocates with hipMalloc at
- *    duwp_init and frees in duwp_destroy.  Host buffers passed to accessors
- *    are owned by the caller and must hold the documented number of elements.
+ *  - The context owns all device memory: it allocates every buffer at
+ *    duwp_init, through the caller's allocator when duwp_opts gives one (the
+ *    Python binding passes torch's caching allocator) and with hipMalloc
+ *    otherwise, and frees them in duwp_destroy.  No other call allocates device
+ *    memory.  Host buffers passed to accessors are owned by the caller and must
+ *    hold the documented number of elements.
  *  - Work is queued on the stream given in duwp_opts (NULL: the null stream).
  *    duwp_step returns after the queued steps finish and the device error
  *    word has been read; the error is then reported as a status.
@@ -82,6 +85,28 @@ typedef struct {
     int64_t capacity;             /* particle capacity of this case; 0 = derived from the mass */
 } duwp_case;
 
+/* Tile shapes and thresholds of the step's kernels (the autotuner's knobs).  A
+ * zero selects the default.  None of them changes an integer result (the sort
+ * is stable and the collisions keep their sequential order whatever the
+ * tiling), and only scatter_items (like block_cells) changes a floating one: it
+ * sets the order in which the scatter sums each cell's particle moments, so
+ * those agree to rounding. */
+typedef struct {
+    int32_t scatter_items;        /* particles per thread and chunk of multi-wave scatter blocks: 2 or 4 (0: 4) */
+    int32_t big_block;            /* threads (candidates per chunk) of the block-per-cell collide:
+                                     256, 512 or 1024 (0: 512 with FP32 particles, 256 with FP64) */
+    int32_t big_blocks_per_cu;    /* resident blocks of that kernel per compute unit: 1 or 2 (0: 2; a
+                                     1024-thread block with FP64 particles needs 1) */
+    int32_t big_min_particles;    /* a cell collides in that kernel when it holds at least this many
+                                     particles ... (0: 4096; at least 64) */
+    int32_t big_min_candidates;   /* ... and draws at least this many candidates (0: 4096; at least 64) */
+    int32_t collide_by_cell_max;  /* up to this many cells in all a wave per cell runs the other cells'
+                                     collisions, beyond it work items cut from the candidate list (0: 8192) */
+    int32_t count_dests;          /* destination cells per block of the sort's count and base kernels
+                                     on large grids, a multiple of 4 in 4..256 (0: 256) */
+    int32_t reserved;             /* 0 */
+} duwp_tune;
+
 typedef struct {
     uint64_t seed;                /* Philox key: (low 32 bits, high 32 bits + case index) */
     int32_t precision;            /* DUWP_FP64 or DUWP_MIXED */
@@ -89,7 +114,17 @@ typedef struct {
     void *stream;                 /* hipStream_t, or NULL */
     double headroom;              /* capacity = headroom * mass / m_particle when capacity = 0 (<= 0: 1.5) */
     int32_t block_cells;          /* threads per block of the per-cell kernels, 64..512 (0: 256) */
-    int32_t reserved;
+    int32_t reserved;             /* 0 */
+    /* Device memory provider.  alloc = NULL: hipMalloc and hipFree.  Otherwise
+     * duwp_init takes every device buffer from alloc(bytes, alloc_ctx) (device
+     * memory of the current device, at least 256-byte aligned, NULL on failure,
+     * usable from any stream), and duwp_destroy returns each through
+     * free(ptr, alloc_ctx) after the context's streams have finished.  free must
+     * be given with alloc. */
+    void *(*alloc)(size_t bytes, void *alloc_ctx);
+    void (*free)(void *ptr, void *alloc_ctx);
+    void *alloc_ctx;
+    duwp_tune tune;
 } duwp_opts;
 
 typedef struct duwp_ctx duwp_ctx;
@@ -100,7 +135,9 @@ typedef struct duwp_ctx duwp_ctx;
  * particle part (Eq. gkt_moment0 over the cell's particles, per unit area), or
  * NULL.  The step sums it in its own order while it sorts; a restore that
  * brings it back resumes bit for bit, one without it sums it afresh from the
- * particles (equal up to rounding order). */
+ * particles (equal up to rounding order).  avg_sum: [ncells*5], the running
+ * sum of Psi_t behind the time average (DUWP_M_AVG_*), or NULL; avg_count: the
+ * number of steps in it, which the context shares among its cases. */
 typedef struct {
     int64_t n_particles;
     int32_t ncells;
@@ -110,6 +147,8 @@ typedef struct {
     double *psi_w;
     double *cr_max;
     double *psi_p;
+    double *avg_sum;
+    int64_t avg_count;
 } duwp_state;
 
 /* What duwp_moments returns, each [ncells*5] doubles */
@@ -133,9 +172,11 @@ enum {
 /* Create a context holding ncases independent cases; all cases step together.
  * Fails with DUWP_EINVAL on an invalid case (ncells <= 0, x_hi <= x_lo, m_particle
  * or dt <= 0, no gas constants, a mode field out of its range, reserved_case not 0)
- * or options (precision, block_cells not a multiple of 64 up to 512), checked before
- * any device call; DUWP_ENOMEM when buffers do not fit.  The initial
- * state puts all mass in the wave part (no particles), the first step samples them. */
+ * or options (precision, block_cells not a multiple of 64 up to 512, a tuning
+ * field out of its range, alloc without free), checked before any device call;
+ * DUWP_ENOMEM when buffers do not fit (everything allocated so far is returned).
+ * The initial state puts all mass in the wave part (no particles), the first
+ * step samples them. */
 duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, const duwp_opts *opts);
 
 /* Advance all cases by nsteps >= 0 steps (Sec. 3.4, Steps 2-3, then Eq. r1).
@@ -166,19 +207,23 @@ duwp_status duwp_diag(duwp_ctx *ctx, int32_t case_id, int32_t *n_abs, int32_t *n
                       int32_t *n_cand, int32_t *n_coll, int64_t *n_inj, int64_t *n_out);
 
 /* Copy one case's state to host buffers sized from duwp_counts (checkpoint, parity).
- * A NULL array is skipped. */
+ * A NULL array is skipped; avg_count is always written. */
 duwp_status duwp_get_state(duwp_ctx *ctx, int32_t case_id, duwp_state *st);
 
 /* Replace one case's state (and the context's step index) from host buffers.  The
  * particle moments of the case's cells are loaded from psi_p, or recomputed from
  * the particles when psi_p is NULL (a state whose particles were changed, or one
  * saved by a context of the other precision, whose particles the load rounds, must
- * not bring the old psi_p); other cases keep theirs.  The case keeps its place among
- * the others.
- * With the case's particle count unchanged only its records move (host work in
- * proportion to the case); otherwise the whole canonical array makes a round trip
- * through the host.  DUWP_EINVAL if offsets are not monotone, DUWP_ECAPACITY if it
- * does not fit. */
+ * not bring the old psi_p); other cases keep theirs.  With avg_sum the case's
+ * running sums are loaded and the context's step count of the average becomes
+ * avg_count (restore every case of a checkpoint with the same count); without,
+ * both stay as they are.  The case keeps its place among the others.
+ * Host work and transfers are in proportion to the case: its records are uploaded,
+ * and when its particle count changes the later cases' records move on the
+ * device.  The call clears the context's device error word first, so a context
+ * can be reset after DUWP_ECAPACITY, DUWP_ERANGE or DUWP_ESTATE.
+ * DUWP_EINVAL if offsets are not monotone, DUWP_ECAPACITY if it does not fit,
+ * DUWP_ESTATE if a loaded cell total is not finite. */
 duwp_status duwp_set_state(duwp_ctx *ctx, int32_t case_id, const duwp_state *st);
 
 /* Average device duration in ms of each kernel of the step over nsteps eager steps

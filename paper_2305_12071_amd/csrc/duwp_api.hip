@@ -21,6 +21,21 @@ constexpr double kPi = 3.14159265358979323846;
         if ((expr) != hipSuccess) return DUWP_EDEVICE; \
     } while (0)
 
+bool tune_valid(const duwp_tune &t, int precision)
+{
+    if (t.reserved != 0) return false;
+    if (t.scatter_items != 0 && t.scatter_items != 2 && t.scatter_items != 4) return false;
+    if (t.big_block != 0 && t.big_block != 256 && t.big_block != 512 && t.big_block != 1024) return false;
+    if (t.big_blocks_per_cu < 0 || t.big_blocks_per_cu > 2) return false;
+    // a 1024-thread FP64 block needs more than half the compute unit's LDS
+    if (precision == DUWP_FP64 && t.big_block == 1024 && t.big_blocks_per_cu == 2) return false;
+    if (t.big_min_particles < 0 || (t.big_min_particles > 0 && t.big_min_particles < 64)) return false;
+    if (t.big_min_candidates < 0 || (t.big_min_candidates > 0 && t.big_min_candidates < 64)) return false;
+    if (t.collide_by_cell_max < 0) return false;
+    if (t.count_dests < 0 || t.count_dests % 4 || t.count_dests > 256) return false;
+    return true;
+}
+
 bool case_valid(const duwp_case &c)
 {
     if (c.ncells <= 0 || !(c.x_hi > c.x_lo) || !(c.m_particle > 0.0) || !(c.dt > 0.0)) return false;
@@ -87,11 +102,23 @@ int64_t inject_bound(const duwp_case &c, int side)
     return (int64_t)std::ceil(rho * Lg / c.m_particle) + 2;
 }
 
+// one device buffer from the caller's allocator, or hipMalloc; every buffer is
+// listed for duwp_destroy
 template <typename P>
 duwp_status dalloc(duwp_ctx *ctx, P **p, size_t bytes)
 {
     void *q = nullptr;
-    if (hipMalloc(&q, bytes ? bytes : 64) != hipSuccess) return DUWP_ENOMEM;
+    bytes = bytes ? (bytes + 255) / 256 * 256 : 256;
+    if (ctx->alloc_fn) {
+        q = ctx->alloc_fn(bytes, ctx->alloc_ctx);
+        if (!q) return DUWP_ENOMEM;
+        if (((uintptr_t)q & 255) != 0) {      // the records and histograms need the alignment
+            ctx->free_fn(q, ctx->alloc_ctx);
+            return DUWP_ENOMEM;
+        }
+    } else if (hipMalloc(&q, bytes) != hipSuccess) {
+        return DUWP_ENOMEM;
+    }
     ctx->allocs.push_back(q);
     *p = (P *)q;
     return DUWP_OK;
@@ -282,11 +309,11 @@ duwp_status build_graphs(duwp_ctx *ctx)
     return DUWP_OK;
 }
 
-// host copy of the canonical offsets of the current parity
-duwp_status host_offsets(duwp_ctx *ctx, std::vector<int64_t> &off)
+// host copy of the canonical offsets of one case's cells (ncells + 1 values) at the current parity
+duwp_status case_offsets(duwp_ctx *ctx, const DCase &d, std::vector<int64_t> &off)
 {
-    off.resize((size_t)ctx->G + 1);
-    HIP_OK(hipMemcpyAsync(off.data(), ctx->off[ctx->step & 1], 8 * off.size(), hipMemcpyDeviceToHost,
+    off.resize((size_t)d.ncells + 1);
+    HIP_OK(hipMemcpyAsync(off.data(), ctx->off[ctx->step & 1] + d.cell_base, 8 * off.size(), hipMemcpyDeviceToHost,
                           ctx->stream));
     HIP_OK(hipStreamSynchronize(ctx->stream));
     return DUWP_OK;
@@ -333,8 +360,12 @@ void duwp_destroy(duwp_ctx *ctx)
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (auto &g : ctx->graph)
         if (g) (void)hipGraphExecDestroy(g);
+    if (ctx->stream2) (void)hipStreamSynchronize(ctx->stream2);
     for (hipEvent_t e : ctx->timer.ev) (void)hipEventDestroy(e);
-    for (void *p : ctx->allocs) (void)hipFree(p);
+    for (void *p : ctx->allocs) {
+        if (ctx->free_fn) ctx->free_fn(p, ctx->alloc_ctx);
+        else (void)hipFree(p);
+    }
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     if (ctx->stream2) (void)hipStreamDestroy(ctx->stream2);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
@@ -348,7 +379,10 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
     *out = nullptr;
     // every check on the arguments comes before the first device call
     if (opts->precision != DUWP_FP64 && opts->precision != DUWP_MIXED) return DUWP_EINVAL;
-    if (opts->block_cells > 0 && (opts->block_cells % 64 || opts->block_cells > 512)) return DUWP_EINVAL;
+    if (opts->block_cells < 0 || (opts->block_cells > 0 && (opts->block_cells % 64 || opts->block_cells > 512)))
+        return DUWP_EINVAL;
+    if (opts->reserved != 0 || (opts->alloc != nullptr) != (opts->free != nullptr)) return DUWP_EINVAL;
+    if (!tune_valid(opts->tune, opts->precision)) return DUWP_EINVAL;
     {
         int64_t cells = 0;
         for (int k = 0; k < ncases; ++k) {
@@ -373,6 +407,19 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
     }
     ctx->seed = opts->seed;
     ctx->block_cells = opts->block_cells > 0 ? opts->block_cells : 256;
+    ctx->alloc_fn = opts->alloc;
+    ctx->free_fn = opts->free;
+    ctx->alloc_ctx = opts->alloc_ctx;
+    {
+        const duwp_tune &t = opts->tune;
+        ctx->scat_items = t.scatter_items ? t.scatter_items : 4;
+        ctx->big_block = t.big_block ? t.big_block : (opts->precision == DUWP_MIXED ? 512 : 256);
+        ctx->big_per_cu = t.big_blocks_per_cu ? t.big_blocks_per_cu : (ctx->big_block == 1024 ? 1 : 2);
+        ctx->big_min_n = t.big_min_particles ? t.big_min_particles : duwp::BIG_N;
+        ctx->big_min_m = t.big_min_candidates ? t.big_min_candidates : duwp::BIG_M;
+        ctx->coll_by_cell_max = t.collide_by_cell_max ? t.collide_by_cell_max : 8192;
+        ctx->count_dests = t.count_dests ? t.count_dests : 256;
+    }
     if (hipStreamCreateWithFlags(&ctx->stream2, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
@@ -426,7 +473,7 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
         // the scatter visits cells largest first only when its grid runs in
         // few rounds of resident blocks (the tail then matters); with many
         // rounds the order lookup would only lengthen each block's load chain
-        const int64_t resident = (int64_t)duwp::scatter_blocks_per_cu(ctx->precision, ctx->block_cells) * ncu;
+        const int64_t resident = (int64_t)duwp::scatter_blocks_per_cu(ctx->precision, ctx->block_cells, ctx->scat_items) * ncu;
         ctx->scat_by_order = G < 16 * resident ? 1 : 0;
     }
     duwp_status s = alloc_all(ctx);
@@ -580,18 +627,19 @@ duwp_status duwp_get_state(duwp_ctx *ctx, int32_t case_id, duwp_state *st)
     if (!ctx || !st || case_id < 0 || case_id >= ctx->ncases) return DUWP_EINVAL;
     const DCase &d = ctx->hcases[case_id];
     std::vector<int64_t> off;
-    TRY(host_offsets(ctx, off));
-    const int64_t b = off[d.cell_base], n = off[d.cell_base + d.ncells] - b;
+    TRY(case_offsets(ctx, d, off));
+    const int64_t b = off[0], n = off[d.ncells] - b;
     if (st->ncells != d.ncells || st->n_particles < n) return DUWP_EINVAL;
     st->n_particles = n;
     st->step = ctx->step;
+    st->avg_count = ctx->avg_count;
     if (st->off)
-        for (int i = 0; i <= d.ncells; ++i) st->off[i] = off[d.cell_base + i] - b;
+        for (int i = 0; i <= d.ncells; ++i) st->off[i] = off[i] - b;
     if (ctx->precision == DUWP_MIXED) {
         std::vector<float> h[4];
         TRY(download_particles<float>(ctx, b, n, h));
         for (int i = 0; i < d.ncells; ++i)
-            for (int64_t q = off[d.cell_base + i] - b; q < off[d.cell_base + i + 1] - b; ++q) {
+            for (int64_t q = off[i] - b; q < off[i + 1] - b; ++q) {
                 if (st->x) st->x[q] = d.x_lo + ((double)i + (double)h[0][q]) * d.dx;
                 if (st->u) st->u[q] = h[1][q];
                 if (st->v) st->v[q] = h[2][q];
@@ -605,14 +653,12 @@ duwp_status duwp_get_state(duwp_ctx *ctx, int32_t case_id, duwp_state *st)
             if (dst[a]) std::memcpy(dst[a], h[a].data(), 8 * (size_t)n);
     }
     hipStream_t s = ctx->stream;
-    if (st->psi_w)
-        HIP_OK(hipMemcpyAsync(st->psi_w, ctx->cl.psi_w + 5 * (size_t)d.cell_base, 8 * 5 * (size_t)d.ncells,
-                              hipMemcpyDeviceToHost, s));
+    const size_t o5 = 5 * (size_t)d.cell_base, n5 = 8 * 5 * (size_t)d.ncells;
+    if (st->psi_w) HIP_OK(hipMemcpyAsync(st->psi_w, ctx->cl.psi_w + o5, n5, hipMemcpyDeviceToHost, s));
     if (st->cr_max)
         HIP_OK(hipMemcpyAsync(st->cr_max, ctx->cl.cr_max + d.cell_base, 8 * (size_t)d.ncells, hipMemcpyDeviceToHost, s));
-    if (st->psi_p)
-        HIP_OK(hipMemcpyAsync(st->psi_p, ctx->cl.psi_p + 5 * (size_t)d.cell_base, 8 * 5 * (size_t)d.ncells,
-                              hipMemcpyDeviceToHost, s));
+    if (st->psi_p) HIP_OK(hipMemcpyAsync(st->psi_p, ctx->cl.psi_p + o5, n5, hipMemcpyDeviceToHost, s));
+    if (st->avg_sum) HIP_OK(hipMemcpyAsync(st->avg_sum, ctx->cl.avg + o5, n5, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     return DUWP_OK;
 }
@@ -626,17 +672,27 @@ duwp_status duwp_set_state(duwp_ctx *ctx, int32_t case_id, const duwp_state *st)
     if (st->off[0] != 0 || st->off[d.ncells] != st->n_particles) return DUWP_EINVAL;
     for (int i = 0; i < d.ncells; ++i)
         if (st->off[i + 1] < st->off[i]) return DUWP_EINVAL;
-    std::vector<int64_t> off;
-    TRY(host_offsets(ctx, off));
+    if (st->avg_sum && st->avg_count < 0) return DUWP_EINVAL;
     const int G = ctx->G, p = ctx->step & 1;
-    const int64_t b = off[d.cell_base], nold = off[d.cell_base + d.ncells] - b;
-    const int64_t total = off[G] - nold + st->n_particles;
+    // the case's first offset and its end, and the end of the whole array
+    int64_t b, e, endall;
+    {
+        hipStream_t s = ctx->stream;
+        HIP_OK(hipMemcpyAsync(&b, ctx->off[p] + d.cell_base, 8, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(&e, ctx->off[p] + d.cell_base + d.ncells, 8, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(&endall, ctx->off[p] + G, 8, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+    }
+    const int64_t nold = e - b, nnew = st->n_particles, delta = nnew - nold;
+    const int64_t total = endall + delta;
     if (total > ctx->cap) return DUWP_ECAPACITY;
     const bool mixed = ctx->precision == DUWP_MIXED;
     const size_t es = mixed ? 4 : 8, rs = 4 * es;   // element and record sizes
     // the case's records in device layout, record q at out + rs q
-    auto fill = [&](char *out) {
+    std::vector<char> hh(rs * (size_t)nnew);
+    {
         const double *srcv[4] = {st->x, st->u, st->v, st->w};
+        char *out = hh.data();
         for (int i = 0; i < d.ncells; ++i)
             for (int64_t q = st->off[i]; q < st->off[i + 1]; ++q)
                 for (int a = 0; a < 4; ++a) {
@@ -657,63 +713,50 @@ duwp_status duwp_set_state(duwp_ctx *ctx, int32_t case_id, const duwp_state *st)
                         std::memcpy(slot, &val, 8);
                     }
                 }
-    };
-    hipStream_t s = ctx->stream;
-    if (st->n_particles == nold) {
-        // same particle count: the case's records and cell offsets are replaced
-        // in place; the other cases are not touched
-        std::vector<char> hh(rs * (size_t)nold);
-        fill(hh.data());
-        if (nold)
-            HIP_OK(hipMemcpyAsync((char *)ctx->A[p] + rs * (size_t)b, hh.data(), hh.size(), hipMemcpyHostToDevice, s));
-        std::vector<int64_t> coff((size_t)d.ncells + 1);
-        for (int i = 0; i <= d.ncells; ++i) coff[i] = b + st->off[i];
-        HIP_OK(hipMemcpyAsync(ctx->off[p] + d.cell_base, coff.data(), 8 * coff.size(), hipMemcpyHostToDevice, s));
-        HIP_OK(hipStreamSynchronize(s));
-    } else {
-        // rebuild the whole canonical array on the host: earlier cases, this case, later cases
-        std::vector<char> hh(rs * (size_t)total);
-        {
-            std::vector<char> old(rs * (size_t)off[G]);
-            if (off[G]) HIP_OK(hipMemcpyAsync(old.data(), ctx->A[p], old.size(), hipMemcpyDeviceToHost, s));
-            HIP_OK(hipStreamSynchronize(s));
-            std::memcpy(hh.data(), old.data(), rs * (size_t)b);
-            std::memcpy(hh.data() + rs * (size_t)(b + st->n_particles), old.data() + rs * (size_t)(b + nold),
-                        rs * (size_t)(off[G] - b - nold));
-        }
-        fill(hh.data() + rs * (size_t)b);
-        if (total) HIP_OK(hipMemcpyAsync(ctx->A[p], hh.data(), hh.size(), hipMemcpyHostToDevice, s));
-        HIP_OK(hipStreamSynchronize(s));
-        std::vector<int64_t> noff((size_t)G + 1);
-        const int64_t delta = st->n_particles - nold;
-        for (int g = 0; g <= G; ++g) {
-            if (g < d.cell_base) noff[g] = off[g];
-            else if (g <= d.cell_base + d.ncells) noff[g] = b + st->off[g - d.cell_base];
-            else noff[g] = off[g] + delta;
-        }
-        HIP_OK(hipMemcpyAsync(ctx->off[p], noff.data(), 8 * noff.size(), hipMemcpyHostToDevice, s));
-        HIP_OK(hipStreamSynchronize(s));
     }
-    HIP_OK(hipMemcpyAsync(ctx->cl.psi_w + 5 * (size_t)d.cell_base, st->psi_w, 8 * 5 * (size_t)d.ncells,
-                          hipMemcpyHostToDevice, s));
+    std::vector<int64_t> coff((size_t)d.ncells + 1);
+    for (int i = 0; i <= d.ncells; ++i) coff[i] = b + st->off[i];
+    hipStream_t s = ctx->stream;
+    // a fresh error word: the context may be restored after a step reported one
+    HIP_OK(hipMemsetAsync(ctx->d_err, 0, 4, s));
+    char *A = (char *)ctx->A[p];
+    if (delta != 0) {
+        // the later cases' records move by delta, on the device, through the
+        // staging buffer (source and destination overlap); their offsets follow
+        const int64_t tail = endall - e;
+        if (tail > 0) {
+            HIP_OK(hipMemcpyAsync(ctx->S, A + rs * (size_t)e, rs * (size_t)tail, hipMemcpyDeviceToDevice, s));
+            HIP_OK(hipMemcpyAsync(A + rs * (size_t)(e + delta), ctx->S, rs * (size_t)tail, hipMemcpyDeviceToDevice, s));
+        }
+        (void)hipGetLastError();
+        duwp::enqueue_shift_offsets(ctx, ctx->off[p], d.cell_base + d.ncells + 1, delta);
+        if (hipGetLastError() != hipSuccess) return DUWP_EDEVICE;
+    }
+    if (nnew) HIP_OK(hipMemcpyAsync(A + rs * (size_t)b, hh.data(), hh.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(ctx->off[p] + d.cell_base, coff.data(), 8 * coff.size(), hipMemcpyHostToDevice, s));
+    const size_t o5 = 5 * (size_t)d.cell_base, n5 = 8 * 5 * (size_t)d.ncells;
+    HIP_OK(hipMemcpyAsync(ctx->cl.psi_w + o5, st->psi_w, n5, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(ctx->cl.cr_max + d.cell_base, st->cr_max, 8 * (size_t)d.ncells, hipMemcpyHostToDevice, s));
-    if (st->psi_p)
-        HIP_OK(hipMemcpyAsync(ctx->cl.psi_p + 5 * (size_t)d.cell_base, st->psi_p, 8 * 5 * (size_t)d.ncells,
-                              hipMemcpyHostToDevice, s));
-    // the step index is shared by all cases; the parity of the buffers follows it
+    if (st->psi_p) HIP_OK(hipMemcpyAsync(ctx->cl.psi_p + o5, st->psi_p, n5, hipMemcpyHostToDevice, s));
+    if (st->avg_sum) HIP_OK(hipMemcpyAsync(ctx->cl.avg + o5, st->avg_sum, n5, hipMemcpyHostToDevice, s));
+    // the step index is shared by all cases; the buffers of the state follow its parity
     if ((st->step & 1u) != (ctx->step & 1u)) {
-        if (total) HIP_OK(hipMemcpyAsync(ctx->A[p ^ 1], ctx->A[p], rs * (size_t)total, hipMemcpyDeviceToDevice, s));
+        if (total)
+            HIP_OK(hipMemcpyAsync(ctx->A[p ^ 1], ctx->A[p], rs * (size_t)total, hipMemcpyDeviceToDevice, s));
         HIP_OK(hipMemcpyAsync(ctx->off[p ^ 1], ctx->off[p], 8 * (size_t)(G + 1), hipMemcpyDeviceToDevice, s));
+        HIP_OK(hipMemcpyAsync(ctx->hist_buf[p ^ 1], ctx->hist_buf[p], 4 * (size_t)G * duwp::NBIN,
+                              hipMemcpyDeviceToDevice, s));
+        HIP_OK(hipMemcpyAsync(ctx->fix_buf[p ^ 1], ctx->fix_buf[p], 4 * (size_t)G, hipMemcpyDeviceToDevice, s));
     }
     ctx->step = st->step;
+    if (st->avg_sum) ctx->avg_count = st->avg_count;
     uint32_t dstep = st->step;
     HIP_OK(hipMemcpyAsync(ctx->d_step, &dstep, 4, hipMemcpyHostToDevice, s));
-    HIP_OK(hipStreamSynchronize(s));
     (void)hipGetLastError();
+    // the case's particle moments (loaded or summed afresh) and its destination histograms
     duwp::enqueue_moments(ctx, d.cell_base, d.cell_base + d.ncells, st->psi_p == nullptr);
     if (hipGetLastError() != hipSuccess) return DUWP_EDEVICE;
-    HIP_OK(hipStreamSynchronize(s));
-    return DUWP_OK;
+    return read_error(ctx);
 }
 
 duwp_status duwp_profile(duwp_ctx *ctx, int32_t nsteps, const char **names, double *ms, int32_t cap,

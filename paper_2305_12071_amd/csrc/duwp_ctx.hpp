@@ -73,21 +73,36 @@ struct duwp_ctx {
     double *diag = nullptr;        // [G*5] on-demand cell diagnostics
     int64_t *d_psteps = nullptr;   // particle-steps since init or the last reset
 
+    // tile shapes and thresholds (defaults filled in)
+    int scat_items = 4;            // particles per thread and chunk, multi-wave scatter blocks
+    int big_block = 512;           // threads of the block-per-cell collide
+    int big_per_cu = 2;            // its resident blocks per compute unit
+    int big_min_n = 4096, big_min_m = 4096;   // cells at least this large collide in it
+    int coll_by_cell_max = 8192;   // up to this many cells: a wave per cell in k_collide
+    int count_dests = 256;         // destinations per block of k_count_new / k_bases (large grids)
+
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     bool graph_ready = false;
     duwp::KernelTimer timer;
+    // device memory provider: the caller's, or hipMalloc/hipFree when alloc_fn is null
+    void *(*alloc_fn)(size_t, void *) = nullptr;
+    void (*free_fn)(void *, void *) = nullptr;
+    void *alloc_ctx = nullptr;
     std::vector<void *> allocs;
 };
 
 namespace duwp {
 // Launch the kernels of one step on ctx->stream (defined with the kernels).
 void enqueue_step(duwp_ctx *ctx);
-// Scatter blocks that fit on one compute unit at once (for this precision and block size).
-int scatter_blocks_per_cu(int precision, int bc);
+// Scatter blocks that fit on one compute unit at once (for this precision, block size
+// and items per thread of multi-wave blocks).
+int scatter_blocks_per_cu(int precision, int bc, int items);
 // Particle moments of cells [g0, g1) of the current canonical state: recomputed
 // from the particles, or (recompute false) kept as loaded and checked for finite
-// totals; then the destination histogram of every cell (no averaging).
+// totals; then the destination histogram of the same cells (no averaging).
 void enqueue_moments(duwp_ctx *ctx, int g0, int g1, bool recompute);
+// Add delta to the canonical offsets off[g0..G].
+void enqueue_shift_offsets(duwp_ctx *ctx, int64_t *off, int g0, int64_t delta);
 // Normal stress and heat flux of cells [g0, g1) of the current state into out[G*5].
 void enqueue_stress_heat(duwp_ctx *ctx, int g0, int g1, double *out);
 }  // namespace duwp

@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ ca
                                                      const int64_t *__restrict__ off,
                                                      const uint32_t *__restrict__ d_step, int G,
                                                      int32_t *err, int64_t *d_nout, int64_t *d_ninj,
-                                                     int abs_stream)
+                                                     int abs_stream, int big_min_n, int big_min_m)
 {
     __shared__ double sP[WAVE];
     __shared__ int64_t sb[WAVE], se[WAVE], spb[WAVE];
@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ ca
     }
     // cells with many particles and many candidates collide one block each
     // (k_collide_big); the others go to the wave kernel's candidate list
-    const bool big = in && N >= BIG_N && M >= BIG_M;
+    const bool big = in && N >= big_min_n && M >= big_min_m;
     const uint64_t bm = __ballot(big);
     if (bm) {
         int base = 0;
@@ -450,7 +450,6 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
 // ---------------------------------------------------------------------------
 constexpr int COLL_HBITS = 8;
 constexpr int COLL_WPB = 4;      // waves per block
-constexpr int COLL_BY_CELL_MAX = 8192;    // up to this many cells: a wave per cell
 
 // item_cell[w] = first cell of item w; d_items = {number of items, S}
 __global__ void __launch_bounds__(256) k_items(const int64_t *__restrict__ cbase, int G, int32_t *item_cell,
@@ -680,14 +679,13 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
 // ---------------------------------------------------------------------------
 constexpr int BIG_LIST = 4;
 
-// B threads (candidates per chunk), 2^HBITS hash slots (at least twice the
-// particles a chunk draws), PER_CU blocks resident per compute unit (LDS bound)
-template <typename T>
+// B threads (candidates per chunk: 256, 512 or 1024), 2^HBITS hash slots (twice
+// the particles a chunk draws)
+template <int B>
 struct BigCfg {
-    static constexpr int B = sizeof(T) == 4 ? 512 : 256;
-    static constexpr int HBITS = sizeof(T) == 4 ? 11 : 10;
+    static constexpr int HBITS = B == 256 ? 10 : (B == 512 ? 11 : 12);
     static constexpr int SLOTS = 1 << HBITS;
-    static constexpr int PER_CU = 2;
+    static_assert(SLOTS == 4 * B, "hash slots: twice the 2B particles a chunk draws");
 };
 
 
@@ -754,15 +752,14 @@ __device__ __forceinline__ void big_bins(const CaseK &c, int lc, T xi, T ui0, T 
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(BigCfg<T>::B) k_collide_big(const DCase *__restrict__ cases, Cells cl,
-                                                               P4<T> *src, P4<T> *stg,
-                                                               const uint32_t *__restrict__ d_step, int64_t cap)
+template <typename T, int B>
+__global__ void __launch_bounds__(B) k_collide_big(const DCase *__restrict__ cases, Cells cl,
+                                                   P4<T> *src, P4<T> *stg,
+                                                   const uint32_t *__restrict__ d_step, int64_t cap)
 {
-    constexpr int B = BigCfg<T>::B;
     constexpr int NW = B / WAVE;
-    constexpr int SLOTS = BigCfg<T>::SLOTS;
-    constexpr int HB = BigCfg<T>::HBITS;
+    constexpr int SLOTS = BigCfg<B>::SLOTS;
+    constexpr int HB = BigCfg<B>::HBITS;
     __shared__ uint32_t hkey[SLOTS];
     __shared__ int hcnt[SLOTS];
     __shared__ uint16_t hlst[SLOTS][BIG_LIST];
@@ -1145,22 +1142,22 @@ __global__ void __launch_bounds__(1024) k_inject_rank(const DCase *__restrict__ 
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(512) k_hist_build(const DCase *__restrict__ cases, Cells cl, P4<T> *src,
-                                                     P4<T> *stg, const int64_t *__restrict__ off, int G,
-                                                     int64_t cap, int all)
+                                                     P4<T> *stg, const int64_t *__restrict__ off, int gbeg,
+                                                     int gend, int64_t cap, int all)
 {
     // Recount of the destination histogram of a cell from its particles: every
-    // cell of a loaded canonical state (all = 1), or the intermediate segments
-    // of the cells flagged during the step (all = 0, usually none).  A block
-    // takes groups of 64 consecutive cells: one wave reads their flags, and the
-    // block recounts the flagged ones.
+    // cell in [gbeg, gend) of a loaded canonical state (all = 1), or the
+    // intermediate segments of the cells flagged during the step (all = 0,
+    // usually none).  A block takes groups of 64 consecutive cells: one wave
+    // reads their flags, and the block recounts the flagged ones.
     constexpr int IT = 4;
     __shared__ int h[NBIN];
     __shared__ int flagged[WAVE];
     __shared__ int nfl;
-    for (int g0 = blockIdx.x * WAVE; g0 < G; g0 += gridDim.x * WAVE) {
+    for (int g0 = gbeg + blockIdx.x * WAVE; g0 < gend; g0 += gridDim.x * WAVE) {
         if (threadIdx.x < WAVE) {
             const int gg = g0 + (int)threadIdx.x;
-            const bool f = gg < G && (all || cl.fix[gg]);
+            const bool f = gg < gend && (all || cl.fix[gg]);
             const uint64_t m = __ballot(f);
             if (f) flagged[lane_rank_lt(m)] = gg;
             if (threadIdx.x == 0) nfl = __popcll(m);
@@ -1377,7 +1374,7 @@ __device__ __forceinline__ void add_phi(double (&a)[5], double u, double v, doub
 // Items per thread and chunk, and the waves per SIMD the register budget is cut
 // for (FP32 particles): one-wave blocks (small cells) and blocks of several waves.
 constexpr int SCAT_IT1 = 2, SCAT_W1 = 5;
-constexpr int SCAT_ITN = 4, SCAT_WN = 1;
+constexpr int SCAT_WN = 1;
 
 template <typename T, int MAXW, int IT>
 __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1 : SCAT_WN)) k_scatter(const DCase *__restrict__ cases, Cells cl, P4<T> *src,
@@ -1860,16 +1857,15 @@ __global__ void __launch_bounds__(256) k_stress_heat(const DCase *__restrict__ c
     }
 }
 
-// Particle moments recomputed from a canonical array (after a state is loaded).
+// Particle moments of cells [g0, g1) recomputed from a canonical array (after a
+// state is loaded), or kept as loaded; either way their totals are checked.
 template <typename T>
 __global__ void __launch_bounds__(512) k_moments(const DCase *__restrict__ cases, Cells cl, const P4<T> *a,
-                                                  const int64_t *__restrict__ off, int G, int g0, int g1,
+                                                  const int64_t *__restrict__ off, int g0, int g1,
                                                   int recompute, int32_t *err)
 {
     __shared__ double red[5 * 16];
-    for (int gi = blockIdx.x; gi < G; gi += gridDim.x) {
-        const int g = cl.order[gi];
-        if (g < g0 || g >= g1) continue;   // uniform over the block
+    for (int g = g0 + (int)blockIdx.x; g < g1; g += gridDim.x) {
         const DCase &c = cases[cl.cell_case[g]];
         double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         if (recompute) {
@@ -1950,7 +1946,8 @@ static void step_impl(duwp_ctx *ctx)
         const int cblk = (G + WAVE - 1) / WAVE;
         const int cw = std::max(1, std::min(16, (8192 + cblk - 1) / cblk));
         hipLaunchKernelGGL(k_cellstate, dim3(cblk), dim3(WAVE * cw), 0, st, ctx->d_cases, cl, ctx->off[p],
-                           ctx->d_step, G, ctx->d_err, ctx->d_nout, ctx->d_ninj, ctx->abs_stream);
+                           ctx->d_step, G, ctx->d_err, ctx->d_nout, ctx->d_ninj, ctx->abs_stream,
+                           ctx->big_min_n, ctx->big_min_m);
     }
     {
         Mark m(ctx, "scan_staging");
@@ -1990,15 +1987,23 @@ static void step_impl(duwp_ctx *ctx)
         // cells with many particles and candidates (their own list): disjoint
         // from the cells of k_collide, so the two run side by side
         Mark m(ctx, "collide_big");
-        hipLaunchKernelGGL(k_collide_big<T>, dim3(ctx->big_blocks * BigCfg<T>::PER_CU), dim3(BigCfg<T>::B), 0, s2,
-                           ctx->d_cases, cl, src, stg, ctx->d_step, ctx->cap);
+        const dim3 gb(ctx->big_blocks * ctx->big_per_cu);
+        if (ctx->big_block == 256)
+            hipLaunchKernelGGL((k_collide_big<T, 256>), gb, dim3(256), 0, s2, ctx->d_cases, cl, src, stg,
+                               ctx->d_step, ctx->cap);
+        else if (ctx->big_block == 512)
+            hipLaunchKernelGGL((k_collide_big<T, 512>), gb, dim3(512), 0, s2, ctx->d_cases, cl, src, stg,
+                               ctx->d_step, ctx->cap);
+        else
+            hipLaunchKernelGGL((k_collide_big<T, 1024>), gb, dim3(1024), 0, s2, ctx->d_cases, cl, src, stg,
+                               ctx->d_step, ctx->cap);
     }
     if (fork) (void)hipEventRecord(ctx->ev_join, s2);
     {
         Mark m(ctx, "collide");
         // few cells: a wave per cell; many (mostly small) cells: work items cut
         // from the scanned candidate list
-        const int by_cell = G <= COLL_BY_CELL_MAX;
+        const int by_cell = G <= ctx->coll_by_cell_max;
         if (!by_cell) {
             enqueue_scan(ctx, ctx->cl.ncand_w, ctx->cl.cbase, ctx->d_total + 2, INT64_MAX);
             hipLaunchKernelGGL(k_items, dim3((G + 1 + 255) / 256), dim3(256), 0, st, ctx->cl.cbase, G,
@@ -2013,11 +2018,11 @@ static void step_impl(duwp_ctx *ctx)
     // destinations per block of the two histogram passes: 4 (a wave each, small
     // grids) or up to 256 (a thread each), so that their grids keep about 1000
     // blocks or more
-    const int nd = std::max(4, std::min(CN_D, G / 1024 / 4 * 4));
+    const int nd = std::max(4, std::min(std::min(CN_D, ctx->count_dests), G / 1024 / 4 * 4));
     {
         Mark m(ctx, "hist_fix");
         hipLaunchKernelGGL(k_hist_build<T>, dim3((G + WAVE - 1) / WAVE), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
-                           ctx->off[p], G, ctx->cap, 0);
+                           ctx->off[p], 0, G, ctx->cap, 0);
     }
     {
         Mark m(ctx, "count_new");
@@ -2036,8 +2041,11 @@ static void step_impl(duwp_ctx *ctx)
         if (bc == WAVE)
             hipLaunchKernelGGL((k_scatter<T, 1, SCAT_IT1>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
                                dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout, ctx->scat_by_order);
+        else if (ctx->scat_items == 2)
+            hipLaunchKernelGGL((k_scatter<T, 8, 2>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
+                               dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout, ctx->scat_by_order);
         else
-            hipLaunchKernelGGL((k_scatter<T, 8, SCAT_ITN>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
+            hipLaunchKernelGGL((k_scatter<T, 8, 4>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
                                dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout, ctx->scat_by_order);
     }
     {
@@ -2052,14 +2060,17 @@ static void step_impl(duwp_ctx *ctx)
     }
 }
 
-// Scatter blocks that fit on one compute unit at once, for this precision and block size.
-int scatter_blocks_per_cu(int precision, int bc)
+// Scatter blocks that fit on one compute unit at once, for this precision, block size
+// and items per thread.
+int scatter_blocks_per_cu(int precision, int bc, int items)
 {
     const void *f;
     if (precision == DUWP_MIXED)
-        f = bc == WAVE ? (const void *)&k_scatter<float, 1, SCAT_IT1> : (const void *)&k_scatter<float, 8, SCAT_ITN>;
+        f = bc == WAVE ? (const void *)&k_scatter<float, 1, SCAT_IT1>
+                       : (items == 2 ? (const void *)&k_scatter<float, 8, 2> : (const void *)&k_scatter<float, 8, 4>);
     else
-        f = bc == WAVE ? (const void *)&k_scatter<double, 1, SCAT_IT1> : (const void *)&k_scatter<double, 8, SCAT_ITN>;
+        f = bc == WAVE ? (const void *)&k_scatter<double, 1, SCAT_IT1>
+                       : (items == 2 ? (const void *)&k_scatter<double, 8, 2> : (const void *)&k_scatter<double, 8, 4>);
     int per = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, bc, 0) != hipSuccess || per <= 0) per = 1;
     return per;
@@ -2081,20 +2092,36 @@ __global__ void k_zero_i32(int32_t *a, int n)
 template <typename T>
 static void reload_impl(duwp_ctx *ctx, int g0, int g1, bool recompute)
 {
-    const int p = ctx->step & 1, G = ctx->G;
+    const int p = ctx->step & 1, n = g1 - g0;
+    if (n <= 0) return;
     Cells cl = ctx->cl;
     cl.hist = ctx->hist_buf[p];
     cl.fix = ctx->fix_buf[p];
     P4<T> *const a = recs<T>(ctx->A[p]);
-    hipLaunchKernelGGL(k_moments<T>, dim3(G), dim3(ctx->block_cells), 0, ctx->stream, ctx->d_cases, cl, a,
-                       ctx->off[p], G, g0, g1, recompute ? 1 : 0, ctx->d_err);
-    hipLaunchKernelGGL(k_hist_build<T>, dim3((G + WAVE - 1) / WAVE), dim3(ctx->block_cells), 0, ctx->stream,
-                       ctx->d_cases, cl, a, a, ctx->off[p], G, ctx->cap, 1);
+    hipLaunchKernelGGL(k_moments<T>, dim3(std::min(n, 65535)), dim3(ctx->block_cells), 0, ctx->stream, ctx->d_cases,
+                       cl, a, ctx->off[p], g0, g1, recompute ? 1 : 0, ctx->d_err);
+    hipLaunchKernelGGL(k_hist_build<T>, dim3((n + WAVE - 1) / WAVE), dim3(ctx->block_cells), 0, ctx->stream,
+                       ctx->d_cases, cl, a, a, ctx->off[p], g0, g1, ctx->cap, 1);
+}
+
+// Shift the canonical cell offsets of cells [g0, G] by delta (after a restore
+// changed the particle count of an earlier case).
+__global__ void k_shift_offsets(int64_t *off, int g0, int G, int64_t delta)
+{
+    const int g = g0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (g <= G) off[g] += delta;
+}
+
+void enqueue_shift_offsets(duwp_ctx *ctx, int64_t *off, int g0, int64_t delta)
+{
+    const int n = ctx->G + 1 - g0;
+    if (n > 0 && delta != 0)
+        hipLaunchKernelGGL(k_shift_offsets, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, off, g0, ctx->G, delta);
 }
 
 // Particle moments of cells [g0, g1) of a loaded canonical state (recomputed from
 // the particles, or kept as loaded and only checked), and the destination
-// histogram of all cells.
+// histogram of the same cells.
 void enqueue_moments(duwp_ctx *ctx, int g0, int g1, bool recompute)
 {
     if (ctx->precision == DUWP_MIXED) reload_impl<float>(ctx, g0, g1, recompute);

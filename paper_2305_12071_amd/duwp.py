@@ -43,10 +43,23 @@ class _Case(C.Structure):
     ]
 
 
+TUNE_FIELDS = ("scatter_items", "big_block", "big_blocks_per_cu", "big_min_particles", "big_min_candidates",
+               "collide_by_cell_max", "count_dests")
+
+
+class _Tune(C.Structure):
+    _fields_ = [(f, C.c_int32) for f in TUNE_FIELDS] + [("reserved", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class _Opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("precision", C.c_int32), ("use_graph", C.c_int32),
                 ("stream", C.c_void_p), ("headroom", C.c_double), ("block_cells", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p),
+                ("tune", _Tune)]
 
 
 class _State(C.Structure):
@@ -54,10 +67,48 @@ class _State(C.Structure):
                 ("x", C.POINTER(C.c_double)), ("u", C.POINTER(C.c_double)),
                 ("v", C.POINTER(C.c_double)), ("w", C.POINTER(C.c_double)),
                 ("off", C.POINTER(C.c_int64)), ("psi_w", C.POINTER(C.c_double)),
-                ("cr_max", C.POINTER(C.c_double)), ("psi_p", C.POINTER(C.c_double))]
+                ("cr_max", C.POINTER(C.c_double)), ("psi_p", C.POINTER(C.c_double)),
+                ("avg_sum", C.POINTER(C.c_double)), ("avg_count", C.c_int64)]
+
+
+class TorchAllocator:
+    """torch's caching allocator as the library's device memory provider: the
+    callbacks the context calls at duwp_init and duwp_destroy (kept alive here
+    while the context lives)."""
+
+    def __init__(self, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.cuda.current_device()
+        self.stream = stream
+        self.live = 0
+
+        def _alloc(nbytes, _ctx):
+            try:
+                ptr = self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:        # out of memory: the library reports DUWP_ENOMEM
+                return None
+            self.live += 1
+            return ptr
+
+        def _free(ptr, _ctx):
+            self.torch.cuda.caching_allocator_delete(ptr)
+            self.live -= 1
+
+        self.alloc = ALLOC_FN(_alloc)
+        self.free = FREE_FN(_free)
 
 
 _lib = None
+_live = None     # contexts not yet closed (closed at exit, while torch is still loaded)
+
+
+def _close_all():
+    for sim in list(_live or ()):
+        try:
+            sim.close()
+        except Exception:
+            pass
 
 
 def lib():
@@ -142,6 +193,14 @@ def make_case(case) -> _Case:
     return c
 
 
+def _torch_gpu() -> bool:
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
 def current_stream():
     """hipStream_t of torch's current stream (torch is only plumbing here), or None."""
     try:
@@ -157,7 +216,10 @@ class Sim:
     """A set of independent cases advanced together by the HIP pipeline."""
 
     def __init__(self, cases, seed: int = 1, precision: int = FP64, use_graph: bool = False,
-                 stream=None, headroom: float = 0.0, block_cells: int = 0):
+                 stream=None, headroom: float = 0.0, block_cells: int = 0, tune: dict | None = None,
+                 allocator: str = "torch"):
+        """allocator: "torch" (device buffers from torch's caching allocator, the
+        default when torch sees a GPU) or "hip" (the library's hipMalloc)."""
         if not isinstance(cases, (list, tuple)):
             cases = [cases]
         self.cases = list(cases)
@@ -171,9 +233,26 @@ class Sim:
         o.stream = C.c_void_p(s) if s else None
         o.headroom = headroom
         o.block_cells = block_cells
+        for k, v in (tune or {}).items():
+            if k not in TUNE_FIELDS:
+                raise ValueError(f"unknown tuning field {k}")
+            setattr(o.tune, k, int(v))
+        self.allocator = None
+        if allocator == "torch" and _torch_gpu():
+            self.allocator = TorchAllocator()
+            o.alloc, o.free = self.allocator.alloc, self.allocator.free
+        elif allocator not in ("torch", "hip"):
+            raise ValueError(f"allocator {allocator!r}")
         self.precision = precision
         self.ptr = C.c_void_p()
         _check(lib().duwp_init(C.byref(self.ptr), arr, len(cases), C.byref(o)), "duwp_init")
+        global _live
+        if _live is None:
+            import atexit
+            import weakref
+            _live = weakref.WeakSet()
+            atexit.register(_close_all)
+        _live.add(self)
 
     def close(self) -> None:
         if getattr(self, "ptr", None) and self.ptr.value:
@@ -237,10 +316,13 @@ class Sim:
         psi = np.zeros(nc * 5)
         cr = np.zeros(nc)
         pp = np.zeros(nc * 5)
-        s = _State(n, nc, step, _p(x), _p(u), _p(v), _p(w), _p(off, C.c_int64), _p(psi), _p(cr), _p(pp))
+        av = np.zeros(nc * 5)
+        s = _State(n, nc, step, _p(x), _p(u), _p(v), _p(w), _p(off, C.c_int64), _p(psi), _p(cr), _p(pp),
+                   _p(av), 0)
         _check(lib().duwp_get_state(self.ptr, case_id, C.byref(s)), "duwp_get_state")
         return dict(x=x, u=u, v=v, w=w, off=off, psi_w=psi.reshape(nc, 5), cr_max=cr, step=s.step,
-                    psi_p=pp.reshape(nc, 5), precision=self.precision)
+                    psi_p=pp.reshape(nc, 5), avg_sum=av.reshape(nc, 5), avg_count=int(s.avg_count),
+                    precision=self.precision)
 
     def set_state(self, st: dict, case_id: int = 0) -> None:
         x = np.ascontiguousarray(st["x"], np.float64)
@@ -258,8 +340,12 @@ class Sim:
         if st.get("precision", self.precision) != self.precision:
             pp = None
         pp = None if pp is None else np.ascontiguousarray(pp, np.float64).reshape(-1)
+        # the running time average travels with a checkpoint that has it
+        av = st.get("avg_sum")
+        av = None if av is None else np.ascontiguousarray(av, np.float64).reshape(-1)
         s = _State(len(x), len(off) - 1, int(st["step"]), _p(x), _p(u), _p(v), _p(w),
-                   _p(off, C.c_int64), _p(psi), _p(cr), None if pp is None else _p(pp))
+                   _p(off, C.c_int64), _p(psi), _p(cr), None if pp is None else _p(pp),
+                   None if av is None else _p(av), int(st.get("avg_count", 0)) if av is not None else 0)
         _check(lib().duwp_set_state(self.ptr, case_id, C.byref(s)), "duwp_set_state")
 
     def profile(self, nsteps: int = 3) -> dict:

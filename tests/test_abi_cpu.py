@@ -53,10 +53,24 @@ def test_state_struct_layout_matches_header():
     names = re.findall(r"\b([a-zA-Z_]+)\s*[,;]", re.sub(r"/\*.*?\*/", "", body, flags=re.S))
     assert names == [f for f, _ in duwp._State._fields_]
     assert duwp._State.psi_p.offset == 8 + 4 + 4 + 8 * 7
-    assert ctypes.sizeof(duwp._State) == 8 + 4 + 4 + 8 * 8
+    assert duwp._State.avg_count.offset == 8 + 4 + 4 + 8 * 9
+    assert ctypes.sizeof(duwp._State) == 8 + 4 + 4 + 8 * 10
 
 
-def _init_status(cases, precision=duwp.FP64, block_cells=0):
+def test_opts_and_tune_struct_layout_matches_header():
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "duwp.h")).read(), flags=re.S)
+    body = src[src.index("typedef struct {\n    int32_t scatter_items;"):src.index("} duwp_tune;")]
+    names = re.findall(r"\b([a-zA-Z_]+)\s*;", body)
+    assert names == [f for f, _ in duwp._Tune._fields_]
+    body = src[src.index("typedef struct {\n    uint64_t seed;"):src.index("} duwp_opts;")]
+    names = re.findall(r"\b([a-zA-Z_]+)\s*;|\(\*([a-z_]+)\)", body)
+    names = [a or b for a, b in names]
+    assert names == [f for f, _ in duwp._Opts._fields_]
+    assert duwp._Opts.alloc.offset == 40 and duwp._Opts.tune.offset == 64
+    assert ctypes.sizeof(duwp._Opts) == 64 + 8 * 4
+
+
+def _init_status(cases, precision=duwp.FP64, block_cells=0, tune=None, alloc_only=False):
     arr = (duwp._Case * len(cases))(*[c if isinstance(c, duwp._Case) else duwp.make_case(c) for c in cases])
     o = duwp._Opts()
     o.seed = 1
@@ -65,6 +79,10 @@ def _init_status(cases, precision=duwp.FP64, block_cells=0):
     o.stream = None
     o.headroom = 0.0
     o.block_cells = block_cells
+    for k, v in (tune or {}).items():
+        setattr(o.tune, k, v)
+    if alloc_only:            # an allocator without its free
+        o.alloc = duwp.ALLOC_FN(lambda n, c: None)
     ptr = ctypes.c_void_p()
     s = duwp.lib().duwp_init(ctypes.byref(ptr), arr, len(cases), ctypes.byref(o))
     assert not ptr.value
@@ -90,3 +108,10 @@ def test_init_rejects_bad_descriptors_before_any_device_call():
     assert _init_status([good], precision=7) == EINVAL
     for bc in (100, 1024, 96):
         assert _init_status([good], block_cells=bc) == EINVAL, bc
+    for t in (dict(scatter_items=3), dict(big_block=128), dict(big_block=2048), dict(big_blocks_per_cu=3),
+              dict(big_min_particles=10), dict(big_min_candidates=-1), dict(collide_by_cell_max=-5),
+              dict(count_dests=6), dict(count_dests=512), dict(reserved=1)):
+        assert _init_status([good], tune=t) == EINVAL, t
+    # a 1024-thread FP64 block per cell takes more than half the LDS: one per compute unit
+    assert _init_status([good], tune=dict(big_block=1024, big_blocks_per_cu=2)) == EINVAL
+    assert _init_status([good], alloc_only=True) == EINVAL

@@ -220,8 +220,8 @@ def test_resume_from_checkpoint_is_bitwise_identical():
 @pytest.mark.parametrize("prec", [duwp.FP64, duwp.MIXED])
 def test_restore_in_place_equals_full_rebuild(prec):
     # a restore that keeps a case's particle count replaces its records in
-    # place; one that changes counts rebuilds the whole array: both must leave
-    # the same state behind
+    # place; one that changes counts also moves the later cases' records on the
+    # device: both must leave the same state behind
     cases = [CASES["mach3"], CASES["sod_kn1e-4"], CASES["box_ragged"]]
     _say("restore", prec)
     a = duwp.Sim(cases, seed=6, precision=prec)
@@ -237,7 +237,7 @@ def test_restore_in_place_equals_full_rebuild(prec):
     assert any(b.counts(k)[0] != len(states[k]["x"]) for k in range(3))
     for k in range(3):
         a.set_state(mine[k], k)     # same counts: in place
-        b.set_state(mine[k], k)     # other counts: whole array
+        b.set_state(mine[k], k)     # other counts: later records move
     a.step(4)
     b.step(4)
     for k in range(3):
@@ -321,9 +321,9 @@ def test_resume_with_particle_moments_is_bit_for_bit(prec):
 
 
 def test_non_finite_state_is_reported():
-    # a NaN put into one cell's wave energy through set_state: the cell counts as
-    # vacuum (no sampling, no collisions, no flux), and the step reports the
-    # non-finite total as DUWP_ESTATE
+    # a NaN put into one cell's wave energy through set_state: the restore reports
+    # it as DUWP_ESTATE; stepping on anyway, the cell counts as vacuum (no
+    # sampling, no collisions, no flux) and the step reports the non-finite total
     c = CASES["sod_kn1e-4"]
     _say("non-finite state")
     g = duwp.Sim(c, seed=3)
@@ -331,7 +331,9 @@ def test_non_finite_state_is_reported():
     st = g.get_state()
     st["psi_w"] = st["psi_w"].copy()
     st["psi_w"][5, 4] = np.nan
-    g.set_state(st)
+    with pytest.raises(duwp.DuwpError) as e:
+        g.set_state(st)
+    assert e.value.status == -5
     with pytest.raises(duwp.DuwpError) as e:
         g.step(1)
     assert e.value.status == -5
