@@ -189,6 +189,20 @@ duwp_status duwp_step(duwp_ctx *ctx, int32_t nsteps);
  * out is host memory, or device memory when out_on_device = 1. */
 duwp_status duwp_moments(duwp_ctx *ctx, int32_t case_id, int32_t what, double *out, int64_t len,
                          int32_t out_on_device);
+
+/* For callers that cannot allocate (code under HIP graph capture, serving loops
+ * that forbid allocation): duwp_moments into a device buffer out[len], len >=
+ * ncells*5, that allocates nothing (device or host), copies nothing to or from
+ * the host and does not synchronize.  Its kernels are queued on the context's
+ * stream and the call returns; out holds the result once that stream reaches
+ * them.  DUWP_M_STRESS_HEAT stages each cell's primitive state in a device array
+ * of the library, one per GPU, of DUWP_NOALLOC_MAX_CELLS + 2 rows, held until
+ * the process ends: a case with more cells gets DUWP_EINVAL.  Every call on one
+ * GPU, from any context, uses that one array, so calls that overlap on a GPU
+ * race: queue them on one stream or order them.  Launch failures give
+ * DUWP_EDEVICE; the device error word is not read (duwp_sync reads it). */
+#define DUWP_NOALLOC_MAX_CELLS 65536
+duwp_status duwp_moments_noalloc(duwp_ctx *ctx, int32_t case_id, int32_t what, double *out, int64_t len);
 int64_t duwp_avg_count(duwp_ctx *ctx);
 duwp_status duwp_reset_average(duwp_ctx *ctx);
 

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libduwp.so")
-SOURCES = ["duwp_kernels.hip", "duwp_api.hip"]
+SOURCES = ["duwp_kernels.hip", "duwp_api.hip", "duwp_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

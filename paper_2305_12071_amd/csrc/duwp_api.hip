@@ -465,9 +465,11 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
     {
         // collision work items are taken by a fixed grid of 16 blocks (64 waves) per compute unit
         int dev = 0, ncu = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+        if (hipGetDevice(&dev) != hipSuccess) { duwp_destroy(ctx); return DUWP_EDEVICE; }
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
             ncu = 256;
+        // the allocation-free moments' staging array on this device
+        if (duwp::noalloc_setup(dev, &ctx->scratch) != hipSuccess) { duwp_destroy(ctx); return DUWP_EDEVICE; }
         ctx->coll_blocks = 16 * ncu;   // work items: many waves in flight hide each chunk's load chain
         ctx->big_blocks = ncu;
         // the scatter visits cells largest first only when its grid runs in

@@ -89,6 +89,7 @@ struct duwp_ctx {
     void (*free_fn)(void *, void *) = nullptr;
     void *alloc_ctx = nullptr;
     std::vector<void *> allocs;
+    double *scratch = nullptr;     // this device's staging array of duwp_moments_noalloc
 };
 
 namespace duwp {
@@ -105,4 +106,7 @@ void enqueue_moments(duwp_ctx *ctx, int g0, int g1, bool recompute);
 void enqueue_shift_offsets(duwp_ctx *ctx, int64_t *off, int g0, int64_t delta);
 // Normal stress and heat flux of cells [g0, g1) of the current state into out[G*5].
 void enqueue_stress_heat(duwp_ctx *ctx, int g0, int g1, double *out);
+// Device address of the staging array of duwp_moments_noalloc on device dev (taken
+// once per device, with that device current).
+hipError_t noalloc_setup(int dev, double **ptr);
 }  // namespace duwp

@@ -135,6 +135,8 @@ def lib():
         L.duwp_step.argtypes = [P, C.c_int32]
         L.duwp_moments.restype = C.c_int
         L.duwp_moments.argtypes = [P, C.c_int32, C.c_int32, dp, C.c_int64, C.c_int32]
+        L.duwp_moments_noalloc.restype = C.c_int
+        L.duwp_moments_noalloc.argtypes = [P, C.c_int32, C.c_int32, C.c_void_p, C.c_int64]
         L.duwp_avg_count.restype = C.c_int64
         L.duwp_avg_count.argtypes = [P]
         L.duwp_reset_average.restype = C.c_int
@@ -290,6 +292,12 @@ class Sim:
         out = np.zeros(nc * 5)
         _check(lib().duwp_moments(self.ptr, case_id, what, _p(out), out.size, 0), "duwp_moments")
         return out.reshape(nc, 5)
+
+    def moments_noalloc(self, out_ptr: int, length: int, case_id: int = 0, what: int = M_PRIM) -> None:
+        """duwp_moments_noalloc into device memory at out_ptr (length doubles), queued
+        on the context's stream; nothing is allocated and nothing waits."""
+        _check(lib().duwp_moments_noalloc(self.ptr, case_id, what, C.c_void_p(out_ptr), length),
+               "duwp_moments_noalloc")
 
     def avg_count(self) -> int:
         return lib().duwp_avg_count(self.ptr)
