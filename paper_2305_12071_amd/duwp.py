@@ -82,11 +82,13 @@ class TorchAllocator:
         self.device = torch.cuda.current_device()
         self.stream = stream
         self.live = 0
+        self.last_error = None
 
         def _alloc(nbytes, _ctx):
             try:
                 ptr = self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
-            except Exception:        # out of memory: the library reports DUWP_ENOMEM
+            except Exception as e:   # out of memory: the library reports DUWP_ENOMEM
+                self.last_error = f"{type(e).__name__} for {int(nbytes)} bytes: {e}"
                 return None
             self.live += 1
             return ptr
@@ -247,7 +249,10 @@ class Sim:
             raise ValueError(f"allocator {allocator!r}")
         self.precision = precision
         self.ptr = C.c_void_p()
-        _check(lib().duwp_init(C.byref(self.ptr), arr, len(cases), C.byref(o)), "duwp_init")
+        st = lib().duwp_init(C.byref(self.ptr), arr, len(cases), C.byref(o))
+        if st != 0 and self.allocator is not None and self.allocator.last_error:
+            raise DuwpError(st, f"duwp_init (torch allocator: {self.allocator.last_error[:300]})")
+        _check(st, "duwp_init")
         global _live
         if _live is None:
             import atexit

@@ -229,3 +229,20 @@ def test_tuned_big_cell_collide_mixed_equals_default(tune):
     assert g.diag(0)["n_coll"].sum() > 1000
     g.close()
     d.close()
+
+
+def test_closing_graph_contexts_returns_their_memory():
+    """A context closed right after graph replays (no synchronization by the caller)
+    returns every device buffer: free memory after three such contexts is what it
+    was before the first."""
+    import torch
+    c = I.mach8_shock(1000, 1e7)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for k in range(3):
+        g = duwp.Sim(c, seed=1, precision=duwp.MIXED, use_graph=True, allocator="hip")
+        g.step(3)
+        g.close()
+    torch.cuda.synchronize()
+    lost = free0 - torch.cuda.mem_get_info()[0]
+    assert lost < 64 << 20, lost        # each context holds about 0.7 GB
