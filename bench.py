@@ -328,35 +328,20 @@ def leg_batched(args, graph, legs):
         states = [sf.get_state(k) for k in range(len(cases))]
     sf.close()
     # the same cases one context each, plain FP64, one after another (timed steps only)
-    tot_ps, tot_t = 0, 0.0
-    for c in cases:
-        cfg1 = config_for([c], duwp.FP64, args)
-        s1, p1, t1 = run_path([c], duwp.FP64, args.single_steps, 3, graph, cfg1)
-        s1.close()
-        tot_ps += p1
-        tot_t += t1
-    out["one_context_per_case_fp64"] = tot_ps / tot_t
-    out["batched_fp64_over_one_by_one"] = out["fp64_value"] / out["one_context_per_case_fp64"]
-    out["batched_mixed_over_one_by_one"] = out["value"] / out["one_context_per_case_fp64"]
-    log(f"  one context per case, FP64: {out['one_context_per_case_fp64']:.4e} particle-steps/s")
-    # profile error over 500 steps (average of the last 250), per case
-    S, A = args.batched_precision_steps, args.batched_precision_steps // 2
-    pm = averaged_profiles(cases, duwp.MIXED, S, A, cfg_m, 1)
-    pf = averaged_profiles(cases, duwp.FP64, S, A, cfg_f, 1)
-    pg = averaged_profiles(cases, duwp.FP64, S, A, cfg_f, 2)
-    gaps = [rel_l2(a, b) for a, b in zip(pm, pf)]
-    floor = [rel_l2(a, b) for a, b in zip(pg, pf)]
-    q = ("rho", "U", "T")
-    ratio = [max(g[k] for k in q) / max(max(f[k] for k in q), 1e-300) for g, f in zip(gaps, floor)]
-    out["profile_error"] = {
-        "steps": S, "averaged_steps": S - A,
-        "norm": "relative L2 over the cells per case, rho U T",
-        "mixed_vs_fp64": {"median": {k: float(np.median([g[k] for g in gaps])) for k in q},
-                          "max": {k: float(max(g[k] for g in gaps)) for k in q}},
-        "fp64_seed_to_seed": {"median": {k: float(np.median([f[k] for f in floor])) for k in q},
-                              "max": {k: float(max(f[k] for f in floor)) for k in q}},
-        "ratio_to_seed_gap": {"median": float(np.median(ratio)), "max": float(max(ratio))}}
-    log("  profile error:", json.dumps(out["profile_error"]))
+    if args.single_steps > 0:
+        tot_ps, tot_t = 0, 0.0
+        for c in cases:
+            cfg1 = config_for([c], duwp.FP64, args)
+            s1, p1, t1 = run_path([c], duwp.FP64, args.single_steps, 3, graph, cfg1)
+            s1.close()
+            tot_ps += p1
+            tot_t += t1
+        out["one_context_per_case_fp64"] = tot_ps / tot_t
+        out["batched_fp64_over_one_by_one"] = out["fp64_value"] / out["one_context_per_case_fp64"]
+        out["batched_mixed_over_one_by_one"] = out["value"] / out["one_context_per_case_fp64"]
+        log(f"  one context per case, FP64: {out['one_context_per_case_fp64']:.4e} particle-steps/s")
+    if args.batched_precision_steps > 0:
+        out["profile_error"] = batched_profile_error(args, cases, cfg_m, cfg_f)
     if states is not None:
         n0 = sum(len(s["x"]) for s in states)
         ps, dt, nthr = oracle_pool(cases, states, 1, args.cpu_batched_steps)
@@ -367,6 +352,31 @@ def leg_batched(args, graph, legs):
                                        f"state after warm-up ({n0} particles), one case per thread at a time, "
                                        f"{dt:.1f}s"}
         log(f"  oracle over the cases: {ps / dt:.3e} particle-steps/s on {nthr} threads")
+    return out
+
+
+def batched_profile_error(args, cases, cfg_m, cfg_f):
+    """Per case: rho, U, T averaged over the second half of the run, mixed against FP64
+    (same seed), beside FP64 against FP64 (another seed); medians and maxima over the
+    cases, and the ratio of the two gaps."""
+    from paper_2305_12071_amd import duwp
+    S, A = args.batched_precision_steps, args.batched_precision_steps // 2
+    pm = averaged_profiles(cases, duwp.MIXED, S, A, cfg_m, 1)
+    pf = averaged_profiles(cases, duwp.FP64, S, A, cfg_f, 1)
+    pg = averaged_profiles(cases, duwp.FP64, S, A, cfg_f, 2)
+    gaps = [rel_l2(a, b) for a, b in zip(pm, pf)]
+    floor = [rel_l2(a, b) for a, b in zip(pg, pf)]
+    q = ("rho", "U", "T")
+    ratio = [max(g[k] for k in q) / max(max(f[k] for k in q), 1e-300) for g, f in zip(gaps, floor)]
+    out = {
+        "steps": S, "averaged_steps": S - A,
+        "norm": "relative L2 over the cells per case, rho U T",
+        "mixed_vs_fp64": {"median": {k: float(np.median([g[k] for g in gaps])) for k in q},
+                          "max": {k: float(max(g[k] for g in gaps)) for k in q}},
+        "fp64_seed_to_seed": {"median": {k: float(np.median([f[k] for f in floor])) for k in q},
+                              "max": {k: float(max(f[k] for f in floor)) for k in q}},
+        "ratio_to_seed_gap": {"median": float(np.median(ratio)), "max": float(max(ratio))}}
+    log("  profile error:", json.dumps(out))
     return out
 
 
@@ -456,8 +466,9 @@ def main():
     ap.add_argument("--precision-replicas", type=int, default=4)
     ap.add_argument("--batched-cases", type=int, default=256)
     ap.add_argument("--batched-steps", type=int, default=50)
-    ap.add_argument("--batched-precision-steps", type=int, default=500)
-    ap.add_argument("--single-steps", type=int, default=20, help="timed steps per case, one context each")
+    ap.add_argument("--batched-precision-steps", type=int, default=500, help="0: leave out")
+    ap.add_argument("--single-steps", type=int, default=20,
+                    help="timed steps per case, one context each (0: leave out)")
     ap.add_argument("--large-particles", type=float, default=1e9)
     ap.add_argument("--large-steps", type=int, default=5)
     ap.add_argument("--c2-steps", type=int, default=2000)
@@ -466,7 +477,7 @@ def main():
     ap.add_argument("--cpu-c2-steps", type=int, default=4)
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
+                    help="first run kernels of known traffic on 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -483,10 +494,13 @@ def main():
     torch.cuda.set_device(0)
     duwp.lib()
     if args.calibrate_copy:
+        # kernels of known traffic for the byte counters: a fill writes 1 GiB, a
+        # scale reads 1 GiB and writes 1 GiB, a sum reads 1 GiB
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.mul(a, 2.0, out=b)
+            float(a.sum())
         torch.cuda.synchronize()
         del a, b
     case = I.mach8_shock(args.cells, args.particles)

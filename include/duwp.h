@@ -95,8 +95,9 @@ typedef struct {
     int32_t scatter_items;        /* particles per thread and chunk of multi-wave scatter blocks: 2 or 4 (0: 4) */
     int32_t big_block;            /* threads (candidates per chunk) of the block-per-cell collide:
                                      256, 512 or 1024 (0: 512 with FP32 particles, 256 with FP64) */
-    int32_t big_blocks_per_cu;    /* resident blocks of that kernel per compute unit: 1 or 2 (0: 2; a
-                                     1024-thread block with FP64 particles needs 1) */
+    int32_t big_blocks_per_cu;    /* blocks of that kernel per compute unit, 1..8 (0: 2, or 1 for
+                                     1024 threads); more than the compute unit's LDS holds at once
+                                     run one after another */
     int32_t big_min_particles;    /* a cell collides in that kernel when it holds at least this many
                                      particles ... (0: 4096; at least 64) */
     int32_t big_min_candidates;   /* ... and draws at least this many candidates (0: 4096; at least 64) */

@@ -112,8 +112,8 @@ def _candidates(knob: str, precision: int, ncells: int, has_big: bool):
         if not has_big:
             return []
         if precision == duwp.MIXED:
-            return [(256, 2), (512, 2), (512, 1), (1024, 1)]
-        return [(256, 2), (256, 1), (512, 1), (1024, 1)]
+            return [(256, 2), (256, 4), (256, 6), (512, 2), (512, 3), (512, 1), (1024, 1)]
+        return [(256, 2), (256, 4), (256, 1), (512, 1), (1024, 1)]
     if knob == "big_min":
         return [1024, 4096, 16384] if has_big else []
     if knob == "collide_by_cell_max":

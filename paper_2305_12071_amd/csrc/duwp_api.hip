@@ -26,9 +26,8 @@ bool tune_valid(const duwp_tune &t, int precision)
     if (t.reserved != 0) return false;
     if (t.scatter_items != 0 && t.scatter_items != 2 && t.scatter_items != 4) return false;
     if (t.big_block != 0 && t.big_block != 256 && t.big_block != 512 && t.big_block != 1024) return false;
-    if (t.big_blocks_per_cu < 0 || t.big_blocks_per_cu > 2) return false;
-    // a 1024-thread FP64 block needs more than half the compute unit's LDS
-    if (precision == DUWP_FP64 && t.big_block == 1024 && t.big_blocks_per_cu == 2) return false;
+    if (t.big_blocks_per_cu < 0 || t.big_blocks_per_cu > 8) return false;
+    (void)precision;
     if (t.big_min_particles < 0 || (t.big_min_particles > 0 && t.big_min_particles < 64)) return false;
     if (t.big_min_candidates < 0 || (t.big_min_candidates > 0 && t.big_min_candidates < 64)) return false;
     if (t.collide_by_cell_max < 0) return false;

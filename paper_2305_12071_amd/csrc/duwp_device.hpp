@@ -233,6 +233,23 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double *red)
 // and adds the partner's copy, so the sum of value q ends in lanes 4q..4q+3
 // (the last two steps add those four).  Returns the sum of value lane/4 (0 for
 // q >= N).  17 exchanges instead of 6 per value.
+// One halving step: lanes with bit O set keep the upper H values, the others the
+// lower H, and each adds its partner's copy of the half it keeps.  H and O are
+// template parameters so that every array index is a constant (an index that
+// depends on the lane would turn each access into a chain of selects).
+template <int H, int O>
+__device__ __forceinline__ void spread_step(double (&a)[16], int lane)
+{
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+        const double lo = a[q], hi = a[H + q];
+        const double keep = up ? hi : lo;
+        const double send = up ? lo : hi;
+        a[q] = keep + __shfl_xor(send, O, WAVE);
+    }
+}
+
 template <int N>
 __device__ __forceinline__ double wave_sum_spread(const double (&v)[N])
 {
@@ -241,16 +258,10 @@ __device__ __forceinline__ double wave_sum_spread(const double (&v)[N])
     double a[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) a[q] = q < N ? v[q] : 0.0;
-#pragma unroll
-    for (int h = 8, o = 32; h >= 1; h >>= 1, o >>= 1) {
-        const bool up = (lane & o) != 0;
-#pragma unroll
-        for (int q = 0; q < h; ++q) {
-            const double keep = up ? a[h + q] : a[q];
-            const double send = up ? a[q] : a[h + q];
-            a[q] = keep + __shfl_xor(send, o, WAVE);
-        }
-    }
+    spread_step<8, 32>(a, lane);
+    spread_step<4, 16>(a, lane);
+    spread_step<2, 8>(a, lane);
+    spread_step<1, 4>(a, lane);
     double e = a[0];
     e += __shfl_xor(e, 2, WAVE);
     e += __shfl_xor(e, 1, WAVE);

@@ -1373,7 +1373,7 @@ __device__ __forceinline__ void add_phi(double (&a)[5], double u, double v, doub
 
 // Items per thread and chunk, and the waves per SIMD the register budget is cut
 // for (FP32 particles): one-wave blocks (small cells) and blocks of several waves.
-constexpr int SCAT_IT1 = 2, SCAT_W1 = 5;
+constexpr int SCAT_IT1 = 2, SCAT_W1 = 7;
 constexpr int SCAT_WN = 1;
 
 template <typename T, int MAXW, int IT>

@@ -108,10 +108,8 @@ def test_init_rejects_bad_descriptors_before_any_device_call():
     assert _init_status([good], precision=7) == EINVAL
     for bc in (100, 1024, 96):
         assert _init_status([good], block_cells=bc) == EINVAL, bc
-    for t in (dict(scatter_items=3), dict(big_block=128), dict(big_block=2048), dict(big_blocks_per_cu=3),
+    for t in (dict(scatter_items=3), dict(big_block=128), dict(big_block=2048), dict(big_blocks_per_cu=9),
               dict(big_min_particles=10), dict(big_min_candidates=-1), dict(collide_by_cell_max=-5),
               dict(count_dests=6), dict(count_dests=512), dict(reserved=1)):
         assert _init_status([good], tune=t) == EINVAL, t
-    # a 1024-thread FP64 block per cell takes more than half the LDS: one per compute unit
-    assert _init_status([good], tune=dict(big_block=1024, big_blocks_per_cu=2)) == EINVAL
     assert _init_status([good], alloc_only=True) == EINVAL

@@ -209,3 +209,46 @@ def test_big_cells_with_repeated_particles_match_oracle():
     assert (d["n_cand"] >= 4096).all() and (g.get_state()["off"][1:] - g.get_state()["off"][:-1] >= 4096).all()
     compare_states(g.get_state(), o.get_state(), label="box_big", psi_t=o.cells()["psi_t"])
     g.close()
+
+
+def test_mixed_big_cell_collide_follows_the_vhs_rate_and_conserves():
+    """The FP32 block-per-cell collide (512 candidates a chunk) on one cell of 4e4
+    particles between walls at P = 0, over 20 steps after the first: accepted
+    collisions against Bird's VHS rate (N-1)/2 nu dt with nu = 4 beta p / mu(T)
+    (the oracle's pinned law, here from the cell's state at each step start) at
+    4 sigma, and the cell's energy and transverse momenta (walls only reverse u)
+    kept to FP32 rounding of the collided velocities."""
+    c = I.box(1, 1.0, 1.0, 40000, 0.9, name="box_one_big_cell")
+    k = O.Oracle(c).constants()
+    g = duwp.Sim(c, seed=6, precision=duwp.MIXED, use_graph=True)
+    g.step(1)
+    _say("mixed big-cell collide")
+
+    def totals():
+        st = g.get_state()
+        return (len(st["x"]), (st["v"]).sum(), (st["w"]).sum(),
+                0.5 * (st["u"] ** 2 + st["v"] ** 2 + st["w"] ** 2).sum(),
+                np.sqrt(st["u"] ** 2 + st["v"] ** 2 + st["w"] ** 2).sum())
+    n0, v0, w0, e0, s0 = totals()
+    tot, exp, ncoll = 0, 0.0, 0
+    for s in range(20):
+        prim = g.moments(0, duwp.M_PRIM)[0]
+        N = g.n_particles()
+        g.step(1)
+        d = g.diag()
+        assert d["n_cand"][0] >= 4096 and d["n_abs"][0] == 0 and d["n_new"][0] == 0
+        rho, T = prim[0], prim[4]
+        mu = k["mu_ref"] * (T / c.T_ref) ** c.omega
+        nu = 4.0 * k["beta"] * rho * c.R * T / mu
+        exp += 0.5 * (N - 1) * nu * c.dt
+        tot += int(d["n_coll"][0])
+    assert abs(tot - exp) < 4.0 * np.sqrt(exp), (tot, exp)
+    n1, v1, w1, e1, s1 = totals()
+    assert n1 == n0
+    # each accepted collision rounds the two velocities it writes: energy and the
+    # transverse momenta move by a few FP32 ulps of the pair's speeds per collision
+    ulp = 2.0 ** -23
+    assert abs(e1 - e0) <= 8 * ulp * (tot / n0) * e0 + 1e-12 * e0, (e1 - e0) / e0
+    for a, b in ((v0, v1), (w0, w1)):
+        assert abs(b - a) <= 8 * ulp * (tot / n0) * s0, (a, b)
+    g.close()
