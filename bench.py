@@ -256,6 +256,28 @@ def oracle_pool(cases, states, seed, steps):
 # Legs
 # ---------------------------------------------------------------------------
 
+def stream_ceiling(nbytes: int = 1600 << 20, reps: int = 20) -> dict:
+    """A plain streaming kernel of the scatter's traffic (read nbytes, write nbytes:
+    torch's elementwise scale of a float buffer), timed with HIP events: the HBM
+    rate a read-once write-once kernel reaches on this device."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_launch": 2 * nbytes, "ms": round(ms, 4), "gbs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1),
+            "kernel": "torch elementwise scale (read once, write once)"}
+
+
 def leg_precision(args, case, cfg_m, cfg_f):
     """The mixed path's profile error where it is defined: rho, U, T time-averaged
     over the last half of the run, relative L2 over the cells against the FP64 path
@@ -318,15 +340,16 @@ def leg_batched(args, graph, legs):
     out["kernels_ms"] = {k: round(v, 4) for k, v in sb.profile(args.profile_steps).items()}
     sb.close()
     log(f"  mixed {out['value']:.4e} particle-steps/s, N={out['particles']}")
-    sf, psf, dtf = run_path(cases, duwp.FP64, args.batched_steps, 5, graph, cfg_f)
-    out["fp64_value"] = psf / dtf
-    out["fp64_config"] = {"block_cells": cfg_f[0], "tune": cfg_f[1], "source": cfg_f[2]}
-    out["mixed_over_fp64"] = out["value"] / out["fp64_value"]
-    log(f"  fp64 {out['fp64_value']:.4e} particle-steps/s")
     states = None
-    if "cpu" in legs:
-        states = [sf.get_state(k) for k in range(len(cases))]
-    sf.close()
+    if not args.no_batched_fp64:
+        sf, psf, dtf = run_path(cases, duwp.FP64, args.batched_steps, 5, graph, cfg_f)
+        out["fp64_value"] = psf / dtf
+        out["fp64_config"] = {"block_cells": cfg_f[0], "tune": cfg_f[1], "source": cfg_f[2]}
+        out["mixed_over_fp64"] = out["value"] / out["fp64_value"]
+        log(f"  fp64 {out['fp64_value']:.4e} particle-steps/s")
+        if "cpu" in legs:
+            states = [sf.get_state(k) for k in range(len(cases))]
+        sf.close()
     # the same cases one context each, plain FP64, one after another (timed steps only)
     if args.single_steps > 0:
         tot_ps, tot_t = 0, 0.0
@@ -337,7 +360,8 @@ def leg_batched(args, graph, legs):
             tot_ps += p1
             tot_t += t1
         out["one_context_per_case_fp64"] = tot_ps / tot_t
-        out["batched_fp64_over_one_by_one"] = out["fp64_value"] / out["one_context_per_case_fp64"]
+        if "fp64_value" in out:
+            out["batched_fp64_over_one_by_one"] = out["fp64_value"] / out["one_context_per_case_fp64"]
         out["batched_mixed_over_one_by_one"] = out["value"] / out["one_context_per_case_fp64"]
         log(f"  one context per case, FP64: {out['one_context_per_case_fp64']:.4e} particle-steps/s")
     if args.batched_precision_steps > 0:
@@ -467,6 +491,7 @@ def main():
     ap.add_argument("--batched-cases", type=int, default=256)
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--batched-precision-steps", type=int, default=500, help="0: leave out")
+    ap.add_argument("--no-batched-fp64", action="store_true", help="the batched leg without its FP64 path")
     ap.add_argument("--single-steps", type=int, default=20,
                     help="timed steps per case, one context each (0: leave out)")
     ap.add_argument("--large-particles", type=float, default=1e9)
@@ -519,6 +544,11 @@ def main():
         log(f"  {args.steps} steps in {dt:.3f}s -> {value:.4e} particle-steps/s")
         roofline, kernels = roofline_of(sim, args.profile_steps, case.name, cfg_m[0],
                                         cfg_m[1].get("scatter_items", 4))
+        if not args.calibrate_copy:     # (profiling runs keep their kernel list to the step's)
+            ceil = stream_ceiling()
+            roofline["stream_ceiling_gbs"] = ceil["gbs"]
+            roofline["frac_of_stream_ceiling"] = round(roofline["achieved"] / ceil["gbs"], 4)
+            log("  streaming ceiling:", json.dumps(ceil))
         log("  kernels (ms):", json.dumps(kernels))
         if "cpu" in legs:
             from oracle import oracle as O

@@ -252,3 +252,45 @@ def test_mixed_big_cell_collide_follows_the_vhs_rate_and_conserves():
     for a, b in ((v0, v1), (w0, w1)):
         assert abs(b - a) <= 8 * ulp * (tot / n0) * s0, (a, b)
     g.close()
+
+
+def test_restores_inside_the_256_case_batch_stay_in_proportion_to_the_case():
+    """Sixteen cases spread through the 256-case batch (9.8e7 particles) restored with
+    one particle fewer each: every restore moves only the later cases' records on the
+    device (host work in proportion to the case, well under 0.1 s), one step later the
+    untouched cases equal those of a context that was never restored, bit for bit."""
+    import time
+    cases = I.batched_cases(256)
+    _say("restores in the 256-case batch")
+    g = duwp.Sim(cases, seed=1, precision=duwp.MIXED, use_graph=True, block_cells=64)
+    ref = duwp.Sim(cases, seed=1, precision=duwp.MIXED, use_graph=True, block_cells=64)
+    g.step(3)
+    ref.step(3)
+    picked = list(range(3, 256, 16))
+    states = {}
+    for k in picked:
+        st = g.get_state(k)
+        i = int(st["off"][1]) - 1            # the last particle of the first cell goes
+        assert i >= 0
+        st = dict(st, off=np.concatenate([st["off"][:1], st["off"][1:] - 1]),
+                  **{a: np.delete(st[a], i) for a in ("x", "u", "v", "w")})
+        del st["psi_p"]
+        states[k] = st
+    t = time.perf_counter()
+    for k in picked:
+        g.set_state(states[k], k)
+    per = (time.perf_counter() - t) / len(picked)
+    _say(f"  {per * 1e3:.1f} ms per restore")
+    assert per < 0.1, per
+    for k in picked:
+        assert g.n_particles(k) == len(states[k]["x"])
+    g.step(1)
+    ref.step(1)
+    for k in range(0, 256, 5):
+        if k in picked:
+            continue
+        a, b = g.get_state(k), ref.get_state(k)
+        for key in ("x", "u", "v", "w", "off", "psi_w", "cr_max", "psi_p"):
+            assert np.array_equal(a[key], b[key]), (k, key)
+    g.close()
+    ref.close()
