@@ -206,6 +206,20 @@ def rel_l2(a, b) -> dict:
     return out
 
 
+def leg_roofline(kernel, instance, workload, ms, alg_bytes):
+    """A leg's dominant kernel against the HBM peak: its algorithmic bytes per launch,
+    and the bytes HBM really moved for it (committed counters, when current)."""
+    tr = counted_traffic(instance, workload)
+    out = {"bound": "hbm", "kernel": kernel, "instance": instance, "kernel_ms": ms,
+           "algorithmic_bytes": int(alg_bytes),
+           "achieved": round(alg_bytes / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": tr[0] if tr else None}
+    if tr:
+        out["traffic_gbs"] = round(tr[0] / (ms * 1e-3) / 1e9, 1)
+        out["traffic_frac"] = round(tr[0] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
+
+
 def roofline_of(sim, profile_steps, workload, block_cells, scat_items):
     """Dominant particle-streaming kernel: algorithmic bytes over its event-timed duration."""
     kms = sim.profile(profile_steps)
@@ -338,7 +352,11 @@ def leg_batched(args, graph, legs):
            "precision": "fp32 particles + fp64 cells",
            "config": {"block_cells": cfg_m[0], "tune": cfg_m[1], "source": cfg_m[2]}}
     out["kernels_ms"] = {k: round(v, 4) for k, v in sb.profile(args.profile_steps).items()}
+    prof_ps = sb.particle_steps(reset=True) / args.profile_steps
     sb.close()
+    out["roofline"] = leg_roofline("scatter", "k_scatter<float, 1, 2>" if cfg_m[0] == 64 else
+                                   f"k_scatter<float, 8, {cfg_m[1].get('scatter_items', 4)}>",
+                                   "batched256", out["kernels_ms"]["scatter"], BYTES_PER_PARTICLE["scatter"](4) * prof_ps)
     log(f"  mixed {out['value']:.4e} particle-steps/s, N={out['particles']}")
     states = None
     if not args.no_batched_fp64:
@@ -424,6 +442,12 @@ def leg_large(args, graph):
     out["wave_mass_fraction"] = round(float(wave), 4)
     out["kernels_ms"] = {k: round(v, 3) for k, v in sl.profile(1).items()}
     sl.close()
+    # the big-cell collide reads and writes particle records at random inside cells of
+    # 0.8 MB: its algorithmic bytes are those records (16 B each: two reads per
+    # candidate, two writes per accepted pair); HBM moves whole lines for them
+    cand, acc = out["collision_candidates_per_step"], out["accepted_collisions_per_step"]
+    out["roofline"] = leg_roofline("collide_big", "k_collide_big<float, 512>", c.name, out["kernels_ms"]["collide_big"],
+                                   16.0 * (2 * cand + 2 * acc))
     log(f"  {out['value']:.4e} particle-steps/s, {out['ms_per_step']:.1f} ms/step, N={out['particles']}")
     return out
 
