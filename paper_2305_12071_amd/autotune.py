@@ -115,7 +115,7 @@ def _candidates(knob: str, precision: int, ncells: int, has_big: bool):
             return [(256, 2), (256, 4), (256, 6), (512, 2), (512, 3), (512, 1), (1024, 1)]
         return [(256, 2), (256, 4), (256, 1), (512, 1), (1024, 1)]
     if knob == "big_min":
-        return [1024, 4096, 16384] if has_big else []
+        return [256, 1024, 4096, 16384] if has_big else []
     if knob == "collide_by_cell_max":
         # a wave per cell, or work items from the candidate list, where both apply
         return [ncells, max(ncells - 1, 1)] if 512 <= ncells <= (1 << 16) else []
@@ -156,12 +156,12 @@ def time_config(cases, precision: int, cfg: dict, steps: int, warmup: int) -> fl
 
 
 def _has_big_cells(cases, precision: int) -> bool:
-    """Whether any cell reaches the block-per-cell collide at its lowest threshold
-    after a few steps (particles and candidates per cell from duwp_diag)."""
+    """Whether any cell draws as many candidates as the lowest threshold of the
+    block-per-cell collide after a few steps (candidates per cell from duwp_diag)."""
     sim = duwp.Sim(cases, seed=1, precision=precision, use_graph=False)
     try:
         sim.step(2)
-        return any((sim.diag(k)["n_cand"] >= 1024).any() for k in range(len(cases)))
+        return any((sim.diag(k)["n_cand"] >= 256).any() for k in range(len(cases)))
     finally:
         sim.close()
 

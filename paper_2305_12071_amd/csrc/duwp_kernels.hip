@@ -387,17 +387,18 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
         double ss[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         if (nnew > 0) {
             const double *Wc = cl.wt + (int64_t)g * 5;
+            const Maxwell<T> mw(Wc[1], Wc[2], Wc[3], Wc[4], ck.R);
             for (int q = threadIdx.x; q < nnew; q += blockDim.x) {
                 U4 a = draw(ck, step, (uint32_t)lc, (uint32_t)q, TAG_RVEL, 0);
                 U4 bb = draw(ck, step, (uint32_t)lc, (uint32_t)q, TAG_RVEL, 1);
-                double uu[6] = {u01(a.b), u01(a.c), u01(a.d), u01(bb.a), u01(bb.b), u01(bb.c)};
+                const uint32_t w6[6] = {a.b, a.c, a.d, bb.a, bb.b, bb.c};
                 T xi[3];
-                maxwell_t<T>(Wc[1], Wc[2], Wc[3], Wc[4], ck.R, uu, xi);
+                mw.sample(w6, xi);
                 T px;
                 if constexpr (std::is_same<T, double>::value) {
                     px = ck.x_lo + ((double)lc + u01(a.a)) * ck.dx;
                 } else {
-                    px = (float)u01(a.a);
+                    px = u01f(a.a);
                     if (px >= 1.0f) px = 0.99999994f;
                 }
                 T pu = xi[0], pv = xi[1], pw = xi[2];
@@ -935,6 +936,7 @@ __global__ void __launch_bounds__(256) k_inject_gen(const DCase *__restrict__ ca
     if (blockIdx.x == 0 && threadIdx.x == 0) inj.ncand[blockIdx.y] = ng;
     const int64_t cb = c.cand_base[side];
     __shared__ int scr[16];
+    const Maxwell<T> mw(U, 0.0, 0.0, Ts, c.R);
     // 256-slot chunks; the entrants of a chunk are compacted, in slot order, to its front
     for (int64_t ci = blockIdx.x; ci * 256 < ng; ci += gridDim.x) {
         const int64_t q = ci * 256 + threadIdx.x;
@@ -943,9 +945,9 @@ __global__ void __launch_bounds__(256) k_inject_gen(const DCase *__restrict__ ca
         if (q < ng) {
             U4 a = draw(c, step, (uint32_t)side, (uint32_t)q, TAG_IVEL, 0);
             U4 bb = draw(c, step, (uint32_t)side, (uint32_t)q, TAG_IVEL, 1);
-            double uu[6] = {u01(a.b), u01(a.c), u01(a.d), u01(bb.a), u01(bb.b), u01(bb.c)};
+            const uint32_t w6[6] = {a.b, a.c, a.d, bb.a, bb.b, bb.c};
             T xi[3];
-            maxwell_t<T>(U, 0.0, 0.0, Ts, c.R, uu, xi);
+            mw.sample(w6, xi);
             if constexpr (std::is_same<T, double>::value) {
                 double x = side == 0 ? c.x_lo - u01(a.a) * Lg : c.x_hi + u01(a.a) * Lg;
                 double u = xi[0];
@@ -955,7 +957,7 @@ __global__ void __launch_bounds__(256) k_inject_gen(const DCase *__restrict__ ca
             } else {
                 float u = xi[0];
                 const float lgc = (float)(Lg / c.dx);
-                const float X0 = side == 0 ? -(float)u01(a.a) * lgc : (float)u01(a.a) * lgc;
+                const float X0 = side == 0 ? -u01f(a.a) * lgc : u01f(a.a) * lgc;
                 const float X = X0 + u * c.dtdx_f;
                 const float fl = floorf(X);
                 float s = 0.0f;

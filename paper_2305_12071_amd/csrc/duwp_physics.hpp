@@ -46,40 +46,49 @@ __device__ __forceinline__ uint32_t pick(const U4 &r, uint32_t i)
     return i == 0 ? r.a : (i == 1 ? r.b : (i == 2 ? r.c : r.d));
 }
 
-// Maxwellian velocity, one (cos, log) pair of uniforms per component (Eq. maxsample)
-__device__ __forceinline__ void maxwell(double U, double V, double W, double T, double R,
-                                        const double uu[6], double out[3])
-{
-    double sd = sqrt(2.0 * R * T);
-    double mean[3] = {U, V, W};
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-        out[d] = mean[d] + sd * cos(D_TWO_PI * uu[2 * d]) * sqrt(-log(1.0 - uu[2 * d + 1]));
-}
-
-// The same draw for FP32 particles: the velocity is stored in FP32, so it is
-// computed in FP32 (1 - u' is formed in FP64 first, so its 2^-32 resolution and
-// the tail of the distribution are kept).
-__device__ __forceinline__ void maxwell_f(double U, double V, double W, double T, double R,
-                                          const double uu[6], float out[3])
-{
-    const float sd = sqrtf((float)(2.0 * R * T));
-    const float mean[3] = {(float)U, (float)V, (float)W};
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-        out[d] = mean[d] + sd * cosf(6.2831853f * (float)uu[2 * d]) * sqrtf(-logf((float)(1.0 - uu[2 * d + 1])));
-}
-
+// Maxwellian velocity, one (cos, log) pair of uniforms per component (Eq. maxsample):
+// xi_d = U_d + sqrt(2 R T) cos(2 pi u) sqrt(-ln(1 - u')), the uniforms from the
+// words w[2d] and w[2d+1].  The sampler of one state is set up once per cell.
 template <typename T>
-__device__ __forceinline__ void maxwell_t(double U, double V, double W, double T_, double R, const double uu[6],
-                                          T out[3])
-{
-    if constexpr (std::is_same<T, double>::value) {
-        maxwell(U, V, W, T_, R, uu, out);
-    } else {
-        maxwell_f(U, V, W, T_, R, uu, out);
+struct Maxwell;
+
+template <>
+struct Maxwell<double> {
+    double mean[3], sd;
+    __device__ Maxwell(double U, double V, double W, double T, double R) : mean{U, V, W}, sd(sqrt(2.0 * R * T)) {}
+    __device__ __forceinline__ void sample(const uint32_t w[6], double out[3]) const
+    {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            out[d] = mean[d] + sd * cos(D_TWO_PI * u01(w[2 * d])) * sqrt(-log(1.0 - u01(w[2 * d + 1])));
     }
+};
+
+// FP32 particles: the velocity is stored in FP32, so it is computed in FP32.  The
+// uniforms are the nearest floats to w 2^-32 and to 1 - w 2^-32 (formed from the
+// integer 2^32 - w, so the tail keeps its 2^-32 resolution): the values of the
+// exact FP64 uniforms rounded to FP32.  cos(2 pi u) is taken as cospi(2u), whose
+// argument is exact.
+__device__ __forceinline__ float u01f(uint32_t r) { return (float)r * 2.3283064365386962890625e-10f; }
+__device__ __forceinline__ float one_minus_u01f(uint32_t r)
+{
+    return r == 0u ? 1.0f : (float)(0u - r) * 2.3283064365386962890625e-10f;
 }
+
+template <>
+struct Maxwell<float> {
+    float mean[3], sd;
+    __device__ Maxwell(double U, double V, double W, double T, double R)
+        : mean{(float)U, (float)V, (float)W}, sd(sqrtf((float)(2.0 * R * T)))
+    {
+    }
+    __device__ __forceinline__ void sample(const uint32_t w[6], float out[3]) const
+    {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            out[d] = mean[d] + sd * cospif(2.0f * u01f(w[2 * d])) * sqrtf(-logf(one_minus_u01f(w[2 * d + 1])));
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Free flight and boundaries.  Returns the local destination cell, -1 if the

@@ -294,3 +294,26 @@ def test_restores_inside_the_256_case_batch_stay_in_proportion_to_the_case():
             assert np.array_equal(a[key], b[key]), (k, key)
     g.close()
     ref.close()
+
+
+@pytest.mark.parametrize("k", [0, 4], ids=["kn1e-4", "kn1"])
+def test_sod_kn_sweep_step_from_developed_state_matches_oracle(k):
+    """The Kn sweep's 1000-cell Sod tubes with 1e6 particles, in their own batched
+    context and the tuned launch shape: after 50 GPU steps, one FP64 step from that
+    state matches the oracle's step from the same state."""
+    from paper_2305_12071_amd import autotune
+    cases = I.sod_kn_sweep()
+    hit = autotune.lookup(cases, duwp.FP64)
+    bc, tune = (hit[0], hit[1]) if hit else (0, {})
+    _say("sod sweep tube", k, "block", bc, tune)
+    g = duwp.Sim(cases, seed=2, precision=duwp.FP64, use_graph=True, block_cells=bc, tune=tune)
+    g.step(50)
+    st = g.get_state(k)
+    assert 9e5 < len(st["x"]) < 1.1e6
+    o = O.Oracle(cases[k], seed=2, case_id=k)
+    o.set_state(st)
+    g.step(1)
+    o.step(1)
+    compare_diag(g.diag(k), o.diag(), f"sod{k}")
+    compare_states(g.get_state(k), o.get_state(), label=f"sod{k}", psi_t=o.cells()["psi_t"])
+    g.close()
