@@ -496,7 +496,8 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
     auto chunk = [&](int g, uint32_t q, bool act, bool more) {
         // the cell's particles, constants and pair
         uint32_t i = 0, j = 0;
-        double u2 = 0.0, u3 = 0.0, u4 = 0.0, cm = 1.0, aexp = 0.0;
+        uint32_t w2 = 0, w3 = 0, w4 = 0;
+        double cm = 1.0, aexp = 0.0;
         T xi = 0, ui = 0, vi = 0, wi = 0, xj = 0, uj = 0, vj = 0, wj = 0;
         P4<T> *pr = nullptr;
         int lc = 0, k = 0;
@@ -519,7 +520,7 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
                 i = (uint32_t)mulhi64(r0, (uint64_t)N);
                 j = (uint32_t)mulhi64(r1, (uint64_t)(N - 1));
                 if (j >= i) j += 1;
-                u2 = u01(rb.a); u3 = u01(rb.b); u4 = u01(rb.c);
+                w2 = rb.a; w3 = rb.b; w4 = rb.c;
                 pr = sg + sb;
                 const P4<T> a = pr[i], bq = pr[j];
                 xi = a.x; ui = a.u; vi = a.v; wi = a.w;
@@ -564,7 +565,7 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
                 if (pi >= 0) { ui = fwd[wv][oi][pi]; vi = fwd[wv][oi + 1][pi]; wi = fwd[wv][oi + 2][pi]; }
                 if (pj >= 0) { uj = fwd[wv][oj][pj]; vj = fwd[wv][oj + 1][pj]; wj = fwd[wv][oj + 2][pj]; }
                 const T ui0 = ui, uj0 = uj;
-                if (collide_vals<T>(ui, vi, wi, uj, vj, wj, cm, aexp, u2, u3, u4, seen)) {
+                if (collide_vals<T>(ui, vi, wi, uj, vj, wj, cm, aexp, w2, w3, w4, seen)) {
                     acc = 1;
                     pr[i] = P4<T>{xi, ui, vi, wi};
                     pr[j] = P4<T>{xj, uj, vj, wj};
@@ -667,18 +668,22 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
 // For each of its particles a candidate needs the last earlier candidate of the
 // chunk that touched it: an LDS hash table keyed exactly by particle index
 // records up to BIG_LIST candidates per particle, and the largest one below the
-// candidate's own index is its predecessor.  Candidates then run in block-wide
-// rounds once their (at most two) predecessors have run, taking velocities from
-// the predecessors' LDS slots.  A particle drawn by more than BIG_LIST
-// candidates of one chunk (rare) sends that chunk through a serial path.
+// candidate's own index is its predecessor.  Candidates without predecessors
+// (nearly all of a chunk in a big cell) run at once.  The others wait for their
+// predecessors and take velocities from the predecessors' LDS slots: they are
+// staged in LDS, BIG_DEPCAP at a time in candidate order, and run by one wave in
+// wave-level rounds, so that the collision arithmetic of a chunk is issued about
+// once per wave instead of once per round.  A particle drawn by more than
+// BIG_LIST candidates of one chunk (rare) sends that chunk through a serial path.
 //
 // The random particle reads dominate: the block works on the cell's records in
 // place (one cache line per access), two blocks share a compute unit, and the
-// rounds' barriers order LDS only, so that the stores of a round do not hold up
-// the next.  Histogram moves of accepted collisions are summed in LDS and added
+// barriers inside a chunk order LDS only, so that the stores of the candidates
+// that run first do not hold up the waiting ones.  Histogram moves of accepted collisions are summed in LDS and added
 // once per cell.
 // ---------------------------------------------------------------------------
 constexpr int BIG_LIST = 4;
+constexpr int BIG_DEPCAP = 64;
 
 // B threads (candidates per chunk: 256, 512 or 1024), 2^HBITS hash slots (twice
 // the particles a chunk draws)
@@ -721,18 +726,23 @@ __device__ __forceinline__ void big_pred(const int *hcnt, const uint16_t (*hlst)
     po = (best >= 0 && ci[best] != p) ? 3 : 0;
 }
 
-template <typename T>
-__device__ __forceinline__ void big_pair(const CaseK &c, uint32_t step, int lc, uint32_t q, int32_t N,
-                                         uint32_t &i, uint32_t &j, double &u2, double &u3, double &u4)
+// particles of candidate q (its first draw) and its three uniforms (the second)
+__device__ __forceinline__ void big_idx(const CaseK &c, uint32_t step, int lc, uint32_t q, int32_t N,
+                                        uint32_t &i, uint32_t &j)
 {
     const U4 ra = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 0);
-    const U4 rb = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 1);
     const uint64_t r0 = ((uint64_t)ra.a << 32) | ra.b;
     const uint64_t r1 = ((uint64_t)ra.c << 32) | ra.d;
     i = (uint32_t)mulhi64(r0, (uint64_t)N);
     j = (uint32_t)mulhi64(r1, (uint64_t)(N - 1));
     if (j >= i) j += 1;
-    u2 = u01(rb.a); u3 = u01(rb.b); u4 = u01(rb.c);
+}
+
+__device__ __forceinline__ void big_uni(const CaseK &c, uint32_t step, int lc, uint32_t q, uint32_t &w2,
+                                        uint32_t &w3, uint32_t &w4)
+{
+    const U4 rb = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 1);
+    w2 = rb.a; w3 = rb.b; w4 = rb.c;
 }
 
 // move the pair between destination bins of this step's histogram (summed in hd)
@@ -753,6 +763,14 @@ __device__ __forceinline__ void big_bins(const CaseK &c, int lc, T xi, T ui0, T 
     }
 }
 
+// a candidate that waits for predecessors, staged for the wave that runs it
+template <typename T>
+struct BigDep {
+    T x[2][BIG_DEPCAP], v[6][BIG_DEPCAP];
+    uint32_t u[3][BIG_DEPCAP], p[2][BIG_DEPCAP];
+    int t[BIG_DEPCAP], pred[2][BIG_DEPCAP];   // predecessor * 4 + (0 or 3), or -1
+};
+
 template <typename T, int B>
 __global__ void __launch_bounds__(B) k_collide_big(const DCase *__restrict__ cases, Cells cl,
                                                    P4<T> *src, P4<T> *stg,
@@ -767,27 +785,17 @@ __global__ void __launch_bounds__(B) k_collide_big(const DCase *__restrict__ cas
     __shared__ uint32_t ci[B];
     __shared__ int done[B];
     __shared__ T fwd[6][B];
+    __shared__ BigDep<T> dq;
     __shared__ int hd[NBIN];
     __shared__ double redd[NW];
     __shared__ int redi[NW];
     __shared__ int ovf[2];           // by chunk parity
-    __shared__ int rflag[NW];        // per-wave "still waiting" flags of a round
+    __shared__ int wdep[NW];         // per-wave counts of waiting candidates
     const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
     const int nbig = *cl.nbig;
     if ((int)blockIdx.x >= nbig) return;   // no cell for this block (often none at all)
     const uint32_t step = *d_step;
     for (int s = t; s < SLOTS; s += B) { hkey[s] = 0xffffffffu; hcnt[s] = 0; }
-    // barrier over LDS only (the rounds exchange nothing else through memory),
-    // true when any thread of the block passes v
-    auto lds_any = [&](bool v) {
-        const uint64_t b = __ballot(v);
-        if (lane == 0) rflag[wv] = b != 0;
-        lds_barrier();
-        bool r = false;
-#pragma unroll
-        for (int w2 = 0; w2 < NW; ++w2) r |= rflag[w2] != 0;
-        return r;
-    };
     for (int e = blockIdx.x; e < nbig; e += gridDim.x) {
         const int g = cl.big_list[e];
         const int k = cl.cell_case[g];
@@ -808,16 +816,30 @@ __global__ void __launch_bounds__(B) k_collide_big(const DCase *__restrict__ cas
         __syncthreads();
         double seen = 0.0;
         int acc = 0;
+        // candidate tt on particles a and b with their current records; its
+        // outgoing velocities go to its LDS slot
+        auto run = [&](int tt, uint32_t a, uint32_t b, T xa, T ua, T va, T wa, T xb, T ub, T vb, T wb,
+                       uint32_t v2, uint32_t v3, uint32_t v4) {
+            const T ua0 = ua, ub0 = ub;
+            if (collide_vals<T>(ua, va, wa, ub, vb, wb, cm, aexp, v2, v3, v4, seen)) {
+                ++acc;
+                P[a] = P4<T>{xa, ua, va, wa};
+                P[b] = P4<T>{xb, ub, vb, wb};
+                big_bins<T>(ck, lc, xa, ua0, ua, xb, ub0, ub, hd, far);
+            }
+            fwd[0][tt] = ua; fwd[1][tt] = va; fwd[2][tt] = wa;
+            fwd[3][tt] = ub; fwd[4][tt] = vb; fwd[5][tt] = wb;
+            done[tt] = 1;
+        };
         int par = 0;
         for (int64_t q0 = 0; q0 < M; q0 += B, par ^= 1) {
             const int64_t q = q0 + t;
             const bool act = q < M;
             uint32_t i = 0, j = 0;
-            double u2 = 0.0, u3 = 0.0, u4 = 0.0;
             T xi = 0, ui = 0, vi = 0, wi = 0, xj = 0, uj = 0, vj = 0, wj = 0;
             int si = 0, sj = 0;
             if (act) {
-                big_pair<T>(ck, step, lc, (uint32_t)q, N, i, j, u2, u3, u4);
+                big_idx(ck, step, lc, (uint32_t)q, N, i, j);
                 const P4<T> a = P[i], bq = P[j];
                 xi = a.x; ui = a.u; vi = a.v; wi = a.w;
                 xj = bq.x; uj = bq.u; vj = bq.v; wj = bq.w;
@@ -836,9 +858,9 @@ __global__ void __launch_bounds__(B) k_collide_big(const DCase *__restrict__ cas
                 if (t == 0) {
                     const int nq = (int)min((int64_t)B, M - q0);
                     for (int l = 0; l < nq; ++l) {
-                        uint32_t a, bq;
-                        double v2, v3, v4;
-                        big_pair<T>(ck, step, lc, (uint32_t)(q0 + l), N, a, bq, v2, v3, v4);
+                        uint32_t a, bq, v2, v3, v4;
+                        big_idx(ck, step, lc, (uint32_t)(q0 + l), N, a, bq);
+                        big_uni(ck, step, lc, (uint32_t)(q0 + l), v2, v3, v4);
                         P4<T> ra = P[a], rb = P[bq];
                         const T ua0 = ra.u, ub0 = rb.u;
                         if (collide_vals<T>(ra.u, ra.v, ra.w, rb.u, rb.v, rb.w, cm, aexp, v2, v3, v4, seen)) {
@@ -850,32 +872,68 @@ __global__ void __launch_bounds__(B) k_collide_big(const DCase *__restrict__ cas
                     }
                 }
             } else {
+                uint32_t u2 = 0, u3 = 0, u4 = 0;
                 int pi = -1, pj = -1, oi = 0, oj = 0;
                 if (act) {
+                    big_uni(ck, step, lc, (uint32_t)q, u2, u3, u4);
                     big_pred(hcnt, hlst, ci, si, i, t, pi, oi);
                     big_pred(hcnt, hlst, ci, sj, j, t, pj, oj);
                 }
-                // block-wide rounds: a candidate runs once its predecessors have run
-                bool mine = act;
-                while (true) {
-                    const bool ready = mine && (pi < 0 || done[pi]) && (pj < 0 || done[pj]);
-                    lds_barrier();
-                    if (ready) {
-                        if (pi >= 0) { ui = fwd[oi][pi]; vi = fwd[oi + 1][pi]; wi = fwd[oi + 2][pi]; }
-                        if (pj >= 0) { uj = fwd[oj][pj]; vj = fwd[oj + 1][pj]; wj = fwd[oj + 2][pj]; }
-                        const T ui0 = ui, uj0 = uj;
-                        if (collide_vals<T>(ui, vi, wi, uj, vj, wj, cm, aexp, u2, u3, u4, seen)) {
-                            ++acc;
-                            P[i] = P4<T>{xi, ui, vi, wi};
-                            P[j] = P4<T>{xj, uj, vj, wj};
-                            big_bins<T>(ck, lc, xi, ui0, ui, xj, uj0, uj, hd, far);
-                        }
-                        fwd[0][t] = ui; fwd[1][t] = vi; fwd[2][t] = wi;
-                        fwd[3][t] = uj; fwd[4][t] = vj; fwd[5][t] = wj;
-                        done[t] = 1;
-                        mine = false;
+                const bool waits = pi >= 0 || pj >= 0;
+                // no predecessor: the records read above are current
+                if (act && !waits) run(t, i, j, xi, ui, vi, wi, xj, uj, vj, wj, u2, u3, u4);
+                const uint64_t wb = __ballot(act && waits);
+                if (lane == 0) wdep[wv] = __popcll(wb);
+                lds_barrier();
+                int ndep = 0, before = 0;
+#pragma unroll
+                for (int w2 = 0; w2 < NW; ++w2) {
+                    const int n2 = wdep[w2];
+                    before += w2 < wv ? n2 : 0;
+                    ndep += n2;
+                }
+                // the waiting candidates, BIG_DEPCAP at a time in candidate order, are
+                // staged in LDS and run by wave 0 (their predecessors come earlier)
+                for (int b0 = 0; b0 < ndep; b0 += BIG_DEPCAP) {
+                    if (b0 > 0) lds_barrier();   // wave 0 is done with the previous batch
+                    const int d = before + __popcll(wb & lanemask_lt()) - b0;
+                    if (act && waits && d >= 0 && d < BIG_DEPCAP) {
+                        dq.x[0][d] = xi; dq.x[1][d] = xj;
+                        dq.v[0][d] = ui; dq.v[1][d] = vi; dq.v[2][d] = wi;
+                        dq.v[3][d] = uj; dq.v[4][d] = vj; dq.v[5][d] = wj;
+                        dq.u[0][d] = u2; dq.u[1][d] = u3; dq.u[2][d] = u4;
+                        dq.p[0][d] = i; dq.p[1][d] = j;
+                        dq.t[d] = t;
+                        dq.pred[0][d] = pi < 0 ? -1 : pi * 4 + oi;
+                        dq.pred[1][d] = pj < 0 ? -1 : pj * 4 + oj;
                     }
-                    if (!lds_any(mine)) break;
+                    lds_barrier();
+                    if (wv == 0) {
+                        bool mine = lane < min(BIG_DEPCAP, ndep - b0);
+                        const int e2 = mine ? lane : 0;
+                        const int ti = dq.t[e2], ri = dq.pred[0][e2], rj = dq.pred[1][e2];
+                        T a0 = dq.v[0][e2], a1 = dq.v[1][e2], a2 = dq.v[2][e2];
+                        T c0 = dq.v[3][e2], c1 = dq.v[4][e2], c2 = dq.v[5][e2];
+                        // wave-level rounds: LDS operations of one wave complete in order
+                        while (true) {
+                            const bool ready = mine && (ri < 0 || done[ri >> 2]) && (rj < 0 || done[rj >> 2]);
+                            if (ready) {
+                                if (ri >= 0) {
+                                    const int l = ri >> 2, o = ri & 3;
+                                    a0 = fwd[o][l]; a1 = fwd[o + 1][l]; a2 = fwd[o + 2][l];
+                                }
+                                if (rj >= 0) {
+                                    const int l = rj >> 2, o = rj & 3;
+                                    c0 = fwd[o][l]; c1 = fwd[o + 1][l]; c2 = fwd[o + 2][l];
+                                }
+                                run(ti, dq.p[0][e2], dq.p[1][e2], dq.x[0][e2], a0, a1, a2, dq.x[1][e2], c0, c1, c2,
+                                    dq.u[0][e2], dq.u[1][e2], dq.u[2][e2]);
+                                mine = false;
+                            }
+                            lds_fence();
+                            if (__ballot(mine) == 0) break;
+                        }
+                    }
                 }
             }
             // empty the table for the next chunk; make this chunk's stores visible to it

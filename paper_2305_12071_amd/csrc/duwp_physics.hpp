@@ -396,15 +396,17 @@ __device__ inline void case_face_flux(const DCase &c, const Cells &cl, int f, do
 // ---------------------------------------------------------------------------
 // Equal-mass VHS collision of a particle pair held in registers (Appendix A):
 // acceptance (c_r/c_max)^(1-2 upsilon), isotropic scattering with
-// cos(theta) = 2 u3 - 1, phi = 2 pi u4.  Returns true when accepted (the
-// velocities are then replaced by the post-collision ones).
+// cos(theta) = 2 u3 - 1, phi = 2 pi u4, the uniforms u_k = w_k 2^-32 from the
+// candidate's words.  Returns true when accepted (the velocities are then
+// replaced by the post-collision ones).
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ bool collide_vals(T &ui, T &vi, T &wi, T &uj, T &vj, T &wj, double cm,
-                                             double accept_exp, double u2, double u3, double u4,
+                                             double accept_exp, uint32_t w2, uint32_t w3, uint32_t w4,
                                              double &seen)
 {
     if constexpr (std::is_same<T, double>::value) {
+        const double u2 = u01(w2), u3 = u01(w3), u4 = u01(w4);
         double d0 = ui - uj, d1 = vi - vj, d2 = wi - wj;
         double cr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
         seen = fmax(seen, cr);
@@ -422,12 +424,16 @@ __device__ __forceinline__ bool collide_vals(T &ui, T &vi, T &wi, T &uj, T &vj, 
         float d0 = ui - uj, d1 = vi - vj, d2 = wi - wj;
         float cr = sqrtf(__fmaf_rn(d0, d0, __fmaf_rn(d1, d1, d2 * d2)));
         seen = fmax(seen, (double)cr);
-        float pa = powf(cr / (float)cm, (float)accept_exp);
-        if (!(u2 < (double)pa)) return false;
-        float ct = __fmaf_rn(2.0f, (float)u3, -1.0f);
+        // (c_r/c_max)^a as 2^(a log2(c_r/c_max)); a = 1 (hard spheres) and a = 0
+        // (Maxwell molecules) exactly
+        const float rat = cr / (float)cm, ae = (float)accept_exp;
+        const float pa = ae == 1.0f ? rat : (ae == 0.0f ? 1.0f : exp2f(ae * log2f(rat)));
+        if (!(u01(w2) < (double)pa)) return false;
+        float ct = __fmaf_rn(2.0f, u01f(w3), -1.0f);
         float st = sqrtf(fmaxf(__fmaf_rn(-ct, ct, 1.0f), 0.0f));
+        // phi = 2 pi u4: sin and cos of pi (2 u4), whose argument is exact
         float sp, cp;
-        sincosf((float)D_TWO_PI * (float)u4, &sp, &cp);
+        sincospif(2.0f * u01f(w4), &sp, &cp);
         float h = 0.5f * cr;
         float r0 = h * st * cp, r1 = h * st * sp, r2 = h * ct;
         float m0 = 0.5f * (ui + uj), m1 = 0.5f * (vi + vj), m2 = 0.5f * (wi + wj);
