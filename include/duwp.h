@@ -103,7 +103,7 @@ typedef struct {
     int32_t big_min_candidates;   /* ... and draws at least this many candidates (0: 4096; at least 64) */
     int32_t collide_by_cell_max;  /* up to this many cells in all a wave per cell runs the other cells'
                                      collisions, beyond it work items cut from the candidate list (0: 8192) */
-    int32_t count_dests;          /* destination cells per block of the sort's count and base kernels
+    int32_t count_dests;          /* destination cells per block of the sort's count-and-base kernel
                                      on large grids, a multiple of 4 in 4..256 (0: 256) */
     int32_t reserved;             /* 0 */
 } duwp_tune;

@@ -193,7 +193,7 @@ duwp_status alloc_all(duwp_ctx *ctx)
     c.hist = ctx->hist_buf[0];
     TRY(dalloc(ctx, &c.cnt_new, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.inj_cnt, 4 * (size_t)G));
-    TRY(dalloc(ctx, &c.inj_start, 8 * (size_t)G));
+    TRY(dalloc(ctx, &c.inj_ofs, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.cell_case, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.order, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.avg, 8 * 5 * (size_t)G));

@@ -79,7 +79,7 @@ struct duwp_ctx {
     int big_per_cu = 2;            // its resident blocks per compute unit
     int big_min_n = 4096, big_min_m = 4096;   // cells at least this large collide in it
     int coll_by_cell_max = 8192;   // up to this many cells: a wave per cell in k_collide
-    int count_dests = 256;         // destinations per block of k_count_new / k_bases (large grids)
+    int count_dests = 256;         // destinations per block of k_count_bases (large grids)
 
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     bool graph_ready = false;

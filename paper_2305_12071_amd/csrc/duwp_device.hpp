@@ -80,7 +80,8 @@ struct Cells {
     int32_t *fix_nx;    // [G] same, for the next step
     int32_t *cnt_new;   // [G]
     int32_t *inj_cnt;   // [G] injected entrants per destination cell
-    int64_t *inj_start; // [G] first slot of the injected entrants of each destination cell
+    int32_t *inj_ofs;   // [G] cell-sourced particles of each destination cell: where its entrants
+                        // start, relative to the cell's start in the next array
     int32_t *cell_case; // [G]
     int32_t *order;     // [G] cells in the visiting order of the block-per-cell kernels
     double *avg;        // [G*5]

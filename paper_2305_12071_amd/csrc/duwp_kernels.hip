@@ -1286,45 +1286,15 @@ __device__ __forceinline__ void load_hist_tile(const Cells &cl, int d0, int nd, 
     }
 }
 
-// 7. particles arriving in each destination cell: the bin of source d + l - KWIN
-// pointing at d is 2 KWIN - l.  Large grids (nd > 4): the block's rows through
-// LDS, a thread per destination summing its 33 entries; small grids (nd = 4): a
-// wave per destination, lane = source offset, rows read in place.
-__global__ void __launch_bounds__(256) k_count_new(Cells cl, int G, int nd)
-{
-    __shared__ int tile[CN_ROWS * NBIN];
-    const int d0 = blockIdx.x * nd;
-    if (nd > 4) {
-        load_hist_tile(cl, d0, nd, G, tile);
-        __syncthreads();
-        const int dd = threadIdx.x, d = d0 + dd;
-        if (dd < nd && d < G) {
-            int v = 0;
-#pragma unroll
-            for (int l = 0; l < NBIN; ++l) v += tile[(dd + l) * NBIN + (2 * KWIN - l)];
-            cl.cnt_new[d] = v + cl.inj_cnt[d];
-        }
-        return;
-    }
-    const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int dd = w; dd < nd && d0 + dd < G; dd += nw) {
-        const int d = d0 + dd;
-        const int src = d + lane - KWIN;
-        int v = 0;
-        if (lane < NBIN && src >= 0 && src < G) v = cl.hist[(int64_t)src * NBIN + (2 * KWIN - lane)];
-        v = wave_sum_i(v);
-        if (lane == 0) cl.cnt_new[d] = v + cl.inj_cnt[d];
-    }
-}
-
-// 9. start of each (source cell, destination) group inside its destination segment,
-// in source-cell order; entrants follow the cell-sourced particles.  The
-// exclusive prefix over the sources d + l - KWIN (l = 0..32) of a destination
-// gives the bases, which replace the counts.  Large grids: a thread per
-// destination over the block's rows in LDS (the block writes back the entries
-// of its destinations); small grids: a wave per destination, lane l = source
-// d + l - KWIN, in place.
-__global__ void __launch_bounds__(256) k_bases(Cells cl, const int64_t *__restrict__ off_new, int G, int nd)
+// 7. Per destination cell d, over its sources d + l - KWIN (l = 0..32, whose bin
+// pointing at d is 2 KWIN - l): the start of each (source, d) group inside the
+// segment of d, in source-cell order (an exclusive prefix, replacing the counts
+// in place), the cell-sourced particles of d (where its entrants start) and its
+// count for the next array with the entrants.  Large grids (nd > 4): the block's
+// rows through LDS, a thread per destination (the block writes back the entries
+// of its destinations); small grids (nd = 4): a wave per destination, lane l =
+// source d + l - KWIN, in place.
+__global__ void __launch_bounds__(256) k_count_bases(Cells cl, int G, int nd)
 {
     __shared__ int tile[CN_ROWS * NBIN];
     const int d0 = blockIdx.x * nd;
@@ -1344,7 +1314,10 @@ __global__ void __launch_bounds__(256) k_bases(Cells cl, const int64_t *__restri
             }
             if (ok) cl.hist[gi] = incl - h;
             const int run = __shfl(incl, WAVE - 1, WAVE);
-            if (lane == 0) cl.inj_start[d] = off_new[d] + run;
+            if (lane == 0) {
+                cl.inj_ofs[d] = run;
+                cl.cnt_new[d] = run + cl.inj_cnt[d];
+            }
         }
         return;
     }
@@ -1362,7 +1335,8 @@ __global__ void __launch_bounds__(256) k_bases(Cells cl, const int64_t *__restri
                 tile[ti] = run;
                 run += h;
             }
-            cl.inj_start[d] = off_new[d] + run;
+            cl.inj_ofs[d] = run;
+            cl.cnt_new[d] = run + cl.inj_cnt[d];
         }
     }
     __syncthreads();
@@ -1379,7 +1353,8 @@ __global__ void __launch_bounds__(256) k_bases(Cells cl, const int64_t *__restri
 // entrants of case k.
 template <typename T>
 __device__ __forceinline__ void scatter_entrants(const DCase &c, const Cells &cl, const Inj<T> &inj, P4<T> *dst,
-                                              int64_t cap, int k, int sub, int nsub)
+                                              const int64_t *__restrict__ off_new, int64_t cap, int k, int sub,
+                                              int nsub)
 {
     const int32_t n = inj.count[k];
     const int lane = lane_id();
@@ -1390,7 +1365,7 @@ __device__ __forceinline__ void scatter_entrants(const DCase &c, const Cells &cl
             const int64_t sl = c.inj_base + i;
             const int d = inj.dest[sl];
             if (d >= 0) {      // -1: an entrant reported out of range
-                const int64_t pos = cl.inj_start[d] + inj.rank[sl];
+                const int64_t pos = off_new[d] + cl.inj_ofs[d] + inj.rank[sl];
                 const T x = inj.x[sl], u = inj.u[sl];
                 if (pos < cap) dst[pos] = P4<T>{x, u, inj.v[sl], inj.w[sl]};
                 bool farp = false;
@@ -1413,9 +1388,9 @@ __device__ __forceinline__ void scatter_entrants(const DCase &c, const Cells &cl
 // 11. the entrants of case blockIdx.y, in gridDim.x parts
 template <typename T>
 __global__ void __launch_bounds__(256) k_scatter_inj(const DCase *__restrict__ cases, Cells cl, Inj<T> inj,
-                                                     P4<T> *dst, int64_t cap)
+                                                     P4<T> *dst, const int64_t *__restrict__ off_new, int64_t cap)
 {
-    scatter_entrants<T>(cases[blockIdx.y], cl, inj, dst, cap, blockIdx.y, blockIdx.x, gridDim.x);
+    scatter_entrants<T>(cases[blockIdx.y], cl, inj, dst, off_new, cap, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1757,7 +1732,7 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
                 }
             cl.far_in[d] = 0;
         }
-        ib = cl.inj_start[d];
+        ib = off_new[d] + cl.inj_ofs[d];
         ie = off_new[d + 1];
     }
     uint64_t todo = __ballot(in && ie > ib);
@@ -2075,9 +2050,9 @@ static void step_impl(duwp_ctx *ctx)
                            by_cell);
     }
     if (fork) (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
-    // destinations per block of the two histogram passes: 4 (a wave each, small
-    // grids) or up to 256 (a thread each), so that their grids keep about 1000
-    // blocks or more
+    // destinations per block of the histogram pass before the scatter: 4 (a wave
+    // each, small grids) or up to 256 (a thread each), so that its grid keeps
+    // about 1000 blocks or more
     const int nd = std::max(4, std::min(std::min(CN_D, ctx->count_dests), G / 1024 / 4 * 4));
     {
         Mark m(ctx, "hist_fix");
@@ -2085,16 +2060,21 @@ static void step_impl(duwp_ctx *ctx)
                            ctx->off[p], 0, G, ctx->cap, 0);
     }
     {
-        Mark m(ctx, "count_new");
-        hipLaunchKernelGGL(k_count_new, dim3((G + nd - 1) / nd), dim3(256), 0, st, cl, G, nd);
+        Mark m(ctx, "count_bases");
+        hipLaunchKernelGGL(k_count_bases, dim3((G + nd - 1) / nd), dim3(256), 0, st, cl, G, nd);
     }
     {
         Mark m(ctx, "scan_offsets");
         enqueue_scan(ctx, ctx->cl.cnt_new, ctx->off[p ^ 1], ctx->d_total + 1, ctx->cap);
     }
+    // The entrants' scatter writes its own places of the next array (after the
+    // cell-sourced particles of each cell) and adds to the next histogram
+    // atomically, like the scatter, so the two can go in either order.  (On a
+    // second stream beside the scatter it made the step slower.)
     {
-        Mark m(ctx, "bases");
-        hipLaunchKernelGGL(k_bases, dim3((G + nd - 1) / nd), dim3(256), 0, st, cl, ctx->off[p ^ 1], G, nd);
+        Mark m(ctx, "scatter_inj");
+        hipLaunchKernelGGL(k_scatter_inj<T>, dim3(8, ctx->ncases), dim3(256), 0, st, ctx->d_cases, cl, inj,
+                           dst, ctx->off[p ^ 1], ctx->cap);
     }
     {
         Mark m(ctx, "scatter");
@@ -2107,11 +2087,6 @@ static void step_impl(duwp_ctx *ctx)
         else
             hipLaunchKernelGGL((k_scatter<T, 8, 4>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
                                dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout, ctx->scat_by_order);
-    }
-    {
-        Mark m(ctx, "scatter_inj");
-        hipLaunchKernelGGL(k_scatter_inj<T>, dim3(8, ctx->ncases), dim3(256), 0, st, ctx->d_cases, cl, inj,
-                           dst, ctx->cap);
     }
     {
         Mark m(ctx, "gather_moments");
