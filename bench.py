@@ -292,34 +292,6 @@ def stream_ceiling(nbytes: int = 1600 << 20, reps: int = 20) -> dict:
             "kernel": "torch elementwise scale (read once, write once)"}
 
 
-def random_read_ceiling(rows_log2: int = 30, reads_log2: int = 27, reps: int = 5) -> dict:
-    """Rate of 16-byte reads at random rows of a 16 GiB array (2^30 rows; torch's
-    index_select of complex128 rows: one row per lane, the indices and the output
-    streamed), timed with HIP events: the ceiling of a kernel whose reads land on
-    random particle records of a large array, each in a line of its own."""
-    import torch
-    src = torch.zeros(1 << rows_log2, dtype=torch.complex128, device="cuda")
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(12345)
-    idx = torch.randint(0, 1 << rows_log2, (1 << reads_log2,), device="cuda", generator=gen)
-    out = torch.empty(1 << reads_log2, dtype=torch.complex128, device="cuda")
-    for _ in range(2):
-        torch.index_select(src, 0, idx, out=out)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        torch.index_select(src, 0, idx, out=out)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del src, idx, out
-    torch.cuda.empty_cache()
-    n = 1 << reads_log2
-    return {"reads_per_launch": n, "array_bytes": 16 << rows_log2, "ms": round(ms, 4),
-            "reads_per_s": round(n / (ms * 1e-3), 1),
-            "kernel": "torch index_select of 16-byte rows at random indices (one row per lane)"}
-
-
 def leg_precision(args, case, cfg_m, cfg_f):
     """The mixed path's profile error where it is defined: rho, U, T time-averaged
     over the last half of the run, relative L2 over the cells against the FP64 path
@@ -477,15 +449,9 @@ def leg_large(args, graph):
     inst = f"k_collide_big<float, {cfg[1].get('big_block', 512)}>"
     out["roofline"] = leg_roofline("collide_big", inst, c.name, out["kernels_ms"]["collide_big"],
                                    16.0 * (2 * cand + 2 * acc))
-    # its reads, two records per candidate at random in the cell, beside the rate of
-    # random 16-byte reads over an array of the particle array's size
-    if not args.calibrate_copy:
-        rc = random_read_ceiling()
-        rate = 2 * cand / (out["kernels_ms"]["collide_big"] * 1e-3)
-        out["roofline"]["random_reads_per_s"] = round(rate, 1)
-        out["roofline"]["random_read_ceiling"] = rc
-        out["roofline"]["frac_of_random_read_ceiling"] = round(rate / rc["reads_per_s"], 4)
-        log(f"  random reads: collide {rate:.3e}/s, ceiling {rc['reads_per_s']:.3e}/s")
+    # its record accesses at random inside the cells: two reads per candidate and two
+    # writes per accepted pair, each in a 128-byte line of its own
+    out["roofline"]["record_accesses_per_s"] = round((2 * cand + 2 * acc) / (out["kernels_ms"]["collide_big"] * 1e-3), 1)
     log(f"  {out['value']:.4e} particle-steps/s, {out['ms_per_step']:.1f} ms/step, N={out['particles']}")
     return out
 
