@@ -16,11 +16,12 @@
 //   scan             staging offsets of the cells that change
 //   absorb_resample  classify, absorb into Psi_w, compact survivors, sample
 //                    new particles (Eq. maxsample), subtract their moments
-//   collide          NTC/VHS (Appendix A), one wave per cell, candidates in
-//                    order with conflict-free rounds
+//   collide          NTC/VHS (Appendix A), candidates in order: a wave per
+//                    cell or per work item with conflict-free rounds, or a
+//                    block per big cell
 //   inject_gen/rank  reservoir entrants
 //   hist_fix         recount of the destination histograms of flagged cells
-//   count/scan/bases windowed stable counting-sort offsets
+//   count_bases/scan windowed stable counting-sort counts, group bases, offsets
 //   scatter          free flight again, stable scatter into the next canonical
 //                    array, particle moment sums per destination
 //   scatter_inj      entrants after the cell-sourced particles of their cell
@@ -679,8 +680,8 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
 // The random particle reads dominate: the block works on the cell's records in
 // place (one cache line per access), two blocks share a compute unit, and the
 // barriers inside a chunk order LDS only, so that the stores of the candidates
-// that run first do not hold up the waiting ones.  Histogram moves of accepted collisions are summed in LDS and added
-// once per cell.
+// that run first do not hold up the waiting ones.  Histogram moves of accepted
+// collisions are summed in LDS and added once per cell.
 // ---------------------------------------------------------------------------
 constexpr int BIG_LIST = 4;
 constexpr int BIG_DEPCAP = 64;
