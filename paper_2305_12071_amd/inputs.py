@@ -4,7 +4,7 @@ This module only *describes* inputs: gas constants, initial/boundary states,
 mesh, time step and particle weight for each case.  It contains none of the
 DUWP step arithmetic (no moments, no random streams, no collision or flux
 code) and imports nothing else from this package, so both the HIP path and
-the CPU checker can be driven from it without sharing any method code.
+the oracle can be driven from it without sharing any method code.
 
 Cases follow the paper's test section (shock structure, Sec. 4.1; Sod tube,
 Sec. 4.2 and Table 1) with argon VHS constants.  The shock's downstream state
