@@ -52,7 +52,7 @@ BYTES_PER_PARTICLE = {
     "scatter": lambda s: 8 * s,
     "absorb_resample": lambda s: 8 * s,
 }
-# A textbook model of a whole step when almost nothing is absorbed: each
+# A simple model of a whole step when almost nothing is absorbed: each
 # particle's record read and written once by a cell pass and once by the sort.
 STEP_BYTES_PER_PARTICLE = {"mixed": 64, "fp64": 128}
 KERNEL_HEADERS = ("duwp_physics.hpp", "duwp_device.hpp")
