@@ -23,6 +23,17 @@ def _say(*a):
     sys.stdout.flush()
 
 
+def box_omega(omega, ncells, rho, T, ppc, dt_over_tau, **kw):
+    """I.box with viscosity exponent omega instead of argon's (the reference
+    mean free path set again so that dt/tau at the box state is dt_over_tau)."""
+    c = I.box(ncells, rho, T, ppc, dt_over_tau, **kw)
+    c.omega = omega
+    tau = c.dt / dt_over_tau
+    c.lambda_ref = tau * rho * T ** (1.0 - omega) / (I.vhs_beta(omega) * np.sqrt(2.0 * np.pi))
+    c.name = f"box_omega{omega}"
+    return c
+
+
 def _cases():
     out = {
         "mach3": I.mach3_small(),                       # P = 0: DSMC, reservoirs, injection
@@ -63,6 +74,10 @@ def _cases():
     c = I.argon_shock(3.0, 60, 60 * 20.0, 3e4, name="shock_dx20_stream")
     c.absorb_stream = 1
     out["shock_dx20_stream"] = c
+    # the two VHS limits: hard spheres (acceptance c_r/c_max) and Maxwell
+    # molecules (every candidate accepted), with some absorption
+    out["box_hard_spheres"] = box_omega(0.5, 6, 1.0, 1.0, 400, 2.0)
+    out["box_maxwell_molecules"] = box_omega(1.0, 6, 1.0, 1.0, 400, 1.5)
     return out
 
 
@@ -537,4 +552,32 @@ def test_entrants_beyond_the_window_are_reported():
     with pytest.raises(duwp.DuwpError) as e:
         g.step(2)
     assert e.value.status == -6
+    g.close()
+
+
+@pytest.mark.parametrize("omega", [0.5, 1.0], ids=["hard_spheres", "maxwell_molecules"])
+def test_mixed_collisions_at_the_vhs_limits(omega):
+    """FP32 particles, P = 0 between walls, 12 steps: accepted collisions against
+    Bird's VHS rate (N-1)/2 nu dt per cell, nu = 4 beta p / mu(T) (the oracle's
+    pinned law), at 4 sigma; Maxwell molecules accept every candidate."""
+    c = box_omega(omega, 8, 1.0, 1.0, 3000, 0.05)
+    k = O.Oracle(c).constants()
+    g = duwp.Sim(c, seed=5, precision=duwp.MIXED)
+    g.step(1)
+    _say("mixed VHS limit", omega)
+    tot, exp = 0, 0.0
+    for _ in range(12):
+        prim = g.moments(0, duwp.M_PRIM)
+        N = np.diff(g.get_state()["off"])
+        g.step(1)
+        d = g.diag()
+        assert (d["n_abs"] == 0).all()
+        if omega == 1.0:
+            assert np.array_equal(d["n_coll"], d["n_cand"])
+        rho, T = prim[:, 0], prim[:, 4]
+        mu = k["mu_ref"] * (T / c.T_ref) ** c.omega
+        nu = 4.0 * k["beta"] * rho * c.R * T / mu
+        exp += float((0.5 * (N - 1) * nu * c.dt).sum())
+        tot += int(d["n_coll"].sum())
+    assert abs(tot - exp) < 4.0 * np.sqrt(exp), (tot, exp)
     g.close()
