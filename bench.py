@@ -425,7 +425,7 @@ def batched_profile_error(args, cases, cfg_m, cfg_f):
 def leg_large(args, graph):
     from paper_2305_12071_amd import duwp
     from paper_2305_12071_amd import inputs as I
-    c = I.mach10_large(n_kept=args.large_particles)
+    c = I.mach10_large(ncells=args.large_cells, n_kept=args.large_particles)
     cfg = config_for([c], duwp.MIXED, args)
     log(f"large near-continuum case: {c.name}, {args.large_particles:.0e} kept particles, {cfg}")
     sl, psl, dtl = run_path([c], duwp.MIXED, args.large_steps, 3, graph, cfg)
@@ -523,6 +523,8 @@ def main():
     ap.add_argument("--single-steps", type=int, default=20,
                     help="timed steps per case, one context each (0: leave out)")
     ap.add_argument("--large-particles", type=float, default=1e9)
+    ap.add_argument("--large-cells", type=int, default=20000,
+                    help="cells of the near-continuum case (2500 with 1.25e8 particles: one GPU's share of eight)")
     ap.add_argument("--large-steps", type=int, default=5)
     ap.add_argument("--c2-steps", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=16)
