@@ -152,6 +152,8 @@ __device__ __forceinline__ uint64_t mulhi64(uint64_t r, uint64_t n) { return __u
 // Wave / block primitives
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+// index of this wave in its block, as a wave-uniform value
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 // number of set bits of m below this lane
 __device__ __forceinline__ int lane_rank_lt(uint64_t m)
@@ -213,7 +215,7 @@ __device__ __forceinline__ void lds_barrier()
 template <int N>
 __device__ __forceinline__ void block_sum(double (&v)[N], double *red)
 {
-    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int w = wave_id(), nw = blockDim.x >> 6;
 #pragma unroll
     for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
     __syncthreads();
@@ -277,7 +279,7 @@ __device__ __forceinline__ double wave_sum_spread(const double (&v)[N])
 template <int N>
 __device__ __forceinline__ double block_sum_to_thread(const double (&v)[N], double *red)
 {
-    const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
     const double e = wave_sum_spread<N>(v);
     if (nw == 1) {
         const double r = __shfl(e, (lane & 15) * 4, WAVE);
@@ -297,7 +299,7 @@ __device__ __forceinline__ double block_sum_to_thread(const double (&v)[N], doub
 // scratch must hold blockDim/64 ints.
 __device__ __forceinline__ int block_flag_prefix(bool f, int *scratch, int *total)
 {
-    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int w = wave_id(), nw = blockDim.x >> 6;
     uint64_t m = __ballot(f);
     int in_wave = __popcll(m & lanemask_lt());
     __syncthreads();
@@ -317,7 +319,7 @@ __device__ __forceinline__ int block_flag_prefix(bool f, int *scratch, int *tota
 // prefix, *total the block total.  scratch must hold blockDim/64 ints.
 __device__ __forceinline__ int block_count_prefix(int v, int *scratch, int *total)
 {
-    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = lane_id();
+    const int w = wave_id(), nw = blockDim.x >> 6, lane = lane_id();
     int incl = v;
 #pragma unroll
     for (int o = 1; o < WAVE; o <<= 1) {

@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ ca
     __shared__ int64_t sb[WAVE], se[WAVE], spb[WAVE];
     __shared__ int sk[WAVE], scnt[WAVE];
     const uint32_t step = *d_step;
-    const int lane = lane_id(), wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = lane_id(), wv = wave_id(), nw = blockDim.x >> 6;
     const int g0 = blockIdx.x * WAVE;
     if (g0 >= G) return;
     const int nc = min(WAVE, G - g0);
@@ -487,7 +487,7 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
 {
     __shared__ uint64_t hmask[COLL_WPB][1 << COLL_HBITS];
     __shared__ T fwd[COLL_WPB][6][WAVE];     // (u,v,w) of particle i, then of j, per lane
-    const int wv = threadIdx.x >> 6, lane = lane_id();
+    const int wv = wave_id(), lane = lane_id();
     const uint32_t step = *d_step;
     for (int t = lane; t < (1 << COLL_HBITS); t += WAVE) hmask[wv][t] = 0ull;
     lds_fence();
@@ -792,7 +792,7 @@ __global__ void __launch_bounds__(B) k_collide_big(const DCase *__restrict__ cas
     __shared__ int redi[NW];
     __shared__ int ovf[2];           // by chunk parity
     __shared__ int wdep[NW];         // per-wave counts of waiting candidates
-    const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
+    const int t = threadIdx.x, lane = lane_id(), wv = wave_id();
     const int nbig = *cl.nbig;
     if ((int)blockIdx.x >= nbig) return;   // no cell for this block (often none at all)
     const uint32_t step = *d_step;
@@ -1059,7 +1059,7 @@ __device__ __forceinline__ int inj_cell(int slot, int C)
 template <int NB>
 __device__ __forceinline__ int block_stable_rank(int key, int *binbase, int (*wcnt)[NB])
 {
-    const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
     int my = 0;
     uint64_t rem = __ballot(key >= 0);
     while (rem) {
@@ -1119,7 +1119,7 @@ __global__ void __launch_bounds__(1024) k_inject_rank(const DCase *__restrict__ 
         int sum = 0;
         for (int64_t i = threadIdx.x; i < nch0; i += blockDim.x) sum += inj.cchunk[c.chunk_base[0] + i];
         sum = wave_sum_i(sum);
-        if (lane == 0) red[threadIdx.x >> 6] = sum;
+        if (lane == 0) red[wave_id()] = sum;
         __syncthreads();
         for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) count += red[w2];
     }
@@ -1300,7 +1300,7 @@ __global__ void __launch_bounds__(256) k_count_bases(Cells cl, int G, int nd)
     __shared__ int tile[CN_ROWS * NBIN];
     const int d0 = blockIdx.x * nd;
     if (nd <= 4) {
-        const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
         for (int dd = w; dd < nd && d0 + dd < G; dd += nw) {
             const int d = d0 + dd;
             const int src = d + lane - KWIN;
@@ -1446,7 +1446,7 @@ __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1
     __shared__ __attribute__((aligned(16))) int hn[(NBIN * NBIN + 3) / 4 * 4];
     __shared__ int nout;
     if ((int)blockIdx.x >= G) return;
-    const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
     for (int t = threadIdx.x; t < (NBIN * NBIN + 3) / 4; t += blockDim.x)
         reinterpret_cast<int4 *>(hn)[t] = int4{0, 0, 0, 0};
     if (threadIdx.x == 0) nout = 0;
@@ -1699,7 +1699,7 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
 {
     const int lane = lane_id();
     constexpr int CPW = WAVE / 2;    // cells per wave
-    const int d0 = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * CPW;
+    const int d0 = (blockIdx.x * (blockDim.x >> 6) + wave_id()) * CPW;
     const int d = d0 + (lane >> 1), h = lane & 1;
     // the step's close: particle-steps (particles alive at its start), step
     // index, and the big-cell list emptied for the next step

@@ -15,7 +15,7 @@ constexpr int SCAN_TILE = SCAN_ITEMS * SCAN_BLOCK;
 
 __device__ __forceinline__ int64_t block_exclusive_scan64(int64_t v, int64_t *lds, int64_t *total)
 {
-    const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
     int64_t incl = v;
 #pragma unroll
     for (int o = 1; o < WAVE; o <<= 1) {
