@@ -16,6 +16,11 @@ cells must stay near one (a small bias shared by many cells shows there).
 - Sod tube at the paper's resolution, Kn = 1e-4 (absorption, resampling and the
   wave flux all active on the left): the ensemble average of 50 replicas at
   t = 0.15 (300 steps), as in Sec. 4.2, FP64 and FP32+FP64 on the GPU.
+- Mach-10 shock in the near-continuum regime (cells of 1000 upstream mean free
+  paths, nearly all particles absorbed and resampled every step, most of the
+  mass in the wave part), 100 cells and 2e4 particles, every cell's
+  collisions in the block-per-cell kernel: 200 steps, time average of the last
+  100, 16 replicas a side.
 """
 import numpy as np
 import pytest
@@ -28,8 +33,8 @@ from paper_2305_12071_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_runs(case, nrep, seed, steps, avg_from, prec):
-    g = duwp.Sim([case] * nrep, seed=seed, precision=prec, use_graph=True)
+def _gpu_runs(case, nrep, seed, steps, avg_from, prec, tune=None):
+    g = duwp.Sim([case] * nrep, seed=seed, precision=prec, use_graph=True, tune=tune)
     if avg_from is None:
         g.step(steps)
         out = np.stack([g.moments(k, duwp.M_PRIM) for k in range(nrep)])
@@ -86,3 +91,23 @@ def test_sod_ensemble_at_t015_matches_oracle_ensemble(prec):
     g1.close()
     assert wave[:20].mean() > 0.5
     E.compare(gg, oo, f"sod Kn1e-4 prec={prec}")
+
+
+@pytest.mark.parametrize("prec", [duwp.FP64, duwp.MIXED], ids=["fp64", "mixed"])
+def test_near_continuum_shock_through_the_block_per_cell_collide(prec):
+    c = I.mach10_large(ncells=100, n_kept=2e4)
+    # thresholds lowered so that every cell (about 200 particles and 250
+    # candidates) collides in the block-per-cell kernel, 256 candidates a chunk:
+    # its waiting-candidate rounds and its serial path both run
+    tune = {"big_min_particles": 64, "big_min_candidates": 64, "big_block": 256}
+    nrep, steps, avg_from = 16, 200, 100
+    E.say("near-continuum long run", prec)
+    g1 = duwp.Sim(c, seed=7, precision=prec, tune=tune)
+    g1.step(20)
+    d = g1.diag()
+    wave = g1.moments(0, duwp.M_PSI_W)[:, 0].sum() / g1.moments(0, duwp.M_PSI_T)[:, 0].sum()
+    g1.close()
+    assert wave > 0.9 and d["n_new"].sum() > 0.8 * d["n_abs"].sum() > 0
+    gg = _gpu_runs(c, nrep, 5005, steps, avg_from, prec, tune=tune)
+    oo = _oracle_ensemble("mach10", c, nrep, 6006, steps, avg_from)
+    E.compare(gg, oo, f"mach10 near-continuum prec={prec}")
