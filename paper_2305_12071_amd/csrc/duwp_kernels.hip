@@ -492,42 +492,39 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
     for (int t = lane; t < (1 << COLL_HBITS); t += WAVE) hmask[wv][t] = 0ull;
     lds_fence();
     const uint64_t lt = lanemask_lt();
-    // One chunk: lane l runs candidate q of cell g (act false: no candidate);
-    // more: another chunk of the same work follows and reads what this one stored.
-    auto chunk = [&](int g, uint32_t q, bool act, bool more) {
-        // the cell's particles, constants and pair
-        uint32_t i = 0, j = 0;
-        uint32_t w2 = 0, w3 = 0, w4 = 0;
-        double cm = 1.0, aexp = 0.0;
-        T xi = 0, ui = 0, vi = 0, wi = 0, xj = 0, uj = 0, vj = 0, wj = 0;
-        P4<T> *pr = nullptr;
-        int lc = 0, k = 0;
-        if (act) {
-            const int32_t N = cl.n_int[g];
-            const int64_t sb = cl.seg[g];
-            k = cl.cell_case[g];
-            const DCase &c = cases[k];
-            lc = g - c.cell_base;
-            if (sb + N > cap) {
-                act = false;   // capacity overflow, already reported
-            } else {
-                P4<T> *sg = cl.seg_stg[g] ? stg : src;
-                cm = cl.cr_max[g];
-                aexp = 1.0 - 2.0 * c.ups;
-                const U4 ra = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 0);
-                const U4 rb = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 1);
-                const uint64_t r0 = ((uint64_t)ra.a << 32) | ra.b;
-                const uint64_t r1 = ((uint64_t)ra.c << 32) | ra.d;
-                i = (uint32_t)mulhi64(r0, (uint64_t)N);
-                j = (uint32_t)mulhi64(r1, (uint64_t)(N - 1));
-                if (j >= i) j += 1;
-                w2 = rb.a; w3 = rb.b; w4 = rb.c;
-                pr = sg + sb;
-                const P4<T> a = pr[i], bq = pr[j];
-                xi = a.x; ui = a.u; vi = a.v; wi = a.w;
-                xj = bq.x; uj = bq.u; vj = bq.v; wj = bq.w;
-            }
-        }
+    // One chunk: lane l runs candidate q of cell g (act false: no candidate).
+    // The cell's constants (CellRef) and the candidate's pair, words and records
+    // (Cand) come first; run finds each lane's predecessors in the chunk, runs
+    // the candidates in dependency rounds and adds the per-cell results.  more:
+    // another chunk of the same work follows and reads what this one stored.
+    struct CellRef {
+        P4<T> *pr;
+        int lc, k;
+        double cm, aexp;
+    };
+    struct Cand {
+        uint32_t i, j, w2, w3, w4;
+        T xi, ui, vi, wi, xj, uj, vj, wj;
+    };
+    // pair and words of candidate q of a cell with N >= 2 particles at pr, and
+    // the two records
+    auto pair = [&](const DCase &c, int lc, uint32_t q, int32_t N, P4<T> *pr, Cand &d) {
+        const U4 ra = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 0);
+        const U4 rb = draw(c, step, (uint32_t)lc, q, TAG_PAIR, 1);
+        const uint64_t r0 = ((uint64_t)ra.a << 32) | ra.b;
+        const uint64_t r1 = ((uint64_t)ra.c << 32) | ra.d;
+        d.i = (uint32_t)mulhi64(r0, (uint64_t)N);
+        d.j = (uint32_t)mulhi64(r1, (uint64_t)(N - 1));
+        if (d.j >= d.i) d.j += 1;
+        d.w2 = rb.a; d.w3 = rb.b; d.w4 = rb.c;
+        const P4<T> x = pr[d.i], y = pr[d.j];
+        d.xi = x.x; d.ui = x.u; d.vi = x.v; d.wi = x.w;
+        d.xj = y.x; d.uj = y.u; d.vj = y.v; d.wj = y.w;
+    };
+    auto run = [&](int g, bool act, bool more, const CellRef &cr, const Cand &d) {
+        const uint32_t i = d.i, j = d.j;
+        T ui = d.ui, vi = d.vi, wi = d.wi, uj = d.uj, vj = d.vj, wj = d.wj;
+        const T xi = d.xi, xj = d.xj;
         if (!act) g = -1;
         // last earlier lane touching each of this lane's particles
         const uint32_t si = coll_slot(g, i), sj = coll_slot(g, j);
@@ -566,16 +563,16 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
                 if (pi >= 0) { ui = fwd[wv][oi][pi]; vi = fwd[wv][oi + 1][pi]; wi = fwd[wv][oi + 2][pi]; }
                 if (pj >= 0) { uj = fwd[wv][oj][pj]; vj = fwd[wv][oj + 1][pj]; wj = fwd[wv][oj + 2][pj]; }
                 const T ui0 = ui, uj0 = uj;
-                if (collide_vals<T>(ui, vi, wi, uj, vj, wj, cm, aexp, w2, w3, w4, seen)) {
+                if (collide_vals<T>(ui, vi, wi, uj, vj, wj, cr.cm, cr.aexp, d.w2, d.w3, d.w4, seen)) {
                     acc = 1;
-                    pr[i] = P4<T>{xi, ui, vi, wi};
-                    pr[j] = P4<T>{xj, uj, vj, wj};
+                    cr.pr[i] = P4<T>{xi, ui, vi, wi};
+                    cr.pr[j] = P4<T>{xj, uj, vj, wj};
                     // move the pair between destination bins of this step's histogram
-                    const DCase &c = cases[k];
+                    const DCase &c = cases[cr.k];
                     int32_t *hg = cl.hist + (int64_t)g * NBIN;
                     bool f0 = false;
-                    const int a0 = flight_bin<T>(c, lc, xi, ui0, &f0), a1 = flight_bin<T>(c, lc, xi, ui, &far);
-                    const int b0 = flight_bin<T>(c, lc, xj, uj0, &f0), b1 = flight_bin<T>(c, lc, xj, uj, &far);
+                    const int a0 = flight_bin<T>(c, cr.lc, xi, ui0, &f0), a1 = flight_bin<T>(c, cr.lc, xi, ui, &far);
+                    const int b0 = flight_bin<T>(c, cr.lc, xj, uj0, &f0), b1 = flight_bin<T>(c, cr.lc, xj, uj, &far);
                     if (a0 != a1) {
                         if (a0 >= 0) atomicSub(&hg[a0], 1);
                         if (a1 >= 0) atomicAdd(&hg[a1], 1);
@@ -602,18 +599,35 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
         }
         const int gd = __shfl_down(g, 1, WAVE);
         if (g >= 0 && (lane == WAVE - 1 || gd != g) && sacc > 0) atomicAdd(&cl.d_coll[g], sacc);
-        if (act && seen > cm)
+        if (act && seen > cr.cm)
             atomicMax((unsigned long long *)&cl.cr_seen[g], (unsigned long long)__double_as_longlong(seen));
         if (far) cl.fix[g] = 1;
         // the next chunk of this work reads what this one stored
         if (more) __threadfence_block();
     };
     if (by_cell) {
-        // a wave per cell, cells in visiting order (few cells with many candidates)
+        // a wave per cell, cells in visiting order (few cells with many
+        // candidates); the cell's constants are read once, not per chunk
         for (int gi = blockIdx.x * COLL_WPB + wv; gi < G; gi += gridDim.x * COLL_WPB) {
-            const int g = cl.order[gi];
-            const int32_t M = cl.ncand_w[g];
-            for (int32_t q0 = 0; q0 < M; q0 += WAVE) chunk(g, (uint32_t)(q0 + lane), q0 + lane < M, q0 + WAVE < M);
+            const int g = __builtin_amdgcn_readfirstlane(cl.order[gi]);
+            const int32_t M = __builtin_amdgcn_readfirstlane(cl.ncand_w[g]);
+            if (M <= 0) continue;
+            const int32_t N = __builtin_amdgcn_readfirstlane(cl.n_int[g]);
+            const int64_t sb = cl.seg[g];
+            if (sb + N > cap) continue;   // capacity overflow, already reported
+            CellRef cr;
+            cr.k = __builtin_amdgcn_readfirstlane(cl.cell_case[g]);
+            const DCase &c = cases[cr.k];
+            cr.lc = g - c.cell_base;
+            cr.pr = (cl.seg_stg[g] ? stg : src) + sb;
+            cr.cm = cl.cr_max[g];
+            cr.aexp = 1.0 - 2.0 * c.ups;
+            for (int32_t q0 = 0; q0 < M; q0 += WAVE) {
+                const bool act = q0 + lane < M;
+                Cand d{};
+                if (act) pair(c, cr.lc, (uint32_t)(q0 + lane), N, cr.pr, d);
+                run(g, act, q0 + WAVE < M, cr, d);
+            }
         }
         return;
     }
@@ -656,7 +670,26 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
                 }
             }
             const int gnext = __builtin_amdgcn_readlane(g, WAVE - 1);
-            chunk(g, (uint32_t)(Q - gstart), act, Q0 + WAVE < qend);
+            // the lane's cell and candidate (a cell beyond the capacity was
+            // reported already)
+            CellRef cr{nullptr, 0, 0, 1.0, 0.0};
+            Cand d{};
+            if (act) {
+                const int32_t N = cl.n_int[g];
+                const int64_t sb = cl.seg[g];
+                cr.k = cl.cell_case[g];
+                const DCase &c = cases[cr.k];
+                cr.lc = g - c.cell_base;
+                if (sb + N > cap) {
+                    act = false;
+                } else {
+                    cr.pr = (cl.seg_stg[g] ? stg : src) + sb;
+                    cr.cm = cl.cr_max[g];
+                    cr.aexp = 1.0 - 2.0 * c.ups;
+                    pair(c, cr.lc, (uint32_t)(Q - gstart), N, cr.pr, d);
+                }
+            }
+            run(g, act, Q0 + WAVE < qend, cr, d);
             gcur = gnext;
         }
     }
