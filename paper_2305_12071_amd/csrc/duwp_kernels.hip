@@ -708,7 +708,9 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
 // staged in LDS, BIG_DEPCAP at a time in candidate order, and run by one wave in
 // wave-level rounds, so that the collision arithmetic of a chunk is issued about
 // once per wave instead of once per round.  A particle drawn by more than
-// BIG_LIST candidates of one chunk (rare) sends that chunk through a serial path.
+// BIG_LIST candidates of one chunk sends that chunk through a serial path: with
+// 8 per list, about 4e-8 of the chunks of a cell of 1800 particles (one chunk
+// in 40 with 4 per list, a serial chunk then costing as much as the rest).
 //
 // The random particle reads dominate: the block works on the cell's records in
 // place (one cache line per access), two blocks share a compute unit, and the
@@ -716,7 +718,7 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
 // that run first do not hold up the waiting ones.  Histogram moves of accepted
 // collisions are summed in LDS and added once per cell.
 // ---------------------------------------------------------------------------
-constexpr int BIG_LIST = 4;
+constexpr int BIG_LIST = 8;
 constexpr int BIG_DEPCAP = 64;
 
 // B threads (candidates per chunk: 256, 512 or 1024), 2^HBITS hash slots (twice
