@@ -193,9 +193,9 @@ def test_big_cells_collide_in_block_kernel_and_match_oracle():
 
 
 def test_big_cells_with_repeated_particles_match_oracle():
-    """Cells of ~4500 particles with ~5 candidates per particle: a particle is often
-    drawn more than four times within one chunk of the block kernel, which then runs
-    that chunk serially.  Three FP64 steps match the oracle."""
+    """Cells of ~4500 particles with ~5 candidates per particle: particles drawn
+    several times within one chunk of the block kernel (its per-particle lists of
+    the chunk's candidates).  Three FP64 steps match the oracle."""
     c = I.box(4, 1.0, 1.0, 18000.0, 4.0, name="box_big_repeat")
     c.dsmc_full_dt = 1
     _say("big cells with repeats")
@@ -208,6 +208,53 @@ def test_big_cells_with_repeated_particles_match_oracle():
         compare_diag(d, o.diag(), f"box_big:{s}")
     assert (d["n_cand"] >= 4096).all() and (g.get_state()["off"][1:] - g.get_state()["off"][:-1] >= 4096).all()
     compare_states(g.get_state(), o.get_state(), label="box_big", psi_t=o.cells()["psi_t"])
+    g.close()
+
+
+def _chunks_past_the_lists(seed, case_id, step, lc, n, m, chunk=256, lst=8):
+    """Per chunk of the block kernel: whether a particle is drawn more than lst
+    times in it (the pair draws of the candidate stream, computed here from the
+    oracle's Philox and the pair rule of Appendix A)."""
+    key = (seed & 0xFFFFFFFF, (seed >> 32) + case_id)
+    out = []
+    for q0 in range(0, m, chunk):
+        cnt = {}
+        for q in range(q0, min(m, q0 + chunk)):
+            w = [int(v) for v in O.philox((step, lc, q, (5 << 16) | 0), key)]
+            i = (((w[0] << 32) | w[1]) * n) >> 64
+            j = (((w[2] << 32) | w[3]) * (n - 1)) >> 64
+            j += j >= i
+            cnt[i] = cnt.get(i, 0) + 1
+            cnt[j] = cnt.get(j, 0) + 1
+        out.append(max(cnt.values()) > lst)
+    return out
+
+
+def test_block_kernel_serial_chunks_match_oracle():
+    """Cells of ~120 particles and ~300 candidates sent to the block kernel (256
+    candidates a chunk, FP64): a particle drawn more than 8 times in a chunk sends
+    that chunk through the serial path.  About half of the chunks of three steps do
+    (checked on the CPU from the candidate stream), the others run through the
+    lists; every step matches the oracle."""
+    c = I.box(4, 1.0, 1.0, 250.0, 2.0, name="box_serial_chunks")
+    c.dsmc_full_dt = 1
+    tune = {"big_min_particles": 64, "big_min_candidates": 64, "big_block": 256}
+    _say("block kernel, serial chunks")
+    g = duwp.Sim(c, seed=2, precision=duwp.FP64, use_graph=True, tune=tune)
+    o = O.Oracle(c, seed=2, case_id=0)
+    flags = []
+    for s in range(3):
+        n0 = np.diff(o.get_state()["off"])
+        step = o.step_index
+        g.step(1)
+        o.step(1)
+        d = o.diag()
+        compare_diag(g.diag(), d, f"box_serial:{s}")
+        n = n0 - d["n_abs"] + d["n_new"]
+        for lc in range(c.ncells):
+            flags += _chunks_past_the_lists(2, 0, step, lc, int(n[lc]), int(d["n_cand"][lc]))
+    assert 0 < sum(flags) < len(flags), flags
+    compare_states(g.get_state(), o.get_state(), label="box_serial", psi_t=o.cells()["psi_t"])
     g.close()
 
 
