@@ -8,7 +8,9 @@ other collisions, destinations per block of the sort's count kernels).  None
 of them changes an integer result, so the tuner only times.
 
 `tune` searches one knob at a time (coordinate descent, each knob over its
-candidates with the others at their best so far), timing graph-replayed steps
+candidates with the others at their best so far; the size threshold of the
+block-per-cell collide before its shape, which matters only for the cells the
+threshold sends there), timing graph-replayed steps
 of a fresh context per candidate, and stores the winner in a JSON cache under
 the workload's shape family: GPU architecture, precision, number of cases,
 cells per case and particles per cell (both rounded to powers of two), and
@@ -113,7 +115,7 @@ def _candidates(knob: str, precision: int, ncells: int, has_big: bool):
             return []
         if precision == duwp.MIXED:
             return [(256, 2), (256, 4), (256, 6), (512, 2), (512, 3), (512, 1), (1024, 1)]
-        return [(256, 2), (256, 4), (256, 1), (512, 1), (1024, 1)]
+        return [(256, 2), (256, 3), (256, 4), (256, 1), (512, 1), (1024, 1)]
     if knob == "big_min":
         return [256, 1024, 4096, 16384] if has_big else []
     if knob == "collide_by_cell_max":
@@ -167,9 +169,11 @@ def _has_big_cells(cases, precision: int) -> bool:
 
 
 def tune(cases, precision: int, steps: int = 20, warmup: int = 5, path: str | None = DEFAULT_CACHE,
-         log=None, knobs=("block_cells", "scatter_items", "big", "big_min", "collide_by_cell_max",
-                          "count_dests")):
-    """Coordinate search over the knobs; stores and returns (block_cells, tune dict)."""
+         log=None, knobs=("block_cells", "scatter_items", "big_min", "big", "collide_by_cell_max",
+                          "count_dests"), sweeps: int = 2):
+    """Coordinate search over the knobs, `sweeps` passes (the knobs interact: the
+    size threshold, the collide kernel's shape and the wave-per-cell switch);
+    stores and returns (block_cells, tune dict)."""
     ncells = sum(c.ncells for c in cases)
     has_big = _has_big_cells(cases, precision)
     best = {"block_cells": 256, "tune": {}}
@@ -181,17 +185,20 @@ def tune(cases, precision: int, steps: int = 20, warmup: int = 5, path: str | No
     tried = {"default": round(best_ms, 5)}
     if log:
         log(f"  autotune default: {best_ms:.4f} ms/step")
-    for knob in knobs:
-        for v in _candidates(knob, precision, ncells, has_big):
-            cfg = _apply(best, knob, v)
-            if knob == "scatter_items" and cfg["block_cells"] == 64:
-                continue            # one-wave scatter blocks have a fixed depth
-            ms = time_config(cases, precision, cfg, steps, warmup)
-            tried[f"{knob}={v}"] = round(ms, 5)
-            if log:
-                log(f"  autotune {knob}={v}: {ms:.4f} ms/step")
-            if ms < best_ms:
-                best, best_ms = cfg, ms
+    for sweep in range(sweeps):
+        for knob in knobs:
+            for v in _candidates(knob, precision, ncells, has_big):
+                cfg = _apply(best, knob, v)
+                if cfg == best:
+                    continue        # the configuration in hand
+                if knob == "scatter_items" and cfg["block_cells"] == 64:
+                    continue        # one-wave scatter blocks have a fixed depth
+                ms = time_config(cases, precision, cfg, steps, warmup)
+                tried[f"{knob}={v}" + (f" (pass {sweep + 1})" if sweep else "")] = round(ms, 5)
+                if log:
+                    log(f"  autotune {knob}={v}: {ms:.4f} ms/step")
+                if ms < best_ms:
+                    best, best_ms = cfg, ms
     if path:
         f = family(cases, precision)
         cache = load_cache(path)

@@ -807,8 +807,10 @@ struct BigDep {
     int t[BIG_DEPCAP], pred[2][BIG_DEPCAP];   // predecessor * 4 + (0 or 3), or -1
 };
 
+// 256 FP64 threads: registers capped for three waves per SIMD (three blocks per
+// compute unit, which their LDS allows)
 template <typename T, int B>
-__global__ void __launch_bounds__(B) k_collide_big(const DCase *__restrict__ cases, Cells cl,
+__global__ void __launch_bounds__(B, (sizeof(T) == 8 && B == 256) ? 3 : 1) k_collide_big(const DCase *__restrict__ cases, Cells cl,
                                                    P4<T> *src, P4<T> *stg,
                                                    const uint32_t *__restrict__ d_step, int64_t cap)
 {
