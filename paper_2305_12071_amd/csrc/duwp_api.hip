@@ -145,7 +145,6 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &ctx->k_n, 16 * (size_t)ctx->ncases));
     TRY(dalloc(ctx, &ctx->k_chunk, 4 * (size_t)ctx->chunk_total));
     for (int p = 0; p < 2; ++p) TRY(dalloc(ctx, &ctx->off[p], 8 * (size_t)(G + 1)));
-    TRY(dalloc(ctx, &ctx->ibase, 8 * (size_t)(G + 1)));
     duwp::Cells &c = ctx->cl;
     TRY(dalloc(ctx, &c.psi_w, 8 * 5 * (size_t)G));
     TRY(dalloc(ctx, &c.psi_p, 8 * 5 * (size_t)G));
@@ -157,7 +156,7 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &c.n_surv, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.n_new, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.n_int, 4 * (size_t)G));
-    TRY(dalloc(ctx, &c.n_stage, 4 * (size_t)G));
+    TRY(dalloc(ctx, &c.nstage, 8));
     TRY(dalloc(ctx, &c.seg, 8 * (size_t)G));
     TRY(dalloc(ctx, &c.seg_stg, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.mpart, 8 * 5 * (size_t)G * duwp::NBIN));
@@ -255,6 +254,7 @@ duwp_status upload_initial(duwp_ctx *ctx)
     if (ctx->cl.wabs) HIP_OK(hipMemsetAsync(ctx->cl.wabs, 0, 8 * 5 * (size_t)G * duwp::NBIN, s));
     HIP_OK(hipMemsetAsync(ctx->cl.nbig, 0, 4, s));
     HIP_OK(hipMemsetAsync(ctx->cl.ntouch, 0, 4, s));
+    HIP_OK(hipMemsetAsync(ctx->cl.nstage, 0, 8, s));
     for (int p = 0; p < 2; ++p) HIP_OK(hipMemsetAsync(ctx->off[p], 0, 8 * (size_t)(G + 1), s));
     HIP_OK(hipMemsetAsync(ctx->d_step, 0, 4, s));
     HIP_OK(hipMemsetAsync(ctx->d_err, 0, 4, s));

@@ -54,7 +54,6 @@ struct duwp_ctx {
     int32_t *fix_buf[2] = {nullptr, nullptr};    // recount flags, by step parity
     int inj_blocks = 0;            // x-blocks of the candidate kernel
     int64_t *off[2] = {nullptr, nullptr};
-    int64_t *ibase = nullptr;
     duwp::Cells cl{};
     int64_t *scan_part = nullptr;
     int ntiles = 0;

@@ -63,7 +63,7 @@ struct Cells {
     int32_t *okc;       // [G] 1 unless vacuum
     double *cr_max;     // [G]
     int32_t *n_surv, *n_new, *n_int;   // [G] survivors, resampled, survivors+resampled
-    int32_t *n_stage;   // [G] particles copied to staging (0 for an untouched cell)
+    int64_t *nstage;    // [1] staging records handed out this step (cleared at the end of each step)
     int64_t *seg;       // [G] start of the cell's intermediate segment
     int32_t *seg_stg;   // [G] 1: segment in the staging buffer, 0: in place in the canonical buffer
     int32_t *d_abs, *d_new, *d_cand, *d_coll;  // [G] diagnostics; d_cand is also the collide work size

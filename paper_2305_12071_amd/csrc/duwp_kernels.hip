@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ ca
                                                      const int64_t *__restrict__ off,
                                                      const uint32_t *__restrict__ d_step, int G,
                                                      int32_t *err, int64_t *d_nout, int64_t *d_ninj,
-                                                     int abs_stream, int big_min_n, int big_min_m)
+                                                     int abs_stream, int big_min_n, int big_min_m, int64_t cap)
 {
     __shared__ double sP[WAVE];
     __shared__ int64_t sb[WAVE], se[WAVE], spb[WAVE];
@@ -162,11 +162,31 @@ __global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ ca
         base = __shfl(base, 0, WAVE);
         if (touched) cl.touch_list[base + lane_rank_lt(tm)] = g;
     }
+    // their segments in the staging array, handed out from a running count a
+    // wave at a time (where a segment lies changes nothing that is computed
+    // from it); past the capacity a cell is reported and skipped
+    int64_t sseg = 0;
+    if (tm) {
+        const int64_t nst = touched ? (int64_t)N : 0;
+        int64_t incl = nst;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const int64_t t = __shfl_up(incl, o, WAVE);
+            if (lane >= o) incl += t;
+        }
+        const int64_t tot = readlane64(incl, WAVE - 1);
+        int64_t base = 0;
+        if (lane == 0) base = (int64_t)atomicAdd((unsigned long long *)cl.nstage, (unsigned long long)tot);
+        sseg = readlane64(base, 0) + incl - nst;
+        if (touched && sseg + N > cap) atomicOr(err, ERR_CAPACITY);
+    }
     if (!in) return;
     if (!touched) {
         cl.seg[g] = b;
         cl.d_abs[g] = 0;
         cl.d_new[g] = 0;
+    } else {
+        cl.seg[g] = sseg;
     }
     cl.fix_nx[g] = 0;
 #pragma unroll
@@ -177,7 +197,6 @@ __global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ ca
     cl.n_surv[g] = ns;
     cl.n_new[g] = nnew;
     cl.n_int[g] = N;
-    cl.n_stage[g] = touched ? N : 0;
     cl.seg_stg[g] = touched ? 1 : 0;
     cl.inj_cnt[g] = 0;
     cl.d_cand[g] = M;
@@ -229,13 +248,13 @@ __device__ __forceinline__ P4<T> *segment(const Cells &cl, int g, P4<T> *src, P4
 
 // ---------------------------------------------------------------------------
 // 3. Classify + absorb + compact survivors + resample (Step 2), for the cells
-// that absorb or resample anything; every cell records where its segment is.
+// that absorb or resample anything, into the staging segments the cell-state
+// kernel handed out.
 // ---------------------------------------------------------------------------
 template <typename T, bool STRM>
 __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict__ cases, Cells cl,
                                                           const P4<T> *__restrict__ src,
                                                           const int64_t *__restrict__ off, P4<T> *__restrict__ stg,
-                                                          const int64_t *__restrict__ sbase,
                                                           const uint32_t *__restrict__ d_step, int G,
                                                           int64_t cap, int32_t *err, int64_t *d_nout)
 {
@@ -247,7 +266,6 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
     const int ntouch = *cl.ntouch;
     for (int e0 = blockIdx.x; e0 < ntouch; e0 += gridDim.x) {
         const int g = cl.touch_list[e0];
-        if (threadIdx.x == 0) cl.seg[g] = sbase[g];
         const int k = cl.cell_case[g];
         const DCase &c = cases[k];
         const CaseK ck(c);
@@ -255,7 +273,7 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
         const double P = cl.pc[g];
         const int64_t b = off[g], e = off[g + 1];
         const int64_t pbase = off[c.cell_base];
-        const int64_t ob = sbase[g];
+        const int64_t ob = cl.seg[g];
         const int32_t nsurv = cl.n_surv[g];
         double sa[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         // absorb_stream: moments of the absorbed particles landing in g-1 and g+1
@@ -1745,6 +1763,7 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
         *d_step += 1;
         *cl.nbig = 0;
         *cl.ntouch = 0;
+        *cl.nstage = 0;
     }
     if (d0 >= G) return;
     const bool in = d < G && h == 0;
@@ -2020,22 +2039,18 @@ static void step_impl(duwp_ctx *ctx)
         const int cw = std::max(1, std::min(16, (8192 + cblk - 1) / cblk));
         hipLaunchKernelGGL(k_cellstate, dim3(cblk), dim3(WAVE * cw), 0, st, ctx->d_cases, cl, ctx->off[p],
                            ctx->d_step, G, ctx->d_err, ctx->d_nout, ctx->d_ninj, ctx->abs_stream,
-                           ctx->big_min_n, ctx->big_min_m);
-    }
-    {
-        Mark m(ctx, "scan_staging");
-        enqueue_scan(ctx, ctx->cl.n_stage, ctx->ibase, ctx->d_total, ctx->cap);
+                           ctx->big_min_n, ctx->big_min_m, ctx->cap);
     }
     {
         Mark m(ctx, "absorb_resample");
         // the listed cells, by a grid of at most 16 blocks per compute unit
         if (ctx->abs_stream)
             hipLaunchKernelGGL((k_absorb_resample<T, true>), dim3(std::min(G, 16 * ctx->big_blocks)), dim3(bc), 0,
-                               st, ctx->d_cases, cl, src, ctx->off[p], stg, ctx->ibase, ctx->d_step, G, ctx->cap,
+                               st, ctx->d_cases, cl, src, ctx->off[p], stg, ctx->d_step, G, ctx->cap,
                                ctx->d_err, ctx->d_nout);
         else
             hipLaunchKernelGGL((k_absorb_resample<T, false>), dim3(std::min(G, 16 * ctx->big_blocks)), dim3(bc), 0,
-                               st, ctx->d_cases, cl, src, ctx->off[p], stg, ctx->ibase, ctx->d_step, G, ctx->cap,
+                               st, ctx->d_cases, cl, src, ctx->off[p], stg, ctx->d_step, G, ctx->cap,
                                ctx->d_err, ctx->d_nout);
     }
     // Injection and the big-cell collide do not depend on the small-cell collide:
