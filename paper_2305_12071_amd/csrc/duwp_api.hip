@@ -144,6 +144,20 @@ duwp_status alloc_all(duwp_ctx *ctx)
     TRY(dalloc(ctx, &ctx->k_dest, 4 * (size_t)ctx->cand_total));
     TRY(dalloc(ctx, &ctx->k_n, 16 * (size_t)ctx->ncases));
     TRY(dalloc(ctx, &ctx->k_chunk, 4 * (size_t)ctx->chunk_total));
+    // the entrant buffers' addresses in device memory: the scatter reads them
+    // there, which spares it fourteen argument registers
+    TRY(dalloc(ctx, &ctx->d_inj, sizeof(duwp::Inj<double>)));
+    if (ctx->precision == DUWP_MIXED) {
+        const duwp::Inj<float> h{(float *)ctx->J[0], (float *)ctx->J[1], (float *)ctx->J[2], (float *)ctx->J[3],
+                                 ctx->j_dest, ctx->j_rank, ctx->j_count, (float *)ctx->K[0], (float *)ctx->K[1],
+                                 (float *)ctx->K[2], (float *)ctx->K[3], ctx->k_dest, ctx->k_n, ctx->k_chunk};
+        HIP_OK(hipMemcpy(ctx->d_inj, &h, sizeof(h), hipMemcpyHostToDevice));
+    } else {
+        const duwp::Inj<double> h{(double *)ctx->J[0], (double *)ctx->J[1], (double *)ctx->J[2], (double *)ctx->J[3],
+                                  ctx->j_dest, ctx->j_rank, ctx->j_count, (double *)ctx->K[0], (double *)ctx->K[1],
+                                  (double *)ctx->K[2], (double *)ctx->K[3], ctx->k_dest, ctx->k_n, ctx->k_chunk};
+        HIP_OK(hipMemcpy(ctx->d_inj, &h, sizeof(h), hipMemcpyHostToDevice));
+    }
     for (int p = 0; p < 2; ++p) TRY(dalloc(ctx, &ctx->off[p], 8 * (size_t)(G + 1)));
     duwp::Cells &c = ctx->cl;
     TRY(dalloc(ctx, &c.psi_w, 8 * 5 * (size_t)G));

@@ -49,6 +49,7 @@ struct duwp_ctx {
     int64_t *k_n = nullptr;        // [ncases*2] candidates per side
     int64_t cand_total = 0;
     int32_t *k_chunk = nullptr;    // entrants per candidate chunk
+    void *d_inj = nullptr;         // the entrant buffers' addresses (Inj<T>) for the scatter's entrant blocks
     int64_t chunk_total = 0;
     int32_t *hist_buf[2] = {nullptr, nullptr};   // destination histograms, by step parity
     int32_t *fix_buf[2] = {nullptr, nullptr};    // recount flags, by step parity

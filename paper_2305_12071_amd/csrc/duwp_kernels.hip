@@ -23,8 +23,8 @@
 //   hist_fix         recount of the destination histograms of flagged cells
 //   count_bases/scan windowed stable counting-sort counts, group bases, offsets
 //   scatter          free flight again, stable scatter into the next canonical
-//                    array, particle moment sums per destination
-//   scatter_inj      entrants after the cell-sourced particles of their cell
+//                    array, particle moment sums per destination; the
+//                    entrants after the cell-sourced particles of their cell
 //   wave             NS wave flux and update of Psi_w
 //   gather_moments   Psi_p of the new state, running average of Psi_t
 #include <hip/hip_runtime.h>
@@ -1441,12 +1441,14 @@ __device__ __forceinline__ void scatter_entrants(const DCase &c, const Cells &cl
     }
 }
 
-// 11. the entrants of case blockIdx.y, in gridDim.x parts
+// 11. the entrants of case blockIdx.y, in gridDim.x parts (beside the one-wave
+// scatter; the scatter of several-wave blocks places them itself)
 template <typename T>
-__global__ void __launch_bounds__(256) k_scatter_inj(const DCase *__restrict__ cases, Cells cl, Inj<T> inj,
-                                                     P4<T> *dst, const int64_t *__restrict__ off_new, int64_t cap)
+__global__ void __launch_bounds__(256) k_scatter_inj(const DCase *__restrict__ cases, Cells cl,
+                                                     const Inj<T> *__restrict__ injp, P4<T> *dst,
+                                                     const int64_t *__restrict__ off_new, int64_t cap)
 {
-    scatter_entrants<T>(cases[blockIdx.y], cl, inj, dst, off_new, cap, blockIdx.y, blockIdx.x, gridDim.x);
+    scatter_entrants<T>(cases[blockIdx.y], cl, *injp, dst, off_new, cap, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1466,14 +1468,16 @@ __device__ __forceinline__ void add_phi(double (&a)[5], double u, double v, doub
 // for (FP32 particles): one-wave blocks (small cells) and blocks of several waves.
 constexpr int SCAT_IT1 = 2, SCAT_W1 = 7;
 constexpr int SCAT_WN = 1;
+// blocks per case that place its entrants, after the cells' blocks
+constexpr int SCAT_INJ_PARTS = 8;
 
 template <typename T, int MAXW, int IT>
 __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1 : SCAT_WN)) k_scatter(const DCase *__restrict__ cases, Cells cl, P4<T> *src,
                                                  P4<T> *stg, P4<T> *dst, const int64_t *__restrict__ off_new,
                                                  int G, int64_t cap, int32_t *err, int64_t *d_nout,
-                                                 int by_order)
+                                                 int by_order, const Inj<T> *__restrict__ injp, int inj_parts)
 {
-    // One block per cell (grid = G), in visiting order cl.order when by_order
+    // One block per cell (the first G blocks), in visiting order cl.order when by_order
     // is set (largest cells first: worth it when the grid runs in few rounds
     // of resident blocks), else in index order, which spares the first load
     // of the chain before a block's particle loads.  Besides placing
@@ -1492,6 +1496,13 @@ __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1
     // keeps the bin bases in registers (lane b: bin b) and needs no barrier
     // inside the chunk loop; blocks of several waves combine their counts in
     // LDS.  IT: items per thread and chunk.
+    //
+    // Blocks of several waves: the inj_parts blocks per case after the first G
+    // place the case's entrants after the cell-sourced particles of their
+    // cells: their own places of the next array, and atomic adds to the next
+    // histogram like the cells' blocks, so the two go in any order (and no
+    // launch of their own).  One-wave blocks leave the entrants to
+    // k_scatter_inj (their code would cost the one-wave instance registers).
     constexpr bool ONE = MAXW == 1;
     __shared__ int binbase[ONE ? 1 : 2][NBIN];     // by chunk parity
     __shared__ int bin0[NBIN];
@@ -1500,7 +1511,13 @@ __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1
     __shared__ double red[NMB * 5 * MAXW];
     __shared__ __attribute__((aligned(16))) int hn[(NBIN * NBIN + 3) / 4 * 4];
     __shared__ int nout;
-    if ((int)blockIdx.x >= G) return;
+    if ((int)blockIdx.x >= G) {
+        if constexpr (!ONE) {
+            const int e = (int)blockIdx.x - G, ke = e / inj_parts;
+            scatter_entrants<T>(cases[ke], cl, *injp, dst, off_new, cap, ke, e - ke * inj_parts, inj_parts);
+        }
+        return;
+    }
     const int lane = lane_id(), w = wave_id(), nw = blockDim.x >> 6;
     for (int t = threadIdx.x; t < (NBIN * NBIN + 3) / 4; t += blockDim.x)
         reinterpret_cast<int4 *>(hn)[t] = int4{0, 0, 0, 0};
@@ -2120,26 +2137,26 @@ static void step_impl(duwp_ctx *ctx)
         Mark m(ctx, "scan_offsets");
         enqueue_scan(ctx, ctx->cl.cnt_new, ctx->off[p ^ 1], ctx->d_total + 1, ctx->cap);
     }
-    // The entrants' scatter writes its own places of the next array (after the
-    // cell-sourced particles of each cell) and adds to the next histogram
-    // atomically, like the scatter, so the two can go in either order.  (On a
-    // second stream beside the scatter it made the step slower.)
-    {
+    // one-wave scatter blocks: the entrants in a kernel of their own before it
+    if (bc == WAVE) {
         Mark m(ctx, "scatter_inj");
-        hipLaunchKernelGGL(k_scatter_inj<T>, dim3(8, ctx->ncases), dim3(256), 0, st, ctx->d_cases, cl, inj,
-                           dst, ctx->off[p ^ 1], ctx->cap);
+        hipLaunchKernelGGL(k_scatter_inj<T>, dim3(SCAT_INJ_PARTS, ctx->ncases), dim3(256), 0, st, ctx->d_cases,
+                           cl, (const Inj<T> *)ctx->d_inj, dst, ctx->off[p ^ 1], ctx->cap);
     }
     {
         Mark m(ctx, "scatter");
         if (bc == WAVE)
             hipLaunchKernelGGL((k_scatter<T, 1, SCAT_IT1>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
-                               dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout, ctx->scat_by_order);
+                               dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout, ctx->scat_by_order,
+                               (const Inj<T> *)ctx->d_inj, SCAT_INJ_PARTS);
         else if (ctx->scat_items == 2)
-            hipLaunchKernelGGL((k_scatter<T, 8, 2>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
-                               dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout, ctx->scat_by_order);
+            hipLaunchKernelGGL((k_scatter<T, 8, 2>), dim3(G + SCAT_INJ_PARTS * ctx->ncases), dim3(bc), 0, st,
+                               ctx->d_cases, cl, src, stg, dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err,
+                               ctx->d_nout, ctx->scat_by_order, (const Inj<T> *)ctx->d_inj, SCAT_INJ_PARTS);
         else
-            hipLaunchKernelGGL((k_scatter<T, 8, 4>), dim3(G), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
-                               dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err, ctx->d_nout, ctx->scat_by_order);
+            hipLaunchKernelGGL((k_scatter<T, 8, 4>), dim3(G + SCAT_INJ_PARTS * ctx->ncases), dim3(bc), 0, st,
+                               ctx->d_cases, cl, src, stg, dst, ctx->off[p ^ 1], G, ctx->cap, ctx->d_err,
+                               ctx->d_nout, ctx->scat_by_order, (const Inj<T> *)ctx->d_inj, SCAT_INJ_PARTS);
     }
     {
         Mark m(ctx, "gather_moments");
