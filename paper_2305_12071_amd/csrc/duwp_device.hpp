@@ -50,8 +50,33 @@ struct CaseK {
     {
     }
 };
+// The fields the free flight of one precision reads on its fast path, held in
+// registers per lane by a kernel whose lanes may work on different cases.
+template <typename T>
+struct FlightK;
+template <>
+struct FlightK<float> {
+    const DCase *pc;
+    float dtdx_f;
+    int ncells;
+    __device__ FlightK() : pc(nullptr), dtdx_f(0.0f), ncells(0) {}
+    __device__ explicit FlightK(const DCase &c) : pc(&c), dtdx_f(c.dtdx_f), ncells(c.ncells) {}
+};
+template <>
+struct FlightK<double> {
+    const DCase *pc;
+    double x_lo, x_hi, dx, dt;
+    int ncells;
+    __device__ FlightK() : pc(nullptr), x_lo(0.0), x_hi(0.0), dx(1.0), dt(0.0), ncells(0) {}
+    __device__ explicit FlightK(const DCase &c)
+        : pc(&c), x_lo(c.x_lo), x_hi(c.x_hi), dx(c.dx), dt(c.dt), ncells(c.ncells)
+    {
+    }
+};
 __device__ __forceinline__ const DCase &case_of(const DCase &c) { return c; }
 __device__ __forceinline__ const DCase &case_of(const CaseK &k) { return *k.pc; }
+template <typename T>
+__device__ __forceinline__ const DCase &case_of(const FlightK<T> &k) { return *k.pc; }
 
 // Per-step, per-cell work arrays shared by the stage kernels.
 struct Cells {

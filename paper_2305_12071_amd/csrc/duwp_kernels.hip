@@ -519,6 +519,10 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
         P4<T> *pr;
         int lc, k;
         double cm, aexp;
+        // FP32: the case's flight constants in registers for the bin moves
+        // inside the rounds (FP64 reads them from the case: its registers are
+        // worth more than the loads)
+        FlightK<T> fk;
     };
     struct Cand {
         uint32_t i, j, w2, w3, w4;
@@ -586,11 +590,17 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
                     cr.pr[i] = P4<T>{xi, ui, vi, wi};
                     cr.pr[j] = P4<T>{xj, uj, vj, wj};
                     // move the pair between destination bins of this step's histogram
-                    const DCase &c = cases[cr.k];
                     int32_t *hg = cl.hist + (int64_t)g * NBIN;
                     bool f0 = false;
-                    const int a0 = flight_bin<T>(c, cr.lc, xi, ui0, &f0), a1 = flight_bin<T>(c, cr.lc, xi, ui, &far);
-                    const int b0 = flight_bin<T>(c, cr.lc, xj, uj0, &f0), b1 = flight_bin<T>(c, cr.lc, xj, uj, &far);
+                    int a0, a1, b0, b1;
+                    auto bins = [&](const auto &kc) {
+                        a0 = flight_bin<T>(kc, cr.lc, xi, ui0, &f0);
+                        a1 = flight_bin<T>(kc, cr.lc, xi, ui, &far);
+                        b0 = flight_bin<T>(kc, cr.lc, xj, uj0, &f0);
+                        b1 = flight_bin<T>(kc, cr.lc, xj, uj, &far);
+                    };
+                    if constexpr (std::is_same<T, float>::value) bins(cr.fk);
+                    else bins(cases[cr.k]);
                     if (a0 != a1) {
                         if (a0 >= 0) atomicSub(&hg[a0], 1);
                         if (a1 >= 0) atomicAdd(&hg[a1], 1);
@@ -640,6 +650,7 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
             cr.pr = (cl.seg_stg[g] ? stg : src) + sb;
             cr.cm = cl.cr_max[g];
             cr.aexp = 1.0 - 2.0 * c.ups;
+            if constexpr (std::is_same<T, float>::value) cr.fk = FlightK<T>(c);
             for (int32_t q0 = 0; q0 < M; q0 += WAVE) {
                 const bool act = q0 + lane < M;
                 Cand d{};
@@ -690,7 +701,7 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
             const int gnext = __builtin_amdgcn_readlane(g, WAVE - 1);
             // the lane's cell and candidate (a cell beyond the capacity was
             // reported already)
-            CellRef cr{nullptr, 0, 0, 1.0, 0.0};
+            CellRef cr{nullptr, 0, 0, 1.0, 0.0, FlightK<T>()};
             Cand d{};
             if (act) {
                 const int32_t N = cl.n_int[g];
@@ -704,6 +715,7 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
                     cr.pr = (cl.seg_stg[g] ? stg : src) + sb;
                     cr.cm = cl.cr_max[g];
                     cr.aexp = 1.0 - 2.0 * c.ups;
+                    if constexpr (std::is_same<T, float>::value) cr.fk = FlightK<T>(c);
                     pair(c, cr.lc, (uint32_t)(Q - gstart), N, cr.pr, d);
                 }
             }
