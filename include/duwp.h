@@ -105,7 +105,8 @@ typedef struct {
                                      collisions, beyond it work items cut from the candidate list (0: 8192) */
     int32_t count_dests;          /* destination cells per block of the sort's count-and-base kernel
                                      on large grids, a multiple of 4 in 4..256 (0: 256) */
-    int32_t reserved;             /* 0 */
+    int32_t collide_blocks_per_cu; /* 256-thread blocks per compute unit of the wave collide when it
+                                     takes work items from the candidate list, 1..256 (0: 16) */
 } duwp_tune;
 
 typedef struct {

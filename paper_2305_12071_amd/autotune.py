@@ -4,7 +4,8 @@ The knobs are the per-cell kernels' block size (`block_cells`) and the tile
 shapes and thresholds of `duwp_tune` (scatter items per thread, the
 block-per-cell collide's block and residency, the size from which a cell
 collides in that kernel, the cell count up to which a wave per cell runs the
-other collisions, destinations per block of the sort's count kernels).  None
+other collisions and the grid of work items beyond it, destinations per block
+of the sort's count kernels).  None
 of them changes an integer result, so the tuner only times.
 
 `tune` searches one knob at a time (coordinate descent, each knob over its
@@ -123,6 +124,10 @@ def _candidates(knob: str, precision: int, ncells: int, has_big: bool):
         return [ncells, max(ncells - 1, 1)] if 512 <= ncells <= (1 << 16) else []
     if knob == "count_dests":
         return [64, 256] if ncells >= 8192 else []
+    if knob == "collide_blocks_per_cu":
+        # the wave collide's grid for work items (the form that more than
+        # collide_by_cell_max cells take)
+        return [32, 64, 128] if ncells >= 512 else []
     raise KeyError(knob)
 
 
@@ -170,7 +175,7 @@ def _has_big_cells(cases, precision: int) -> bool:
 
 def tune(cases, precision: int, steps: int = 20, warmup: int = 5, path: str | None = DEFAULT_CACHE,
          log=None, knobs=("block_cells", "scatter_items", "big_min", "big", "collide_by_cell_max",
-                          "count_dests"), sweeps: int = 2):
+                          "collide_blocks_per_cu", "count_dests"), sweeps: int = 2):
     """Coordinate search over the knobs, `sweeps` passes (the knobs interact: the
     size threshold, the collide kernel's shape and the wave-per-cell switch);
     stores and returns (block_cells, tune dict)."""

@@ -23,7 +23,7 @@ constexpr double kPi = 3.14159265358979323846;
 
 bool tune_valid(const duwp_tune &t, int precision)
 {
-    if (t.reserved != 0) return false;
+    if (t.collide_blocks_per_cu < 0 || t.collide_blocks_per_cu > 256) return false;
     if (t.scatter_items != 0 && t.scatter_items != 2 && t.scatter_items != 4) return false;
     if (t.big_block != 0 && t.big_block != 256 && t.big_block != 512 && t.big_block != 1024) return false;
     if (t.big_blocks_per_cu < 0 || t.big_blocks_per_cu > 8) return false;
@@ -488,7 +488,8 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
             ncu = 256;
         // the allocation-free moments' staging array on this device
         if (duwp::noalloc_setup(dev, &ctx->scratch) != hipSuccess) { duwp_destroy(ctx); return DUWP_EDEVICE; }
-        ctx->coll_blocks = 16 * ncu;   // work items: many waves in flight hide each chunk's load chain
+        // work items: many waves in flight hide each chunk's load chain
+        ctx->coll_blocks = (opts->tune.collide_blocks_per_cu ? opts->tune.collide_blocks_per_cu : 16) * ncu;
         ctx->big_blocks = ncu;
         // the scatter visits cells largest first only when its grid runs in
         // few rounds of resident blocks (the tail then matters); with many

@@ -44,11 +44,11 @@ class _Case(C.Structure):
 
 
 TUNE_FIELDS = ("scatter_items", "big_block", "big_blocks_per_cu", "big_min_particles", "big_min_candidates",
-               "collide_by_cell_max", "count_dests")
+               "collide_by_cell_max", "count_dests", "collide_blocks_per_cu")
 
 
 class _Tune(C.Structure):
-    _fields_ = [(f, C.c_int32) for f in TUNE_FIELDS] + [("reserved", C.c_int32)]
+    _fields_ = [(f, C.c_int32) for f in TUNE_FIELDS]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)

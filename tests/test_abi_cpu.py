@@ -110,6 +110,7 @@ def test_init_rejects_bad_descriptors_before_any_device_call():
         assert _init_status([good], block_cells=bc) == EINVAL, bc
     for t in (dict(scatter_items=3), dict(big_block=128), dict(big_block=2048), dict(big_blocks_per_cu=9),
               dict(big_min_particles=10), dict(big_min_candidates=-1), dict(collide_by_cell_max=-5),
-              dict(count_dests=6), dict(count_dests=512), dict(reserved=1)):
+              dict(count_dests=6), dict(count_dests=512), dict(collide_blocks_per_cu=-1),
+              dict(collide_blocks_per_cu=257)):
         assert _init_status([good], tune=t) == EINVAL, t
     assert _init_status([good], alloc_only=True) == EINVAL
