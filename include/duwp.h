@@ -100,7 +100,8 @@ typedef struct {
                                      run one after another */
     int32_t big_min_particles;    /* a cell collides in that kernel when it holds at least this many
                                      particles ... (0: 4096; at least 64) */
-    int32_t big_min_candidates;   /* ... and draws at least this many candidates (0: 4096; at least 64) */
+    int32_t big_min_candidates;   /* ... and draws at least this many candidates (0: 4096; at least 64;
+                                     2147483647: no cell does, and that kernel is not launched) */
     int32_t collide_by_cell_max;  /* up to this many cells in all a wave per cell runs the other cells'
                                      collisions, beyond it work items cut from the candidate list (0: 8192) */
     int32_t count_dests;          /* destination cells per block of the sort's count-and-base kernel

@@ -118,7 +118,8 @@ def _candidates(knob: str, precision: int, ncells: int, has_big: bool):
             return [(256, 2), (256, 4), (256, 6), (512, 2), (512, 3), (512, 1), (1024, 1)]
         return [(256, 2), (256, 3), (256, 4), (256, 1), (512, 1), (1024, 1)]
     if knob == "big_min":
-        return [256, 1024, 4096, 16384] if has_big else []
+        # 2**31 - 1: no block-per-cell collide at all (not even its launch)
+        return [256, 1024, 4096, 16384, 2147483647] if has_big else [2147483647]
     if knob == "collide_by_cell_max":
         # a wave per cell, or work items from the candidate list, where both apply
         return [ncells, max(ncells - 1, 1)] if 512 <= ncells <= (1 << 16) else []

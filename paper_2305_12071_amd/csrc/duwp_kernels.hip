@@ -2100,9 +2100,10 @@ static void step_impl(duwp_ctx *ctx)
         hipLaunchKernelGGL(k_inject_rank<T>, dim3(ctx->ncases, 2), dim3(1024), 0, s2, ctx->d_cases, cl, inj,
                            ctx->d_ninj, ctx->d_err);
     }
-    {
+    if (ctx->big_min_m < INT32_MAX) {
         // cells with many particles and candidates (their own list): disjoint
-        // from the cells of k_collide, so the two run side by side
+        // from the cells of k_collide, so the two run side by side (a threshold
+        // no cell reaches leaves the kernel out)
         Mark m(ctx, "collide_big");
         const dim3 gb(ctx->big_blocks * ctx->big_per_cu);
         if (ctx->big_block == 256)

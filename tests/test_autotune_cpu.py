@@ -50,5 +50,7 @@ def test_candidates_apply_to_the_right_fields():
     assert A._candidates("big", duwp.FP64, 4000, False) == []
     assert all(1 <= pc <= 8 for _, pc in A._candidates("big", duwp.MIXED, 4000, True))
     assert A._candidates("count_dests", duwp.MIXED, 4000, False) == []
+    assert A._candidates("big_min", duwp.MIXED, 4000, False) == [2147483647]
+    assert A._candidates("big_min", duwp.MIXED, 4000, True)[-1] == 2147483647
     assert A._candidates("collide_blocks_per_cu", duwp.MIXED, 257183, False) == [32, 64, 128]
     assert A._candidates("collide_blocks_per_cu", duwp.MIXED, 100, False) == []

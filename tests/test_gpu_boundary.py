@@ -183,6 +183,7 @@ TUNINGS = [
     dict(collide_by_cell_max=1, count_dests=4),
     dict(collide_by_cell_max=1, count_dests=64, scatter_items=2),
     dict(collide_by_cell_max=1, collide_blocks_per_cu=128),
+    dict(big_min_particles=2147483647, big_min_candidates=2147483647),
     dict(big_min_particles=64, big_min_candidates=64, big_block=256, big_blocks_per_cu=6),
 ]
 
