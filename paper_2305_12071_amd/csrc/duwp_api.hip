@@ -199,10 +199,7 @@ duwp_status alloc_all(duwp_ctx *ctx)
     ctx->items_cap = std::max<int64_t>(1 << 20, 2 * (int64_t)G);
     TRY(dalloc(ctx, &ctx->item_cell, 4 * (size_t)ctx->items_cap));
     TRY(dalloc(ctx, &ctx->d_items, 16));
-    for (int p = 0; p < 2; ++p) {
-        TRY(dalloc(ctx, &ctx->hist_buf[p], 4 * (size_t)G * duwp::NBIN));
-        TRY(dalloc(ctx, &ctx->fix_buf[p], 4 * (size_t)G));
-    }
+    for (int p = 0; p < 2; ++p) TRY(dalloc(ctx, &ctx->hist_buf[p], 4 * (size_t)G * duwp::NBIN));
     c.hist = ctx->hist_buf[0];
     TRY(dalloc(ctx, &c.cnt_new, 4 * (size_t)G));
     TRY(dalloc(ctx, &c.inj_cnt, 4 * (size_t)G));
@@ -277,10 +274,7 @@ duwp_status upload_initial(duwp_ctx *ctx)
     HIP_OK(hipMemsetAsync(ctx->d_ninj, 0, 16 * (size_t)ctx->ncases, s));
     HIP_OK(hipMemsetAsync(ctx->j_count, 0, 4 * (size_t)ctx->ncases, s));
     HIP_OK(hipMemsetAsync(ctx->k_n, 0, 16 * (size_t)ctx->ncases, s));
-    for (int p = 0; p < 2; ++p) {
-        HIP_OK(hipMemsetAsync(ctx->hist_buf[p], 0, 4 * (size_t)G * duwp::NBIN, s));
-        HIP_OK(hipMemsetAsync(ctx->fix_buf[p], 0, 4 * (size_t)G, s));
-    }
+    for (int p = 0; p < 2; ++p) HIP_OK(hipMemsetAsync(ctx->hist_buf[p], 0, 4 * (size_t)G * duwp::NBIN, s));
     const duwp::Cells &c = ctx->cl;
     for (int32_t *p : {c.d_abs, c.d_new, c.d_cand, c.d_coll}) HIP_OK(hipMemsetAsync(p, 0, 4 * (size_t)G, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -767,7 +761,6 @@ duwp_status duwp_set_state(duwp_ctx *ctx, int32_t case_id, const duwp_state *st)
         HIP_OK(hipMemcpyAsync(ctx->off[p ^ 1], ctx->off[p], 8 * (size_t)(G + 1), hipMemcpyDeviceToDevice, s));
         HIP_OK(hipMemcpyAsync(ctx->hist_buf[p ^ 1], ctx->hist_buf[p], 4 * (size_t)G * duwp::NBIN,
                               hipMemcpyDeviceToDevice, s));
-        HIP_OK(hipMemcpyAsync(ctx->fix_buf[p ^ 1], ctx->fix_buf[p], 4 * (size_t)G, hipMemcpyDeviceToDevice, s));
     }
     ctx->step = st->step;
     if (st->avg_sum) ctx->avg_count = st->avg_count;

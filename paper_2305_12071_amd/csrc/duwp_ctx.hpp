@@ -52,7 +52,6 @@ struct duwp_ctx {
     void *d_inj = nullptr;         // the entrant buffers' addresses (Inj<T>) for the scatter's entrant blocks
     int64_t chunk_total = 0;
     int32_t *hist_buf[2] = {nullptr, nullptr};   // destination histograms, by step parity
-    int32_t *fix_buf[2] = {nullptr, nullptr};    // recount flags, by step parity
     int inj_blocks = 0;            // x-blocks of the candidate kernel
     int64_t *off[2] = {nullptr, nullptr};
     duwp::Cells cl{};

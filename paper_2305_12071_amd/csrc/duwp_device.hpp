@@ -101,8 +101,6 @@ struct Cells {
     uint64_t *cr_seen;  // [G] largest relative speed seen this step (bits of a non-negative double)
     int32_t *hist;      // [G*NBIN] destination histogram of this step, then scatter bases
     int32_t *hist_nx;   // [G*NBIN] histogram predicted for the next step
-    int32_t *fix;       // [G] 1: this step's histogram of the cell must be recounted
-    int32_t *fix_nx;    // [G] same, for the next step
     int32_t *cnt_new;   // [G]
     int32_t *inj_cnt;   // [G] injected entrants per destination cell
     int32_t *inj_ofs;   // [G] cell-sourced particles of each destination cell: where its entrants

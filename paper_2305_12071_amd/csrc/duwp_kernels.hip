@@ -12,21 +12,20 @@
 //
 // Per step (Sec. 3.4, Steps 2-3, Eq. r1):
 //   cellstate        Psi_t = Psi_w + Psi_p, (rho,U,T), tau = mu/p, P (Eq. p),
-//                    absorbed and resampled counts
-//   scan             staging offsets of the cells that change
+//                    absorbed and resampled counts, staging segments of the
+//                    cells that change
 //   absorb_resample  classify, absorb into Psi_w, compact survivors, sample
 //                    new particles (Eq. maxsample), subtract their moments
 //   collide          NTC/VHS (Appendix A), candidates in order: a wave per
 //                    cell or per work item with conflict-free rounds, or a
 //                    block per big cell
 //   inject_gen/rank  reservoir entrants
-//   hist_fix         recount of the destination histograms of flagged cells
 //   count_bases/scan windowed stable counting-sort counts, group bases, offsets
 //   scatter          free flight again, stable scatter into the next canonical
 //                    array, particle moment sums per destination; the
 //                    entrants after the cell-sourced particles of their cell
-//   wave             NS wave flux and update of Psi_w
-//   gather_moments   Psi_p of the new state, running average of Psi_t
+//   gather_moments   Psi_p of the new state, NS wave flux and update of
+//                    Psi_w, running average of Psi_t
 #include <hip/hip_runtime.h>
 #include <climits>
 #include <math.h>
@@ -188,7 +187,6 @@ __global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ ca
     } else {
         cl.seg[g] = sseg;
     }
-    cl.fix_nx[g] = 0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) cl.wt[(int64_t)g * 5 + i] = W[i];
     cl.pc[g] = P;
@@ -226,16 +224,18 @@ static void enqueue_scan(duwp_ctx *ctx, const int32_t *in, int64_t *out, int64_t
 }
 
 // Destination bin (d + KWIN) of a particle of local cell lc after free flight;
-// -1 when it leaves through a reservoir (or moves farther than the window,
-// then *far is set).
+// -1 when it leaves through a reservoir or moves farther than the window.  The
+// histograms count a particle in this bin and every change of its velocity
+// moves it between bins, so one in no bin is in none when the scatter places
+// the particles: if it still moves that far, the scatter reports the range
+// error (a recount would give the same histogram).
 template <typename T, typename K>
-__device__ __forceinline__ int flight_bin(const K &c, int lc, T x, T u, bool *far)
+__device__ __forceinline__ int flight_bin(const K &c, int lc, T x, T u)
 {
     const int dest = Flight<T>::go(c, lc, x, u);
     if (dest < 0) return -1;
     const int d = dest - lc;
-    if (d < -KWIN || d > KWIN) { *far = true; return -1; }
-    return d + KWIN;
+    return (d < -KWIN || d > KWIN) ? -1 : d + KWIN;
 }
 
 // Cell segment of the intermediate array: staging buffer or in place.
@@ -288,7 +288,6 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
         // the cell's destination histogram loses the absorbed and gains the resampled particles
         for (int t = threadIdx.x; t < NBIN; t += blockDim.x) dh[t] = 0;
         if (threadIdx.x == 0) farland = 0ull;
-        bool far = false;
         __syncthreads();
         if (P > 0.0) {
             // one Philox block classifies the four particles of an aligned quad of
@@ -336,8 +335,7 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
                             } else {
                                 atomicOr(err, ERR_RANGE);
                             }
-                            bool f2 = false;
-                            const int hb = flight_bin<T>(ck, lc, xs[m], us[m], &f2);
+                            const int hb = flight_bin<T>(ck, lc, xs[m], us[m]);
                             if (hb >= 0) atomicSub(&dh[hb], 1);
                         } else {
                             keep |= 1 << m;
@@ -421,7 +419,7 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
                     if (px >= 1.0f) px = 0.99999994f;
                 }
                 T pu = xi[0], pv = xi[1], pw = xi[2];
-                const int hb = flight_bin<T>(ck, lc, px, pu, &far);
+                const int hb = flight_bin<T>(ck, lc, px, pu);
                 if (hb >= 0) atomicAdd(&dh[hb], 1);
                 int64_t d = ob + nsurv + q;
                 if (d < cap) stg[d] = P4<T>{px, pu, pv, pw};
@@ -433,11 +431,10 @@ __global__ void __launch_bounds__(512) k_absorb_resample(const DCase *__restrict
             }
             block_sum<5>(ss, red);
         }
-        far = __syncthreads_or(far);
+        __syncthreads();
         for (int t = threadIdx.x; t < NBIN; t += blockDim.x)
             if (dh[t]) cl.hist[(int64_t)g * NBIN + t] += dh[t];
         if (threadIdx.x == 0) {
-            if (far) cl.fix[g] = 1;
             const int32_t nabs = (int32_t)(e - b) - nsurv;
             if (nabs > 0)
 #pragma unroll
@@ -577,7 +574,6 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
         const uint64_t dep = (pi >= 0 ? 1ull << pi : 0ull) | (pj >= 0 ? 1ull << pj : 0ull);
         double seen = 0.0;
         int acc = 0;
-        bool far = false;
         uint64_t done = ~__ballot(act);
         while (done != ~0ull) {
             const bool ready = !((done >> lane) & 1ull) && (dep & ~done) == 0ull;
@@ -591,13 +587,12 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
                     cr.pr[j] = P4<T>{xj, uj, vj, wj};
                     // move the pair between destination bins of this step's histogram
                     int32_t *hg = cl.hist + (int64_t)g * NBIN;
-                    bool f0 = false;
                     int a0, a1, b0, b1;
                     auto bins = [&](const auto &kc) {
-                        a0 = flight_bin<T>(kc, cr.lc, xi, ui0, &f0);
-                        a1 = flight_bin<T>(kc, cr.lc, xi, ui, &far);
-                        b0 = flight_bin<T>(kc, cr.lc, xj, uj0, &f0);
-                        b1 = flight_bin<T>(kc, cr.lc, xj, uj, &far);
+                        a0 = flight_bin<T>(kc, cr.lc, xi, ui0);
+                        a1 = flight_bin<T>(kc, cr.lc, xi, ui);
+                        b0 = flight_bin<T>(kc, cr.lc, xj, uj0);
+                        b1 = flight_bin<T>(kc, cr.lc, xj, uj);
                     };
                     if constexpr (std::is_same<T, float>::value) bins(cr.fk);
                     else bins(cases[cr.k]);
@@ -629,7 +624,6 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
         if (g >= 0 && (lane == WAVE - 1 || gd != g) && sacc > 0) atomicAdd(&cl.d_coll[g], sacc);
         if (act && seen > cr.cm)
             atomicMax((unsigned long long *)&cl.cr_seen[g], (unsigned long long)__double_as_longlong(seen));
-        if (far) cl.fix[g] = 1;
         // the next chunk of this work reads what this one stored
         if (more) __threadfence_block();
     };
@@ -813,12 +807,10 @@ __device__ __forceinline__ void big_uni(const CaseK &c, uint32_t step, int lc, u
 
 // move the pair between destination bins of this step's histogram (summed in hd)
 template <typename T>
-__device__ __forceinline__ void big_bins(const CaseK &c, int lc, T xi, T ui0, T ui, T xj, T uj0, T uj, int *hd,
-                                         bool &far)
+__device__ __forceinline__ void big_bins(const CaseK &c, int lc, T xi, T ui0, T ui, T xj, T uj0, T uj, int *hd)
 {
-    bool f0 = false;
-    const int a0 = flight_bin<T>(c, lc, xi, ui0, &f0), a1 = flight_bin<T>(c, lc, xi, ui, &far);
-    const int b0 = flight_bin<T>(c, lc, xj, uj0, &f0), b1 = flight_bin<T>(c, lc, xj, uj, &far);
+    const int a0 = flight_bin<T>(c, lc, xi, ui0), a1 = flight_bin<T>(c, lc, xi, ui);
+    const int b0 = flight_bin<T>(c, lc, xj, uj0), b1 = flight_bin<T>(c, lc, xj, uj);
     if (a0 != a1) {
         if (a0 >= 0) atomicSub(&hd[a0], 1);
         if (a1 >= 0) atomicAdd(&hd[a1], 1);
@@ -876,7 +868,6 @@ __global__ void __launch_bounds__(B, (sizeof(T) == 8 && B == 256) ? 3 : 1) k_col
         P4<T> *sg = segment(cl, g, src, stg, sb);
         if (sb + N > cap) continue;   // capacity overflow, already reported (block-uniform)
         P4<T> *P = sg + sb;           // the cell's records
-        bool far = false;
         const double cm = cl.cr_max[g];
         const double aexp = 1.0 - 2.0 * c.ups;
         if (t < NBIN) hd[t] = 0;
@@ -893,7 +884,7 @@ __global__ void __launch_bounds__(B, (sizeof(T) == 8 && B == 256) ? 3 : 1) k_col
                 ++acc;
                 P[a] = P4<T>{xa, ua, va, wa};
                 P[b] = P4<T>{xb, ub, vb, wb};
-                big_bins<T>(ck, lc, xa, ua0, ua, xb, ub0, ub, hd, far);
+                big_bins<T>(ck, lc, xa, ua0, ua, xb, ub0, ub, hd);
             }
             fwd[0][tt] = ua; fwd[1][tt] = va; fwd[2][tt] = wa;
             fwd[3][tt] = ub; fwd[4][tt] = vb; fwd[5][tt] = wb;
@@ -935,7 +926,7 @@ __global__ void __launch_bounds__(B, (sizeof(T) == 8 && B == 256) ? 3 : 1) k_col
                             ++acc;
                             P[a] = ra;
                             P[bq] = rb;
-                            big_bins<T>(ck, lc, ra.x, ua0, ra.u, rb.x, ub0, rb.u, hd, far);
+                            big_bins<T>(ck, lc, ra.x, ua0, ra.u, rb.x, ub0, rb.u, hd);
                         }
                     }
                 }
@@ -1016,14 +1007,13 @@ __global__ void __launch_bounds__(B, (sizeof(T) == 8 && B == 256) ? 3 : 1) k_col
         int a = wave_sum_i(acc);
         double m = wave_max(seen);
         if (lane == 0) { redi[wv] = a; redd[wv] = m; }
-        const bool anyfar = __syncthreads_or(far);
+        __syncthreads();
         if (t == 0) {
             int sa = 0;
             double sm = 0.0;
             for (int w2 = 0; w2 < NW; ++w2) { sa += redi[w2]; sm = fmax(sm, redd[w2]); }
             cl.d_coll[g] = sa;
             if (sm > cm) cl.cr_seen[g] = (uint64_t)__double_as_longlong(sm);
-            if (anyfar) cl.fix[g] = 1;
         }
         if (t < NBIN && hd[t]) cl.hist[(int64_t)g * NBIN + t] += hd[t];
         __syncthreads();
@@ -1266,74 +1256,47 @@ __global__ void __launch_bounds__(1024) k_inject_rank(const DCase *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// 6. Free flight of the intermediate particles: destination histogram per source cell
+// 6. Free flight of the particles of a loaded canonical state: destination
+// histogram per source cell (the steps keep it from then on: the scatter
+// predicts the next step's, absorption, resampling and collisions move the
+// particles they change between bins)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(512) k_hist_build(const DCase *__restrict__ cases, Cells cl, P4<T> *src,
-                                                     P4<T> *stg, const int64_t *__restrict__ off, int gbeg,
-                                                     int gend, int64_t cap, int all)
+__global__ void __launch_bounds__(512) k_hist_build(const DCase *__restrict__ cases, Cells cl,
+                                                     const P4<T> *__restrict__ src,
+                                                     const int64_t *__restrict__ off, int gbeg, int gend)
 {
-    // Recount of the destination histogram of a cell from its particles: every
-    // cell in [gbeg, gend) of a loaded canonical state (all = 1), or the
-    // intermediate segments of the cells flagged during the step (all = 0,
-    // usually none).  A block takes groups of 64 consecutive cells: one wave
-    // reads their flags, and the block recounts the flagged ones.
+    // a block per cell of [gbeg, gend), in turn
     constexpr int IT = 4;
     __shared__ int h[NBIN];
-    __shared__ int flagged[WAVE];
-    __shared__ int nfl;
-    for (int g0 = gbeg + blockIdx.x * WAVE; g0 < gend; g0 += gridDim.x * WAVE) {
-        if (threadIdx.x < WAVE) {
-            const int gg = g0 + (int)threadIdx.x;
-            const bool f = gg < gend && (all || cl.fix[gg]);
-            const uint64_t m = __ballot(f);
-            if (f) flagged[lane_rank_lt(m)] = gg;
-            if (threadIdx.x == 0) nfl = __popcll(m);
+    for (int g = gbeg + (int)blockIdx.x; g < gend; g += gridDim.x) {
+        const DCase &c = cases[cl.cell_case[g]];
+        const int lc = g - c.cell_base;
+        for (int t = threadIdx.x; t < NBIN; t += blockDim.x) h[t] = 0;
+        __syncthreads();
+        const int64_t b = off[g];
+        const int32_t n = (int32_t)(off[g + 1] - b);
+        for (int i0 = 0; i0 < n; i0 += IT * blockDim.x) {
+            T x[IT], u[IT];
+#pragma unroll
+            for (int j = 0; j < IT; ++j) {
+                const int i = i0 + j * blockDim.x + threadIdx.x;
+                x[j] = 0; u[j] = 0;
+                if (i < n) {
+                    const P4<T> r = src[b + i];
+                    x[j] = r.x; u[j] = r.u;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < IT; ++j) {
+                const int i = i0 + j * blockDim.x + threadIdx.x;
+                if (i >= n) continue;
+                const int hb = flight_bin<T>(c, lc, x[j], u[j]);
+                if (hb >= 0) atomicAdd(&h[hb], 1);
+            }
         }
         __syncthreads();
-        const int nf = nfl;
-        for (int qf = 0; qf < nf; ++qf) {
-            const int g = flagged[qf];
-            const DCase &c = cases[cl.cell_case[g]];
-            const int lc = g - c.cell_base;
-            for (int t = threadIdx.x; t < NBIN; t += blockDim.x) h[t] = 0;
-            __syncthreads();
-            int64_t b;
-            P4<T> *sg;
-            int32_t n;
-            if (all) {
-                sg = src;
-                b = off[g];
-                n = (int32_t)(off[g + 1] - b);
-            } else {
-                sg = segment(cl, g, src, stg, b);
-                n = (int32_t)min((int64_t)cl.n_int[g], cap - b);
-            }
-            bool far = false;
-            for (int i0 = 0; i0 < n; i0 += IT * blockDim.x) {
-                T x[IT], u[IT];
-#pragma unroll
-                for (int j = 0; j < IT; ++j) {
-                    const int i = i0 + j * blockDim.x + threadIdx.x;
-                    x[j] = 0; u[j] = 0;
-                    if (i < n) {
-                        const P4<T> r = sg[b + i];
-                        x[j] = r.x; u[j] = r.u;
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < IT; ++j) {
-                    const int i = i0 + j * blockDim.x + threadIdx.x;
-                    if (i >= n) continue;
-                    const int hb = flight_bin<T>(c, lc, x[j], u[j], &far);
-                    if (hb >= 0) atomicAdd(&h[hb], 1);
-                }
-            }
-            __syncthreads();
-            for (int t = threadIdx.x; t < NBIN; t += blockDim.x) cl.hist[(int64_t)g * NBIN + t] = h[t];
-            if (threadIdx.x == 0) cl.fix[g] = 0;
-            __syncthreads();
-        }
+        for (int t = threadIdx.x; t < NBIN; t += blockDim.x) cl.hist[(int64_t)g * NBIN + t] = h[t];
         __syncthreads();
     }
 }
@@ -1436,10 +1399,8 @@ __device__ __forceinline__ void scatter_entrants(const DCase &c, const Cells &cl
                 const int64_t pos = off_new[d] + cl.inj_ofs[d] + inj.rank[sl];
                 const T x = inj.x[sl], u = inj.u[sl];
                 if (pos < cap) dst[pos] = P4<T>{x, u, inj.v[sl], inj.w[sl]};
-                bool farp = false;
-                const int hb = flight_bin<T>(c, d - c.cell_base, x, u, &farp);
+                const int hb = flight_bin<T>(c, d - c.cell_base, x, u);
                 if (hb >= 0) key = d * NBIN + hb;
-                if (farp) cl.fix_nx[d] = 1;
             }
         }
         uint64_t rem = __ballot(key >= 0);
@@ -1619,10 +1580,8 @@ __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 1 : (MAXW == 1 ? SCAT_W1
             }
             // next step's destination of the particle from its new place
             if (key[j] >= 0) {
-                bool farp = false;
-                const int hb = flight_bin<T>(fk, lc + key[j] - KWIN, X[j], U[j], &farp);
+                const int hb = flight_bin<T>(fk, lc + key[j] - KWIN, X[j], U[j]);
                 if (hb >= 0) atomicAdd(&hn[key[j] * NBIN + hb], 1);
-                if (farp) cl.fix_nx[g + key[j] - KWIN] = 1;
             }
         }
         if (gone) atomicAdd(&nout, gone);
@@ -2058,8 +2017,6 @@ static void step_impl(duwp_ctx *ctx)
     Cells cl = ctx->cl;
     cl.hist = ctx->hist_buf[p];
     cl.hist_nx = ctx->hist_buf[p ^ 1];
-    cl.fix = ctx->fix_buf[p];
-    cl.fix_nx = ctx->fix_buf[p ^ 1];
     {
         Mark m(ctx, "cellstate");
         // 64 cells per block; enough waves in all (>= 8192) to count absorbed
@@ -2138,11 +2095,6 @@ static void step_impl(duwp_ctx *ctx)
     // about 1000 blocks or more
     const int nd = std::max(4, std::min(std::min(CN_D, ctx->count_dests), G / 1024 / 4 * 4));
     {
-        Mark m(ctx, "hist_fix");
-        hipLaunchKernelGGL(k_hist_build<T>, dim3((G + WAVE - 1) / WAVE), dim3(bc), 0, st, ctx->d_cases, cl, src, stg,
-                           ctx->off[p], 0, G, ctx->cap, 0);
-    }
-    {
         Mark m(ctx, "count_bases");
         hipLaunchKernelGGL(k_count_bases, dim3((G + nd - 1) / nd), dim3(256), 0, st, cl, G, nd);
     }
@@ -2214,12 +2166,11 @@ static void reload_impl(duwp_ctx *ctx, int g0, int g1, bool recompute)
     if (n <= 0) return;
     Cells cl = ctx->cl;
     cl.hist = ctx->hist_buf[p];
-    cl.fix = ctx->fix_buf[p];
     P4<T> *const a = recs<T>(ctx->A[p]);
     hipLaunchKernelGGL(k_moments<T>, dim3(std::min(n, 65535)), dim3(ctx->block_cells), 0, ctx->stream, ctx->d_cases,
                        cl, a, ctx->off[p], g0, g1, recompute ? 1 : 0, ctx->d_err);
-    hipLaunchKernelGGL(k_hist_build<T>, dim3((n + WAVE - 1) / WAVE), dim3(ctx->block_cells), 0, ctx->stream,
-                       ctx->d_cases, cl, a, a, ctx->off[p], g0, g1, ctx->cap, 1);
+    hipLaunchKernelGGL(k_hist_build<T>, dim3(std::min(n, 65535)), dim3(ctx->block_cells), 0, ctx->stream,
+                       ctx->d_cases, cl, a, ctx->off[p], g0, g1);
 }
 
 // Shift the canonical cell offsets of cells [g0, G] by delta (after a restore
