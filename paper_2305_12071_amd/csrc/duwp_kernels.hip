@@ -1755,8 +1755,24 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
     }
     if (d0 >= G) return;
     const bool in = d < G && h == 0;
+    // What a lane reads depends on d alone: it is all issued here, before any
+    // store and before the case is known (the face's two cells by global index),
+    // so that a lane waits on its loads once instead of along a chain.
+    const int dc = min(d, G - 1);
+    const int kc = cl.cell_case[dc];
+    const int g0 = max(dc - 1 + h, 0), g1 = min(dc + h, G - 1);
+    double W0[5], W1[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        W0[q] = cl.wt[(int64_t)g0 * 5 + q];
+        W1[q] = cl.wt[(int64_t)g1 * 5 + q];
+    }
+    const int ok0 = cl.okc[g0], ok1 = cl.okc[g1];
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double w0[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, av[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     int64_t ib = 0, ie = 0;
+    int fin = 0, wain = 0;
+    double seen = 0.0, crm = 0.0;
     if (in) {
         constexpr int R = NMB * 5;
 #pragma unroll
@@ -1766,29 +1782,47 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
             const double bq = cl.mnear[(int64_t)d * R + 1 * 5 + q];
             const double cq = d + 1 < G ? cl.mnear[(int64_t)(d + 1) * R + 0 * 5 + q] : 0.0;
             s[q] = (a + bq) + cq;
+            w0[q] = cl.psi_w[(int64_t)d * 5 + q];
+            av[q] = cl.avg[(int64_t)d * 5 + q];
         }
-        if (cl.far_in[d]) {
-            double *row = cl.mpart + (int64_t)d * NBIN * 5;
-            for (int t = 0; t < NBIN; ++t)
-#pragma unroll
-                for (int q = 0; q < 5; ++q) {
-                    s[q] += row[t * 5 + q];
-                    row[t * 5 + q] = 0.0;
-                }
-            cl.far_in[d] = 0;
-        }
+        fin = cl.far_in[d];
+        wain = abs_stream ? cl.wabs_in[d] : 0;
         ib = off_new[d] + cl.inj_ofs[d];
         ie = off_new[d + 1];
+        seen = __longlong_as_double((long long)cl.cr_seen[d]);
+        crm = cl.cr_max[d];
     }
+    if (in && fin) {
+        double *row = cl.mpart + (int64_t)d * NBIN * 5;
+        for (int t = 0; t < NBIN; ++t)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                s[q] += row[t * 5 + q];
+                row[t * 5 + q] = 0.0;
+            }
+        cl.far_in[d] = 0;
+    }
+    // the entrants, cell by cell: each lane sums its records in index order,
+    // four loads in flight (a load past the end repeats the last record and adds
+    // zeros: the loads and sums need no branches)
     uint64_t todo = __ballot(in && ie > ib);
     while (todo) {
         const int l = __ffsll((unsigned long long)todo) - 1;
         todo &= todo - 1;
         const int64_t bl = readlane64(ib, l), el = readlane64(ie, l);
         double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int64_t kk = bl + lane; kk < el; kk += WAVE) {
-            const P4<T> r = dst[kk];
-            add_phi(a, (double)r.u, (double)r.v, (double)r.w);
+        for (int64_t kk = bl + lane; kk < el; kk += 4 * WAVE) {
+            P4<T> r[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) r[j] = dst[min(kk + j * WAVE, el - 1)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool ok = kk + j * WAVE < el;
+                const double u = ok ? (double)r[j].u : 0.0, v = ok ? (double)r[j].v : 0.0;
+                const double w = ok ? (double)r[j].w : 0.0;
+                a[0] += ok ? 1.0 : 0.0; a[1] += u; a[2] += v; a[3] += w;
+                a[4] += 0.5 * (u * u + v * v + w * w);
+            }
         }
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
@@ -1799,9 +1833,13 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
     // wave part: the update with the NS flux of the start-of-step total state
     // (Eq. r1; the states cl.wt are those of the step's start), after the
     // absorbed and resampled moments.  Lane h of a cell takes its face lc + h.
-    const DCase &c = cases[cl.cell_case[min(d, G - 1)]];
+    const DCase &c = cases[kc];
     double F[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (d < G) case_face_flux(c, cl, d - c.cell_base + h, F);
+    if (d < G) {
+        const int f = d - c.cell_base + h;
+        if (c.flux2) case_face_flux(c, cl, f, F);
+        else case_face_flux1(c, f, W0, ok0, W1, ok1, F);
+    }
     double Fr[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) Fr[q] = __shfl_down(F[q], 1, WAVE);
@@ -1812,7 +1850,7 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
         // their sources in order, join the wave part before its flux update
         double wa[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         // (abs_stream: some case of the context streams absorbed particles)
-        const bool win = abs_stream && c.abs_stream && cl.wabs_in[d];
+        const bool win = abs_stream && c.abs_stream && wain;
         if (win) {
             double *row = cl.wabs + (int64_t)d * NBIN * 5;
             for (int t = 0; t < NBIN; ++t)
@@ -1826,14 +1864,13 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
         const double r = c.dt / c.dx;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            const double w0 = win ? cl.psi_w[(int64_t)d * 5 + q] + c.fac * wa[q] : cl.psi_w[(int64_t)d * 5 + q];
-            pw[q] = w0 - r * (Fr[q] - F[q]);
+            const double w = win ? w0[q] + c.fac * wa[q] : w0[q];
+            pw[q] = w - r * (Fr[q] - F[q]);
             cl.psi_w[(int64_t)d * 5 + q] = pw[q];
         }
     }
     // largest relative speed seen by this cell's collision candidates
-    const double seen = __longlong_as_double((long long)cl.cr_seen[d]);
-    if (seen > cl.cr_max[d]) cl.cr_max[d] = seen;
+    if (seen > crm) cl.cr_max[d] = seen;
     cl.cr_seen[d] = 0ull;
     bool bad = false;
 #pragma unroll
@@ -1842,7 +1879,7 @@ __global__ void __launch_bounds__(256) k_gather_moments(const DCase *__restrict_
         cl.psi_p[(int64_t)d * 5 + q] = p;
         const double t = pw[q] + p;
         if (!isfinite(t)) bad = true;
-        cl.avg[(int64_t)d * 5 + q] += t;
+        cl.avg[(int64_t)d * 5 + q] = av[q] + t;
     }
     if (bad) atomicOr(err, ERR_STATE);
 }

@@ -393,6 +393,48 @@ __device__ inline void case_face_flux(const DCase &c, const Cells &cl, int f, do
     }
 }
 
+// First-order flux through local face f of a case, from the start-of-step
+// states of global cells g-1 and g (face f = g - cell_base) that the caller
+// loaded beforehand, indices clamped to the grid: the same states and ghosts as
+// case_face_flux takes (a wall's ghost mirrors the boundary cell, which is g at
+// f = 0 and g-1 at f = ncells; a reservoir's is its own state).
+__device__ inline void case_face_flux1(const DCase &c, int f, const double (&Wg0)[5], int ok0,
+                                       const double (&Wg1)[5], int ok1, double F[5])
+{
+    double Wl[5], Wr[5];
+    int okl = 1, okr = 1;
+    if (f > 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Wl[k] = Wg0[k];
+        okl = ok0;
+    } else if (c.bc_lo == 0) {
+        Wl[0] = c.rho_L; Wl[1] = c.u_L; Wl[2] = 0.0; Wl[3] = 0.0; Wl[4] = c.T_L;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Wl[k] = Wg1[k];
+        Wl[1] = -Wl[1];
+        okl = ok1;
+    }
+    if (f < c.ncells) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Wr[k] = Wg1[k];
+        okr = ok1;
+    } else if (c.bc_hi == 0) {
+        Wr[0] = c.rho_R; Wr[1] = c.u_R; Wr[2] = 0.0; Wr[3] = 0.0; Wr[4] = c.T_R;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Wr[k] = Wg0[k];
+        Wr[1] = -Wr[1];
+        okr = ok0;
+    }
+    if (!(okl && okr)) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) F[k] = 0.0;
+        return;
+    }
+    face_flux(c, Wl, Wr, Wl, Wr, F);
+}
+
 // ---------------------------------------------------------------------------
 // Equal-mass VHS collision of a particle pair held in registers (Appendix A):
 // acceptance (c_r/c_max)^(1-2 upsilon), isotropic scattering with
