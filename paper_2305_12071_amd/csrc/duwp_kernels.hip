@@ -1379,6 +1379,51 @@ __global__ void __launch_bounds__(256) k_count_bases(Cells cl, int G, int nd)
     }
 }
 
+// 7+8 on small grids (G <= CS1_MAX): the same group bases and the offsets of
+// the next array in one block, every histogram row in LDS and a thread per
+// destination, then the block's scan of the destination counts (one launch
+// instead of two on grids whose passes are all latency).
+constexpr int CS1_MAX = 448;
+
+__global__ void __launch_bounds__(1024) k_count_scan_small(Cells cl, int G, int64_t *__restrict__ out,
+                                                           int64_t cap, int64_t *total, int32_t *err)
+{
+    __shared__ int tile[(CS1_MAX + 2 * KWIN) * NBIN];
+    __shared__ int64_t lds[16];
+    load_hist_tile(cl, 0, G, G, tile);
+    __syncthreads();
+    const int d = threadIdx.x;
+    int64_t cnt = 0;
+    if (d < G) {
+        int run = 0;
+#pragma unroll
+        for (int l = 0; l < NBIN; ++l) {
+            const int ti = (d + l) * NBIN + (2 * KWIN - l);
+            const int h = tile[ti];
+            tile[ti] = run;
+            run += h;
+        }
+        cl.inj_ofs[d] = run;
+        cnt = run + cl.inj_cnt[d];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < (G + 2 * KWIN) * NBIN; t += blockDim.x) {
+        const int src = t / NBIN - KWIN;
+        const int dd = src + t % NBIN - KWIN;
+        if (src >= 0 && src < G && dd >= 0 && dd < G) cl.hist[(int64_t)src * NBIN + t % NBIN] = tile[t];
+    }
+    // offsets, clamped to the capacity like the other scans
+    int64_t tot;
+    const int64_t ex = block_exclusive_scan64(cnt, lds, &tot);
+    if (d < G) out[d] = ex < cap ? ex : cap;
+    if (d == G - 1) {
+        const int64_t end = ex + cnt;
+        out[G] = end < cap ? end : cap;
+        *total = end;
+        if (end > cap) atomicOr(err, ERR_CAPACITY);
+    }
+}
+
 // Entrants go after the cell-sourced particles of their destination cell; their
 // next-step destinations join the predicted histogram.  Part sub of nsub of the
 // entrants of case k.
@@ -2131,11 +2176,15 @@ static void step_impl(duwp_ctx *ctx)
     // each, small grids) or up to 256 (a thread each), so that its grid keeps
     // about 1000 blocks or more
     const int nd = std::max(4, std::min(std::min(CN_D, ctx->count_dests), G / 1024 / 4 * 4));
-    {
-        Mark m(ctx, "count_bases");
-        hipLaunchKernelGGL(k_count_bases, dim3((G + nd - 1) / nd), dim3(256), 0, st, cl, G, nd);
-    }
-    {
+    if (G <= CS1_MAX) {
+        Mark m(ctx, "count_scan");
+        hipLaunchKernelGGL(k_count_scan_small, dim3(1), dim3(1024), 0, st, cl, G, ctx->off[p ^ 1], ctx->cap,
+                           ctx->d_total + 1, ctx->d_err);
+    } else {
+        {
+            Mark m(ctx, "count_bases");
+            hipLaunchKernelGGL(k_count_bases, dim3((G + nd - 1) / nd), dim3(256), 0, st, cl, G, nd);
+        }
         Mark m(ctx, "scan_offsets");
         enqueue_scan(ctx, ctx->cl.cnt_new, ctx->off[p ^ 1], ctx->d_total + 1, ctx->cap);
     }
