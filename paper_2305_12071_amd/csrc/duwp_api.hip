@@ -458,7 +458,7 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
             d.cand_base[side] = cand;
             d.cand_cap[side] = nb;
             d.chunk_base[side] = chunks;
-            chunks += (nb + 255) / 256;
+            chunks += (nb + duwp::INJ_CH - 1) / duwp::INJ_CH;
             cand += nb;
             ib += nb;
             max_side = std::max(max_side, nb);

@@ -27,7 +27,7 @@ struct DCase {
     uint32_t key0, key1;
     int64_t inj_base, inj_cap;       // slot range of this case's entrants in the injection buffer
     int64_t cand_base[2], cand_cap[2];  // injection candidate slots per side
-    int64_t chunk_base[2];              // per-side entrant counts of 256-slot candidate chunks
+    int64_t chunk_base[2];              // per-side entrant counts of INJ_CH-slot candidate chunks
     double x_lo, x_hi, dx, dt;
     double R, omega, T_ref, mu_ref, coll_k, ups, c_ref;
     double m_p, fac;                 // fac = m_p / dx
@@ -127,8 +127,12 @@ struct Inj {
     T *cx, *cu, *cv, *cw;
     int32_t *cdest;     // local destination of a candidate, -1 if it does not enter
     int64_t *ncand;     // [ncases*2] candidates generated per side
-    int32_t *cchunk;    // entrants per 256-slot candidate chunk (entrants compacted to the chunk front)
+    int32_t *cchunk;    // entrants per INJ_CH-slot candidate chunk (entrants compacted to the chunk front)
 };
+
+// Injection candidate slots per chunk: one wave's worth, so that any wave of
+// any launch can generate and compact a chunk by itself.
+constexpr int INJ_CH = WAVE;
 
 // One particle: position and velocity in one record (16 B with FP32 particles,
 // 32 B with FP64), so that a particle is one vector access and one cache line.

@@ -43,26 +43,42 @@ constexpr int MB = 1;                  // destinations |d| <= MB get register mo
 constexpr int NMB = 2 * MB + 1;
 constexpr int NBI = 2 * (KWIN + 1);    // injection destination window (both ends)
 
+template <typename T>
+__device__ void inject_gen_wave(const DCase &c, int k, int side, const Inj<T> &inj, uint32_t step, int32_t *err,
+                                int wi, int nwv);
+template <typename T>
+__device__ void inject_rank_block(const DCase &c, const Cells &cl, const Inj<T> &inj, int64_t *d_ninj, int32_t *err,
+                                  int k, int y);
+
 // ---------------------------------------------------------------------------
 // 1. Cell state at step start, absorbed and resampled counts, collision
 // candidate counts.  A block takes 64 cells, one lane of its first wave per
 // cell; the absorbed particles of its cells with P > 0 are counted by all of
 // its waves (cell l by wave l mod waves), so that cells with many particles
-// keep the whole GPU busy.
+// keep the whole GPU busy.  The gen_b blocks per (case, side) after the cells'
+// blocks generate the step's injection candidates (they read nothing the step
+// computes).
 // ---------------------------------------------------------------------------
+template <typename T>
 __global__ void __launch_bounds__(1024) k_cellstate(const DCase *__restrict__ cases, Cells cl,
                                                      const int64_t *__restrict__ off,
                                                      const uint32_t *__restrict__ d_step, int G,
                                                      int32_t *err, int64_t *d_nout, int64_t *d_ninj,
-                                                     int abs_stream, int big_min_n, int big_min_m, int64_t cap)
+                                                     int abs_stream, int big_min_n, int big_min_m, int64_t cap,
+                                                     Inj<T> inj, int gen_b)
 {
     __shared__ double sP[WAVE];
     __shared__ int64_t sb[WAVE], se[WAVE], spb[WAVE];
     __shared__ int sk[WAVE], scnt[WAVE];
     const uint32_t step = *d_step;
     const int lane = lane_id(), wv = wave_id(), nw = blockDim.x >> 6;
+    const int cblk = (G + WAVE - 1) / WAVE;
+    if ((int)blockIdx.x >= cblk) {
+        const int e = (int)blockIdx.x - cblk, ks = e / gen_b, sub = e - ks * gen_b;
+        inject_gen_wave<T>(cases[ks >> 1], ks >> 1, ks & 1, inj, step, err, sub * nw + wv, gen_b * nw);
+        return;
+    }
     const int g0 = blockIdx.x * WAVE;
-    if (g0 >= G) return;
     const int nc = min(WAVE, G - g0);
     for (int t = threadIdx.x; t < nc * NBIN; t += blockDim.x) cl.hist_nx[(int64_t)g0 * NBIN + t] = 0;
     const int g = g0 + lane;
@@ -498,8 +514,17 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases, Cells cl, P4<T> *src,
                                                  P4<T> *stg, const uint32_t *__restrict__ d_step, int G,
                                                  int64_t cap, int32_t *err, const int32_t *__restrict__ item_cell,
-                                                 const int64_t *__restrict__ d_items, int by_cell)
+                                                 const int64_t *__restrict__ d_items, int by_cell, Inj<T> inj,
+                                                 int64_t *d_ninj, int nrk)
 {
+    // the first nrk blocks rank the step's entrants, two per case (the
+    // collisions neither read nor write what they touch)
+    if ((int)blockIdx.x < nrk) {
+        const int kk = (int)blockIdx.x >> 1;
+        inject_rank_block<T>(cases[kk], cl, inj, d_ninj, err, kk, (int)blockIdx.x & 1);
+        return;
+    }
+    const int bid = (int)blockIdx.x - nrk, nbk = (int)gridDim.x - nrk;
     __shared__ uint64_t hmask[COLL_WPB][1 << COLL_HBITS];
     __shared__ T fwd[COLL_WPB][6][WAVE];     // (u,v,w) of particle i, then of j, per lane
     const int wv = wave_id(), lane = lane_id();
@@ -630,7 +655,7 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
     if (by_cell) {
         // a wave per cell, cells in visiting order (few cells with many
         // candidates); the cell's constants are read once, not per chunk
-        for (int gi = blockIdx.x * COLL_WPB + wv; gi < G; gi += gridDim.x * COLL_WPB) {
+        for (int gi = bid * COLL_WPB + wv; gi < G; gi += nbk * COLL_WPB) {
             const int g = __builtin_amdgcn_readfirstlane(cl.order[gi]);
             const int32_t M = __builtin_amdgcn_readfirstlane(cl.ncand_w[g]);
             if (M <= 0) continue;
@@ -656,7 +681,7 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
     }
     // work items of whole cells from the scanned candidate list
     const int64_t nitems = d_items[0];
-    for (int64_t it = (int64_t)blockIdx.x * COLL_WPB + wv; it < nitems; it += (int64_t)gridDim.x * COLL_WPB) {
+    for (int64_t it = (int64_t)bid * COLL_WPB + wv; it < nitems; it += (int64_t)nbk * COLL_WPB) {
         const int ga = item_cell[it];
         const int gb = it + 1 < nitems ? item_cell[it + 1] : G;
         const int64_t qend = cl.cbase[gb];
@@ -1023,17 +1048,19 @@ __global__ void __launch_bounds__(B, (sizeof(T) == 8 && B == 256) ? 3 : 1) k_col
 // ---------------------------------------------------------------------------
 // 5a. Reservoir injection candidates, in parallel over (case, side, slot):
 // a particle sampled in the ghost slab beyond a reservoir side, streamed over
-// dt; it enters when it ends inside the domain.
+// dt; it enters when it ends inside the domain.  Side `side` of case k, by
+// wave wi of the nwv waves that take this side: chunk ci of INJ_CH slots goes
+// to wave ci mod nwv, which compacts its entrants, in slot order, to the
+// chunk's front.  (Run by extra blocks of the cell-state launch: the
+// candidates depend on the step and the case alone.)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) k_inject_gen(const DCase *__restrict__ cases, Inj<T> inj,
-                                                    const uint32_t *__restrict__ d_step, int32_t *err)
+__device__ void inject_gen_wave(const DCase &c, int k, int side, const Inj<T> &inj, uint32_t step, int32_t *err,
+                                int wi, int nwv)
 {
-    const uint32_t step = *d_step;
-    const int k = blockIdx.y >> 1, side = blockIdx.y & 1;
-    const DCase &c = cases[k];
+    const int lane = lane_id();
     if ((side == 0 ? c.bc_lo : c.bc_hi) != 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) inj.ncand[blockIdx.y] = 0;
+        if (wi == 0 && lane == 0) inj.ncand[2 * k + side] = 0;
         return;
     }
     const double rho = side == 0 ? c.rho_L : c.rho_R;
@@ -1046,16 +1073,14 @@ __global__ void __launch_bounds__(256) k_inject_gen(const DCase *__restrict__ ca
     double nf = floor((1.0 - Ps) * rho * Lg / c.m_p + u01(r.a));
     int64_t ng = (int64_t)fmin(nf, 4.0e9);
     if (ng > c.cand_cap[side]) {
-        if (threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
+        if (wi == 0 && lane == 0) atomicOr(err, ERR_CAPACITY);
         ng = c.cand_cap[side];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) inj.ncand[blockIdx.y] = ng;
+    if (wi == 0 && lane == 0) inj.ncand[2 * k + side] = ng;
     const int64_t cb = c.cand_base[side];
-    __shared__ int scr[16];
     const Maxwell<T> mw(U, 0.0, 0.0, Ts, c.R);
-    // 256-slot chunks; the entrants of a chunk are compacted, in slot order, to its front
-    for (int64_t ci = blockIdx.x; ci * 256 < ng; ci += gridDim.x) {
-        const int64_t q = ci * 256 + threadIdx.x;
+    for (int64_t ci = wi; ci * INJ_CH < ng; ci += nwv) {
+        const int64_t q = ci * INJ_CH + lane;
         int dest = -1;
         T px = 0, pu = 0, pv = 0, pw = 0;
         if (q < ng) {
@@ -1083,14 +1108,13 @@ __global__ void __launch_bounds__(256) k_inject_gen(const DCase *__restrict__ ca
             pv = xi[1]; pw = xi[2];
         }
         const bool ent = dest >= 0;
-        int tot;
-        const int pre = block_flag_prefix(ent, scr, &tot);
+        const uint64_t m = __ballot(ent);
         if (ent) {
-            const int64_t sl = cb + ci * 256 + pre;
+            const int64_t sl = cb + ci * INJ_CH + lane_rank_lt(m);
             inj.cx[sl] = px; inj.cu[sl] = pu; inj.cv[sl] = pv; inj.cw[sl] = pw;
             inj.cdest[sl] = dest;
         }
-        if (threadIdx.x == 0) inj.cchunk[c.chunk_base[side] + ci] = tot;
+        if (lane == 0) inj.cchunk[c.chunk_base[side] + ci] = __popcll(m);
     }
 }
 
@@ -1111,8 +1135,8 @@ __device__ __forceinline__ int inj_cell(int slot, int C)
 
 // Stable rank of per-thread keys in [0,NB) within one chunk of a block (one key
 // per thread, in thread order), continuing the running counts binbase[];
-// returns the rank, or -1 for a key < 0.  wcnt holds 16 x NB ints, zero on
-// entry and on exit.
+// returns the rank, or -1 for a key < 0.  wcnt holds a row of NB ints per wave,
+// zero on entry and on exit.
 template <int NB>
 __device__ __forceinline__ int block_stable_rank(int key, int *binbase, int (*wcnt)[NB])
 {
@@ -1150,64 +1174,71 @@ __device__ __forceinline__ int block_stable_rank(int key, int *binbase, int (*wc
 // each side's entrants then land in that side's own bins (one landing in the
 // other side's bins has crossed more than the sort window and is reported), and
 // side 1's entrants follow side 0's.  An entrant that is reported keeps its place
-// with destination -1 and is not scattered.
+// with destination -1 and is not scattered.  Block y of case k, RK_THREADS
+// threads (run by the first blocks of the collision launch: the ranks are
+// needed only by the scatter, and the collisions do not touch them).
+constexpr int RK_THREADS = 256;
+static_assert(RK_THREADS == WAVE * COLL_WPB, "the entrants are ranked by blocks of the collision launch");
 template <typename T>
-__global__ void __launch_bounds__(1024) k_inject_rank(const DCase *__restrict__ cases, Cells cl, Inj<T> inj,
-                                                      int64_t *d_ninj, int32_t *err)
+__device__ void inject_rank_block(const DCase &c, const Cells &cl, const Inj<T> &inj, int64_t *d_ninj, int32_t *err,
+                                  int k, int y)
 {
-    constexpr int MAXCH = 2048;
+    constexpr int MAXCH = 1024;                  // chunks per pass
+    constexpr int RK_IT = MAXCH / RK_THREADS;    // chunk counts per thread in the prefix
+    constexpr int NW = RK_THREADS / WAVE;
     __shared__ int binbase[NBI];
-    __shared__ int wcnt[16][NBI];
+    __shared__ int wcnt[NW][NBI];
     __shared__ int pref[MAXCH + 1];
-    __shared__ int red[16];
-    const int k = blockIdx.x;
-    const DCase &c = cases[k];
+    __shared__ int red[NW];
+    __shared__ int64_t lds[NW];
     const int C = c.ncells;
     const int lane = lane_id();
     const bool split = C > NBI;
-    if (!split && blockIdx.y == 1) return;
-    const int s0 = split ? (int)blockIdx.y : 0, s1 = split ? s0 + 1 : 2;
-    for (int t = threadIdx.x; t < NBI; t += blockDim.x) binbase[t] = 0;
-    for (int t = threadIdx.x; t < 16 * NBI; t += blockDim.x) (&wcnt[0][0])[t] = 0;
+    if (!split && y == 1) return;
+    const int s0 = split ? y : 0, s1 = split ? s0 + 1 : 2;
+    for (int t = threadIdx.x; t < NBI; t += RK_THREADS) binbase[t] = 0;
+    for (int t = threadIdx.x; t < NW * NBI; t += RK_THREADS) (&wcnt[0][0])[t] = 0;
     int64_t count = 0;
     if (s0 == 1) {
         // side 1 follows the entrants of side 0: the sum of its chunk counts
-        const int64_t nch0 = (inj.ncand[2 * k] + 255) / 256;
+        const int64_t nch0 = (inj.ncand[2 * k] + INJ_CH - 1) / INJ_CH;
         int sum = 0;
-        for (int64_t i = threadIdx.x; i < nch0; i += blockDim.x) sum += inj.cchunk[c.chunk_base[0] + i];
+        for (int64_t i = threadIdx.x; i < nch0; i += RK_THREADS) sum += inj.cchunk[c.chunk_base[0] + i];
         sum = wave_sum_i(sum);
         if (lane == 0) red[wave_id()] = sum;
         __syncthreads();
-        for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) count += red[w2];
+        for (int w2 = 0; w2 < NW; ++w2) count += red[w2];
     }
     __syncthreads();
     for (int side = s0; side < s1; ++side) {
         const int64_t n = inj.ncand[2 * k + side];
         const int64_t cb = c.cand_base[side];
-        const int64_t nch = (n + 255) / 256;
+        const int64_t nch = (n + INJ_CH - 1) / INJ_CH;
         int64_t nside = 0;
         for (int64_t ch0 = 0; ch0 < nch; ch0 += MAXCH) {
             const int nb = (int)min((int64_t)MAXCH, nch - ch0);
-            // exclusive prefix of the chunk counts (first wave)
-            if (threadIdx.x < WAVE) {
-                int carry = 0;
-                for (int i0 = 0; i0 < nb; i0 += WAVE) {
-                    const int i = i0 + lane;
-                    const int v = i < nb ? inj.cchunk[c.chunk_base[side] + ch0 + i] : 0;
-                    int incl = v;
+            // exclusive prefix of the chunk counts: a thread loads RK_IT
+            // consecutive counts at once, then one block scan
+            int v[RK_IT];
+            int sv = 0;
 #pragma unroll
-                    for (int o = 1; o < WAVE; o <<= 1) {
-                        const int t = __shfl_up(incl, o, WAVE);
-                        if (lane >= o) incl += t;
-                    }
-                    if (i < nb) pref[i] = carry + incl - v;
-                    carry += __shfl(incl, WAVE - 1, WAVE);
-                }
-                if (lane == 0) pref[nb] = carry;
+            for (int jj = 0; jj < RK_IT; ++jj) {
+                const int i = threadIdx.x * RK_IT + jj;
+                v[jj] = i < nb ? inj.cchunk[c.chunk_base[side] + ch0 + i] : 0;
+                sv += v[jj];
             }
+            int64_t tot;
+            int64_t ex = block_exclusive_scan64(sv, lds, &tot);
+#pragma unroll
+            for (int jj = 0; jj < RK_IT; ++jj) {
+                const int i = threadIdx.x * RK_IT + jj;
+                if (i < nb) pref[i] = (int)ex;
+                ex += v[jj];
+            }
+            if (threadIdx.x == 0) pref[nb] = (int)tot;
             __syncthreads();
             const int E = pref[nb];
-            for (int e0 = 0; e0 < E; e0 += blockDim.x) {
+            for (int e0 = 0; e0 < E; e0 += RK_THREADS) {
                 const int e = e0 + threadIdx.x;
                 int slot = -1, d = -1;
                 int64_t slc = 0;
@@ -1217,7 +1248,7 @@ __global__ void __launch_bounds__(1024) k_inject_rank(const DCase *__restrict__ 
                         const int mid = (lo + hi + 1) >> 1;
                         if (pref[mid] <= e) lo = mid; else hi = mid - 1;
                     }
-                    slc = cb + (ch0 + lo) * 256 + (e - pref[lo]);
+                    slc = cb + (ch0 + lo) * INJ_CH + (e - pref[lo]);
                     d = inj.cdest[slc];
                     slot = inj_slot(d, C);
                     if (slot >= 0 && split && (slot <= KWIN ? 0 : 1) != side) slot = -1;
@@ -1248,7 +1279,7 @@ __global__ void __launch_bounds__(1024) k_inject_rank(const DCase *__restrict__ 
         if (threadIdx.x == 0) d_ninj[2 * k + side] = nside;
     }
     // entrant counts of the bins of the sides ranked here
-    for (int t = threadIdx.x; t < NBI; t += blockDim.x) {
+    for (int t = threadIdx.x; t < NBI; t += RK_THREADS) {
         const int d = inj_cell(t, C);
         if (d >= 0 && (!split || (t <= KWIN ? 0 : 1) == s0)) cl.inj_cnt[c.cell_base + d] = binbase[t];
     }
@@ -2105,9 +2136,12 @@ static void step_impl(duwp_ctx *ctx)
         // particles of large cells at full occupancy, at most 16 per block
         const int cblk = (G + WAVE - 1) / WAVE;
         const int cw = std::max(1, std::min(16, (8192 + cblk - 1) / cblk));
-        hipLaunchKernelGGL(k_cellstate, dim3(cblk), dim3(WAVE * cw), 0, st, ctx->d_cases, cl, ctx->off[p],
-                           ctx->d_step, G, ctx->d_err, ctx->d_nout, ctx->d_ninj, ctx->abs_stream,
-                           ctx->big_min_n, ctx->big_min_m, ctx->cap);
+        // then the injection candidates: at least four waves per 256 slots of
+        // the largest side (up to 256 waves a side)
+        const int gen_b = ctx->inj_blocks > 0 ? (4 * ctx->inj_blocks + cw - 1) / cw : 0;
+        hipLaunchKernelGGL(k_cellstate<T>, dim3(cblk + 2 * ctx->ncases * gen_b), dim3(WAVE * cw), 0, st,
+                           ctx->d_cases, cl, ctx->off[p], ctx->d_step, G, ctx->d_err, ctx->d_nout, ctx->d_ninj,
+                           ctx->abs_stream, ctx->big_min_n, ctx->big_min_m, ctx->cap, inj, gen_b);
     }
     {
         Mark m(ctx, "absorb_resample");
@@ -2121,25 +2155,17 @@ static void step_impl(duwp_ctx *ctx)
                                st, ctx->d_cases, cl, src, ctx->off[p], stg, ctx->d_step, G, ctx->cap,
                                ctx->d_err, ctx->d_nout);
     }
-    // Injection and the big-cell collide do not depend on the small-cell collide:
-    // they go on a second stream (a parallel branch of the captured graph).
-    // Kernel timing keeps everything on one stream.
-    const bool fork = !ctx->timer.on && ctx->stream2 != nullptr;
+    // The big-cell collide does not depend on the small-cell collide: it goes
+    // on a second stream (a parallel branch of the captured graph).  Kernel
+    // timing keeps everything on one stream.
+    const bool big = ctx->big_min_m < INT32_MAX;
+    const bool fork = big && !ctx->timer.on && ctx->stream2 != nullptr;
     hipStream_t s2 = fork ? ctx->stream2 : st;
     if (fork) {
         (void)hipEventRecord(ctx->ev_fork, st);
         (void)hipStreamWaitEvent(s2, ctx->ev_fork, 0);
     }
-    {
-        Mark m(ctx, "inject");
-        if (ctx->inj_blocks > 0)
-            hipLaunchKernelGGL(k_inject_gen<T>, dim3(ctx->inj_blocks, 2 * ctx->ncases), dim3(256), 0, s2,
-                               ctx->d_cases, inj, ctx->d_step, ctx->d_err);
-        // 1024 threads: a side's entrants in few rounds (each round waits on loads)
-        hipLaunchKernelGGL(k_inject_rank<T>, dim3(ctx->ncases, 2), dim3(1024), 0, s2, ctx->d_cases, cl, inj,
-                           ctx->d_ninj, ctx->d_err);
-    }
-    if (ctx->big_min_m < INT32_MAX) {
+    if (big) {
         // cells with many particles and candidates (their own list): disjoint
         // from the cells of k_collide, so the two run side by side (a threshold
         // no cell reaches leaves the kernel out)
@@ -2167,9 +2193,11 @@ static void step_impl(duwp_ctx *ctx)
                                ctx->item_cell, ctx->d_items, ctx->items_cap);
         }
         const int cblocks = by_cell ? std::min(ctx->coll_blocks, (G + COLL_WPB - 1) / COLL_WPB) : ctx->coll_blocks;
-        hipLaunchKernelGGL(k_collide<T>, dim3(cblocks), dim3(64 * COLL_WPB), 0, st, ctx->d_cases,
+        // first, two blocks per case that rank the entrants
+        const int nrk = 2 * ctx->ncases;
+        hipLaunchKernelGGL(k_collide<T>, dim3(nrk + cblocks), dim3(64 * COLL_WPB), 0, st, ctx->d_cases,
                            cl, src, stg, ctx->d_step, G, ctx->cap, ctx->d_err, ctx->item_cell, ctx->d_items,
-                           by_cell);
+                           by_cell, inj, ctx->d_ninj, nrk);
     }
     if (fork) (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
     // destinations per block of the histogram pass before the scatter: 4 (a wave
