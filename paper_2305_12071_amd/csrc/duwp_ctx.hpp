@@ -67,6 +67,7 @@ struct duwp_ctx {
     int64_t items_cap = 0;
     int coll_blocks = 0;
     int big_blocks = 0;            // grid of the block-per-cell collision kernel
+    int rank_sep = 0;              // 1: the entrants are ranked by a kernel of their own (many candidates a side)
     int scat_by_order = 1;         // scatter blocks take cells largest first (few rounds of blocks)
     int abs_stream = 0;            // some case lets absorbed particles stream for their free time
     double *diag = nullptr;        // [G*5] on-demand cell diagnostics

@@ -46,7 +46,7 @@ constexpr int NBI = 2 * (KWIN + 1);    // injection destination window (both end
 template <typename T>
 __device__ void inject_gen_wave(const DCase &c, int k, int side, const Inj<T> &inj, uint32_t step, int32_t *err,
                                 int wi, int nwv);
-template <typename T>
+template <typename T, int NT>
 __device__ void inject_rank_block(const DCase &c, const Cells &cl, const Inj<T> &inj, int64_t *d_ninj, int32_t *err,
                                   int k, int y);
 
@@ -521,7 +521,7 @@ __global__ void __launch_bounds__(256) k_collide(const DCase *__restrict__ cases
     // collisions neither read nor write what they touch)
     if ((int)blockIdx.x < nrk) {
         const int kk = (int)blockIdx.x >> 1;
-        inject_rank_block<T>(cases[kk], cl, inj, d_ninj, err, kk, (int)blockIdx.x & 1);
+        inject_rank_block<T, WAVE * COLL_WPB>(cases[kk], cl, inj, d_ninj, err, kk, (int)blockIdx.x & 1);
         return;
     }
     const int bid = (int)blockIdx.x - nrk, nbk = (int)gridDim.x - nrk;
@@ -1175,14 +1175,17 @@ __device__ __forceinline__ int block_stable_rank(int key, int *binbase, int (*wc
 // other side's bins has crossed more than the sort window and is reported), and
 // side 1's entrants follow side 0's.  An entrant that is reported keeps its place
 // with destination -1 and is not scattered.  Block y of case k, RK_THREADS
-// threads (run by the first blocks of the collision launch: the ranks are
-// needed only by the scatter, and the collisions do not touch them).
+// threads: the first blocks of the collision launch (the ranks are needed
+// only by the scatter, and the collisions do not touch them), or, when a side
+// may have many entrants, a kernel of its own with 1024 threads a block (a
+// quarter of the rounds).
 constexpr int RK_THREADS = 256;
 static_assert(RK_THREADS == WAVE * COLL_WPB, "the entrants are ranked by blocks of the collision launch");
-template <typename T>
+template <typename T, int NT>
 __device__ void inject_rank_block(const DCase &c, const Cells &cl, const Inj<T> &inj, int64_t *d_ninj, int32_t *err,
                                   int k, int y)
 {
+    constexpr int RK_THREADS = NT;
     constexpr int MAXCH = 1024;                  // chunks per pass
     constexpr int RK_IT = MAXCH / RK_THREADS;    // chunk counts per thread in the prefix
     constexpr int NW = RK_THREADS / WAVE;
@@ -1284,6 +1287,13 @@ __device__ void inject_rank_block(const DCase &c, const Cells &cl, const Inj<T> 
         if (d >= 0 && (!split || (t <= KWIN ? 0 : 1) == s0)) cl.inj_cnt[c.cell_base + d] = binbase[t];
     }
     if (threadIdx.x == 0 && s1 == 2) inj.count[k] = (int32_t)min(count, c.inj_cap);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_inject_rank(const DCase *__restrict__ cases, Cells cl, Inj<T> inj,
+                                                      int64_t *d_ninj, int32_t *err)
+{
+    inject_rank_block<T, 1024>(cases[blockIdx.x], cl, inj, d_ninj, err, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -2182,6 +2192,11 @@ static void step_impl(duwp_ctx *ctx)
                                ctx->d_step, ctx->cap);
     }
     if (fork) (void)hipEventRecord(ctx->ev_join, s2);
+    if (ctx->rank_sep) {
+        Mark m(ctx, "inject_rank");
+        hipLaunchKernelGGL(k_inject_rank<T>, dim3(ctx->ncases, 2), dim3(1024), 0, st, ctx->d_cases, cl, inj,
+                           ctx->d_ninj, ctx->d_err);
+    }
     {
         Mark m(ctx, "collide");
         // few cells: a wave per cell; many (mostly small) cells: work items cut
@@ -2193,8 +2208,9 @@ static void step_impl(duwp_ctx *ctx)
                                ctx->item_cell, ctx->d_items, ctx->items_cap);
         }
         const int cblocks = by_cell ? std::min(ctx->coll_blocks, (G + COLL_WPB - 1) / COLL_WPB) : ctx->coll_blocks;
-        // first, two blocks per case that rank the entrants
-        const int nrk = 2 * ctx->ncases;
+        // first, two blocks per case that rank the entrants (unless they have
+        // a kernel of their own)
+        const int nrk = ctx->rank_sep ? 0 : 2 * ctx->ncases;
         hipLaunchKernelGGL(k_collide<T>, dim3(nrk + cblocks), dim3(64 * COLL_WPB), 0, st, ctx->d_cases,
                            cl, src, stg, ctx->d_step, G, ctx->cap, ctx->d_err, ctx->item_cell, ctx->d_items,
                            by_cell, inj, ctx->d_ninj, nrk);
