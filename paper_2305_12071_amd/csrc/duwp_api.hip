@@ -476,8 +476,8 @@ duwp_status duwp_init(duwp_ctx **out, const duwp_case *cases, int32_t ncases, co
     ctx->inj_blocks = (int)std::min<int64_t>((max_side + 255) / 256, 64);
     // sides that may draw more than 2^18 candidates have their entrants ranked
     // by 1024-thread blocks of a kernel of their own rather than inside the
-    // collision launch (a quarter of the rounds: 0.43 -> 0.04 ms on the Mach-10
-    // shock, whose inflow brings 1e5 entrants a step)
+    // collision launch (a quarter of the rounds: 0.43 -> 0.05 ms on the Mach-10
+    // shock, whose inflow brings 1.4e5 entrants a step)
     ctx->rank_sep = max_side > (1 << 18) ? 1 : 0;
     {
         // collision work items are taken by a fixed grid of 16 blocks (64 waves) per compute unit
