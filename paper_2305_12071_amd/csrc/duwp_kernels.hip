@@ -13,14 +13,16 @@
 // Per step (Sec. 3.4, Steps 2-3, Eq. r1):
 //   cellstate        Psi_t = Psi_w + Psi_p, (rho,U,T), tau = mu/p, P (Eq. p),
 //                    absorbed and resampled counts, staging segments of the
-//                    cells that change
+//                    cells that change; in extra blocks, the reservoir
+//                    injection candidates
 //   absorb_resample  classify, absorb into Psi_w, compact survivors, sample
 //                    new particles (Eq. maxsample), subtract their moments
 //   collide          NTC/VHS (Appendix A), candidates in order: a wave per
 //                    cell or per work item with conflict-free rounds, or a
-//                    block per big cell
-//   inject_gen/rank  reservoir entrants
+//                    block per big cell; in its first blocks (or a kernel of
+//                    their own on large inflows), the entrants' ranks
 //   count_bases/scan windowed stable counting-sort counts, group bases, offsets
+//                    (one single-block kernel on small grids)
 //   scatter          free flight again, stable scatter into the next canonical
 //                    array, particle moment sums per destination; the
 //                    entrants after the cell-sourced particles of their cell
